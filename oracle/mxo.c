@@ -1,0 +1,929 @@
+/*
+ * mxo.c -- plain, slow, scalar CPU oracle for the per-ray X-ray Monte Carlo
+ * tracer.  TEST INFRASTRUCTURE ONLY: it exists so that tests, the smoke check
+ * and the CPU-baseline leg of the benchmark can judge the HIP library.  The
+ * product path never links, loads or calls it, and it shares no code, header,
+ * table or constant generator with the HIP library.
+ *
+ * What it computes (the paper's method, sections 2-3): independent photon
+ * packets ("rays") are emitted by a source component and carried, in order,
+ * through a sequential list of components (section 2: an instrument is a
+ * sequential list of components; rays are generated at the source and
+ * propagated through the list).  Each ray carries position, direction, energy
+ * and a Monte Carlo weight (section 2.2.2, the particle struct).  Monitors
+ * accumulate histograms of the weights of the rays that reach them (section
+ * 2.2.2, monitor arrays).  Every random draw comes from a counter-based
+ * generator keyed by (seed, ray id), so a ray's fate is a pure function of
+ * its id (section 2.2.2 asks for a per-thread generator; a counter-based one
+ * makes that independent of the thread layout).
+ *
+ * The paper prints no component equations.  Each component below is the
+ * textbook definition of the physics it names, in the readings listed in the
+ * design notes; the voxel phantom (section 3.3, the 3-D segmented sample)
+ * uses Siddon's exact radiological path in its original merge form
+ * (R. L. Siddon, Med. Phys. 12 (1985) 252): all plane crossings are listed,
+ * sorted, and each consecutive pair is one voxel segment whose voxel is found
+ * from its midpoint.
+ *
+ * Floating point: binary64, round to nearest, compiled with
+ * -ffp-contract=off so every expression rounds exactly as written.
+ *
+ * Parity pins: see the header of oracle/__init__.py.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- types -- */
+
+enum {
+    MXO_SRC_RECT_CONE = 0,
+    MXO_SRC_CONE_BEAM = 1,
+    MXO_SRC_GAUSSIAN = 2,
+    MXO_SLIT = 3,
+    MXO_BOX = 4,
+    MXO_PHANTOM = 5,
+    MXO_MIRROR_ELLIPTIC = 6,
+    MXO_DCM = 7,
+    MXO_POWDER = 8,
+    MXO_DETECTOR = 9
+};
+
+enum { MXO_ALIVE = 0, MXO_EXITED = 1, MXO_ABSORBED = 2 };
+
+#define MXO_SLIT_CIRCULAR 1u
+#define MXO_DET_WAVELENGTH 1u
+
+/* One component as the oracle sees it.  The parameter slots are the oracle's
+ * own; oracle/__init__.py fills them from the neutral instrument dict. */
+typedef struct {
+    int32_t type;
+    uint32_t flags;
+    double pos[3];
+    double rot[9]; /* row major: local = rot * (lab - pos) */
+    double par[24];
+    const void *data0;
+    const void *data1;
+    int64_t n0, n1;
+    int64_t dims[4];
+} mxo_comp;
+
+typedef struct {
+    double r[3], d[3], E, w;
+    int32_t status, dead_at;
+    int64_t bin;
+} mxo_ray;
+
+/* per-detector tally (caller-owned host arrays) */
+typedef struct {
+    uint64_t *count;
+    double *sum_w;
+    double *sum_w2;
+    int64_t n_bins;
+} mxo_tally;
+
+/* ------------------------------------------------------- Philox4x32-10 -- */
+/* Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3"
+ * (SC'11): a 4x32-bit counter and a 2x32-bit key; ten rounds of two 32x32
+ * multiplies (multipliers 0xD2511F53 and 0xCD9E8D57) whose high halves are
+ * xored with the other counter words and the round key; the key is advanced
+ * by the Weyl constants 0x9E3779B9 and 0xBB67AE85 between rounds. */
+void mxo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod_a = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t prod_b = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t a_hi = (uint32_t)(prod_a >> 32), a_lo = (uint32_t)prod_a;
+        uint32_t b_hi = (uint32_t)(prod_b >> 32), b_lo = (uint32_t)prod_b;
+        uint32_t y0 = b_hi ^ x1 ^ k0;
+        uint32_t y1 = b_lo;
+        uint32_t y2 = a_hi ^ x3 ^ k1;
+        uint32_t y3 = a_lo;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* The stream of one ray: counter = (block j, ray id low, ray id high,
+ * purpose << 24 | job), key = (seed low, seed high).  Block j yields
+ * uniforms 2j (from words 1:0) and 2j+1 (from words 3:2). */
+typedef struct {
+    uint32_t key[2];
+    uint32_t ctr_hi[3];
+    int64_t cached_block;
+    uint32_t words[4];
+} mxo_stream;
+
+static void stream_init(mxo_stream *s, uint64_t seed, uint64_t ray, uint32_t purpose, uint32_t job)
+{
+    s->key[0] = (uint32_t)seed;
+    s->key[1] = (uint32_t)(seed >> 32);
+    s->ctr_hi[0] = (uint32_t)ray;
+    s->ctr_hi[1] = (uint32_t)(ray >> 32);
+    s->ctr_hi[2] = (purpose << 24) | (job & 0xFFFFFFu);
+    s->cached_block = -1;
+}
+
+/* 52 random bits mapped to the open interval: ((w >> 12) + 1/2) * 2^-52,
+ * exact in binary64 and strictly inside (0, 1). */
+static double u01_from_word(uint64_t w)
+{
+    return ((double)(w >> 12) + 0.5) * 0x1.0p-52;
+}
+
+static double stream_uniform(mxo_stream *s, int index)
+{
+    int64_t block = index / 2;
+    if (block != s->cached_block) {
+        uint32_t ctr[4] = {(uint32_t)block, s->ctr_hi[0], s->ctr_hi[1], s->ctr_hi[2]};
+        mxo_philox4x32_10(ctr, s->key, s->words);
+        s->cached_block = block;
+    }
+    uint64_t w;
+    if ((index & 1) == 0)
+        w = ((uint64_t)s->words[1] << 32) | s->words[0];
+    else
+        w = ((uint64_t)s->words[3] << 32) | s->words[2];
+    return u01_from_word(w);
+}
+
+/* exported for the known-answer and uniformity tests */
+double mxo_uniform(uint64_t seed, uint64_t ray, uint32_t purpose, uint32_t job, int index)
+{
+    mxo_stream s;
+    stream_init(&s, seed, ray, purpose, job);
+    return stream_uniform(&s, index);
+}
+
+/* ------------------------------------------------------------ frames ---- */
+
+static void to_local(const mxo_comp *c, const double r[3], const double d[3], double q[3], double dl[3])
+{
+    double v[3] = {r[0] - c->pos[0], r[1] - c->pos[1], r[2] - c->pos[2]};
+    for (int i = 0; i < 3; ++i) {
+        const double *R = c->rot + 3 * i;
+        q[i] = R[0] * v[0] + R[1] * v[1] + R[2] * v[2];
+        dl[i] = R[0] * d[0] + R[1] * d[1] + R[2] * d[2];
+    }
+}
+
+static void to_lab(const mxo_comp *c, const double q[3], const double dl[3], double r[3], double d[3])
+{
+    const double *R = c->rot;
+    for (int i = 0; i < 3; ++i) {
+        r[i] = R[i] * q[0] + R[3 + i] * q[1] + R[6 + i] * q[2] + c->pos[i];
+        d[i] = R[i] * dl[0] + R[3 + i] * dl[1] + R[6 + i] * dl[2];
+    }
+}
+
+/* Propagate to the local plane z = 0.  A ray that moves away from the plane
+ * or would have to go back in time cannot reach it. */
+static int to_plane_z0(double q[3], const double dl[3])
+{
+    if (!(dl[2] > 0.0))
+        return 0;
+    double t = -q[2] / dl[2];
+    if (!(t >= 0.0))
+        return 0;
+    q[0] = q[0] + t * dl[0];
+    q[1] = q[1] + t * dl[1];
+    q[2] = 0.0;
+    return 1;
+}
+
+static double cross_dot_norm(const double a[3])
+{
+    return sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+}
+
+/* ----------------------------------------------------------- sources ---- */
+
+static const double HC_KEV_ANGSTROM = 12.398419843320026; /* CODATA 2018 */
+
+/* Square emitter with a cone uniform in solid angle about +z.  Uniform in
+ * solid angle inside half-angle alpha: 1 - cos(theta) = U (1 - cos(alpha)),
+ * i.e. sin(theta/2) = sqrt(U) sin(alpha/2). */
+static void src_rect_cone(const mxo_comp *c, mxo_stream *s, mxo_ray *ray)
+{
+    double wx = c->par[0], wy = c->par[1], alpha = c->par[2], emin = c->par[3], emax = c->par[4];
+    double q[3], dl[3];
+    q[0] = (stream_uniform(s, 0) - 0.5) * wx;
+    q[1] = (stream_uniform(s, 1) - 0.5) * wy;
+    q[2] = 0.0;
+    double theta = 2.0 * asin(sqrt(stream_uniform(s, 2)) * sin(0.5 * alpha));
+    double phi = (2.0 * M_PI) * stream_uniform(s, 3);
+    dl[0] = sin(theta) * cos(phi);
+    dl[1] = sin(theta) * sin(phi);
+    dl[2] = cos(theta);
+    ray->E = emin + (emax - emin) * stream_uniform(s, 4);
+    ray->w = 1.0;
+    to_lab(c, q, dl, ray->r, ray->d);
+}
+
+/* Number of strata per side actually used for n_total rays: the largest
+ * g <= G with g*g <= n_total, so that every stratum holds at least one ray. */
+uint64_t mxo_strata_side(uint64_t G, uint64_t n_total)
+{
+    uint64_t g = G < 1 ? 1 : G;
+    while (g > 1 && g * g > n_total)
+        g -= 1;
+    return g;
+}
+
+/* Gaussian line profile normalised over the real line. */
+static double gauss_pdf(double E, double mean, double sigma)
+{
+    double z = (E - mean) / sigma;
+    return exp(-0.5 * z * z) / (sigma * sqrt(2.0 * M_PI));
+}
+
+/* Tube spectrum as a photon-number density on [emin, emax]: a Kramers
+ * continuum proportional to (E0 - E)/E carrying fraction fc, plus two
+ * Gaussian lines carrying f1 and f2. */
+double mxo_spectrum(const double *par, double E)
+{
+    double emin = par[1], emax = par[2], E0 = par[3];
+    double fc = par[4], E1 = par[5], f1 = par[6], E2 = par[7], f2 = par[8], sig = par[9];
+    double K = E0 * log(emax / emin) - (emax - emin);
+    return fc * ((E0 - E) / E) / K + f1 * gauss_pdf(E, E1, sig) + f2 * gauss_pdf(E, E2, sig);
+}
+
+/* Cone-beam point source: direction uniform in solid angle inside
+ * half-angle alpha, stratified over G x G equal-area cells of the unit
+ * square mapped to the disk by the concentric map (Shirley and Chiu 1997),
+ * energy uniform on [emin, emax] with the spectrum carried in the weight:
+ * w0 = (emax - emin) S(E) * (n_total / G^2) / n_cell. */
+static void src_cone_beam(const mxo_comp *c, mxo_stream *s, mxo_ray *ray, uint64_t ray_id, uint64_t n_total)
+{
+    double alpha = c->par[0], emin = c->par[1], emax = c->par[2];
+    uint64_t G = mxo_strata_side((uint64_t)c->dims[0], n_total);
+    uint64_t G2 = G * G;
+    uint64_t cell = (ray_id * G2) / n_total;
+    uint64_t first = (cell * n_total + G2 - 1) / G2;
+    uint64_t next = ((cell + 1) * n_total + G2 - 1) / G2;
+    uint64_t n_cell = next - first;
+    double cell_factor = ((double)n_total / (double)G2) / (double)n_cell;
+    double u = ((double)(cell % G) + stream_uniform(s, 0)) / (double)G;
+    double v = ((double)(cell / G) + stream_uniform(s, 1)) / (double)G;
+
+    /* concentric square -> disk map */
+    double a = 2.0 * u - 1.0, b = 2.0 * v - 1.0;
+    double rad, ang;
+    if (a == 0.0 && b == 0.0) {
+        rad = 0.0;
+        ang = 0.0;
+    } else if (fabs(a) > fabs(b)) {
+        rad = a;
+        ang = (M_PI / 4.0) * (b / a);
+    } else {
+        rad = b;
+        ang = (M_PI / 2.0) - (M_PI / 4.0) * (a / b);
+    }
+    double px = rad * cos(ang), py = rad * sin(ang);
+    double rho = fabs(rad);
+
+    double theta = 2.0 * asin(rho * sin(0.5 * alpha));
+    double psi = atan2(py, px);
+    double q[3] = {0.0, 0.0, 0.0}, dl[3];
+    dl[0] = sin(theta) * cos(psi);
+    dl[1] = sin(theta) * sin(psi);
+    dl[2] = cos(theta);
+    ray->E = emin + (emax - emin) * stream_uniform(s, 2);
+    ray->w = ((emax - emin) * mxo_spectrum(c->par, ray->E)) * cell_factor;
+    to_lab(c, q, dl, ray->r, ray->d);
+}
+
+/* Gaussian (undulator-like) source: position and angle normal in both
+ * planes (Box-Muller on consecutive uniform pairs), energy flat within a
+ * relative half-width. */
+static void src_gaussian(const mxo_comp *c, mxo_stream *s, mxo_ray *ray)
+{
+    double sx = c->par[0], sy = c->par[1], sxp = c->par[2], syp = c->par[3];
+    double E0 = c->par[4], hw = c->par[5];
+    double r1 = sqrt(-2.0 * log(stream_uniform(s, 0)));
+    double a1 = (2.0 * M_PI) * stream_uniform(s, 1);
+    double r2 = sqrt(-2.0 * log(stream_uniform(s, 2)));
+    double a2 = (2.0 * M_PI) * stream_uniform(s, 3);
+    double q[3], dl[3];
+    q[0] = sx * (r1 * cos(a1));
+    q[1] = sy * (r1 * sin(a1));
+    q[2] = 0.0;
+    double tx = tan(sxp * (r2 * cos(a2)));
+    double ty = tan(syp * (r2 * sin(a2)));
+    double nrm = sqrt(tx * tx + ty * ty + 1.0);
+    dl[0] = tx / nrm;
+    dl[1] = ty / nrm;
+    dl[2] = 1.0 / nrm;
+    ray->E = E0 * ((1.0 - hw) + 2.0 * hw * stream_uniform(s, 4));
+    ray->w = 1.0;
+    to_lab(c, q, dl, ray->r, ray->d);
+}
+
+/* -------------------------------------------------- absorbers and optics -- */
+
+/* Slab method chord through the box |x| < hx, |y| < hy, |z| < hz for the
+ * ray q + a dl, a >= 0. */
+static double box_chord(const double h[3], const double q[3], const double dl[3])
+{
+    double a_in = 0.0, a_out = INFINITY;
+    for (int i = 0; i < 3; ++i) {
+        if (dl[i] == 0.0) {
+            if (!(q[i] > -h[i] && q[i] < h[i]))
+                return 0.0;
+        } else {
+            double inv = 1.0 / dl[i];
+            double a0 = (-h[i] - q[i]) * inv, a1 = (h[i] - q[i]) * inv;
+            double lo = a0 < a1 ? a0 : a1, hi = a0 < a1 ? a1 : a0;
+            if (lo > a_in) a_in = lo;
+            if (hi < a_out) a_out = hi;
+        }
+    }
+    return a_out > a_in ? a_out - a_in : 0.0;
+}
+
+/* Homogeneous box, Beer-Lambert: w *= exp(-mu(E) L), mu = a E^-3 + b in
+ * 1/cm, L in mm. */
+static void comp_box(const mxo_comp *c, mxo_ray *ray)
+{
+    double q[3], dl[3];
+    to_local(c, ray->r, ray->d, q, dl);
+    double L = box_chord(c->par, q, dl);
+    double E = ray->E;
+    double mu = c->par[3] / (E * E * E) + c->par[4];
+    ray->w = ray->w * exp(-(mu * L) / 10.0);
+}
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Siddon's exact radiological path, merge form.  Volume of nx*ny*nz voxels
+ * of edge v (mm), centred on the local origin, voxel (i,j,k) at byte
+ * i + nx*(j + ny*k) holding a material id; mu table [material][energy bin]
+ * in 1/cm on a uniform energy grid.  Returns tau = sum mu * length / 10.
+ * When seg is non-null the segments (voxel index, length) are written out,
+ * in traversal order, up to max_seg of them. */
+typedef struct {
+    const uint8_t *vol;
+    const double *mu;
+    int64_t n[3];
+    double v;
+    double corner[3];
+    int64_t n_mat, n_ebin;
+    double t_emin, t_emax;
+} mxo_volume;
+
+static void volume_from(const mxo_comp *c, mxo_volume *V)
+{
+    V->vol = (const uint8_t *)c->data0;
+    V->mu = (const double *)c->data1;
+    for (int i = 0; i < 3; ++i)
+        V->n[i] = c->dims[i];
+    V->v = c->par[0];
+    for (int i = 0; i < 3; ++i)
+        V->corner[i] = -0.5 * ((double)V->n[i] * V->v);
+    V->t_emin = c->par[1];
+    V->t_emax = c->par[2];
+    V->n_mat = c->dims[3];
+    V->n_ebin = c->n1 / (c->dims[3] > 0 ? c->dims[3] : 1);
+}
+
+static int64_t floor_index(double x, int64_t n)
+{
+    double f = floor(x);
+    if (f < 0.0)
+        return 0;
+    if (f > (double)(n - 1))
+        return n - 1;
+    return (int64_t)f;
+}
+
+double mxo_siddon(const mxo_volume *V, const double q[3], const double dl[3], double E,
+                  int64_t *seg_voxel, double *seg_len, int64_t max_seg, int64_t *n_seg)
+{
+    if (n_seg)
+        *n_seg = 0;
+    double inv[3];
+    double a_in = 0.0, a_out = INFINITY;
+    for (int i = 0; i < 3; ++i) {
+        double lo_plane = V->corner[i];
+        double hi_plane = V->corner[i] + (double)V->n[i] * V->v;
+        if (dl[i] == 0.0) {
+            inv[i] = 0.0;
+            if (!(q[i] > lo_plane && q[i] < hi_plane))
+                return 0.0;
+        } else {
+            inv[i] = 1.0 / dl[i];
+            double a0 = (lo_plane - q[i]) * inv[i], a1 = (hi_plane - q[i]) * inv[i];
+            double lo = a0 < a1 ? a0 : a1, hi = a0 < a1 ? a1 : a0;
+            if (lo > a_in) a_in = lo;
+            if (hi < a_out) a_out = hi;
+        }
+    }
+    if (!(a_out > a_in))
+        return 0.0;
+
+    /* every plane crossing strictly inside (a_in, a_out), plus the ends */
+    int64_t cap = V->n[0] + V->n[1] + V->n[2] + 5;
+    double *alpha = (double *)malloc((size_t)cap * sizeof(double));
+    int64_t m = 0;
+    alpha[m++] = a_in;
+    for (int i = 0; i < 3; ++i) {
+        if (dl[i] == 0.0)
+            continue;
+        for (int64_t p = 0; p <= V->n[i]; ++p) {
+            double plane = V->corner[i] + (double)p * V->v;
+            double a = (plane - q[i]) * inv[i];
+            if (a > a_in && a < a_out)
+                alpha[m++] = a;
+        }
+    }
+    alpha[m++] = a_out;
+    qsort(alpha, (size_t)m, sizeof(double), cmp_double);
+
+    double ebin_scale = (double)V->n_ebin / (V->t_emax - V->t_emin);
+    int64_t e = floor_index((E - V->t_emin) * ebin_scale, V->n_ebin);
+    double tau = 0.0;
+    int64_t ns = 0;
+    for (int64_t k = 0; k + 1 < m; ++k) {
+        double len = alpha[k + 1] - alpha[k];
+        if (!(len > 0.0))
+            continue;
+        double mid = 0.5 * (alpha[k] + alpha[k + 1]);
+        int64_t idx[3];
+        for (int i = 0; i < 3; ++i)
+            idx[i] = floor_index((q[i] + mid * dl[i] - V->corner[i]) / V->v, V->n[i]);
+        int64_t voxel = idx[0] + V->n[0] * (idx[1] + V->n[1] * idx[2]);
+        int64_t mat = V->vol[voxel];
+        if (mat >= V->n_mat)
+            mat = V->n_mat - 1;
+        tau = tau + V->mu[mat * V->n_ebin + e] * len / 10.0;
+        if (seg_voxel && ns < max_seg) {
+            seg_voxel[ns] = voxel;
+            seg_len[ns] = len;
+        }
+        ns++;
+    }
+    free(alpha);
+    if (n_seg)
+        *n_seg = ns;
+    return tau;
+}
+
+/* exported debug entry: segments of one ray through a volume given in
+ * local coordinates */
+double mxo_siddon_debug(const mxo_comp *c, const double q[3], const double dl[3], double E,
+                        int64_t *seg_voxel, double *seg_len, int64_t max_seg, int64_t *n_seg)
+{
+    mxo_volume V;
+    volume_from(c, &V);
+    return mxo_siddon(&V, q, dl, E, seg_voxel, seg_len, max_seg, n_seg);
+}
+
+static void comp_phantom(const mxo_comp *c, mxo_ray *ray)
+{
+    double q[3], dl[3];
+    to_local(c, ray->r, ray->d, q, dl);
+    mxo_volume V;
+    volume_from(c, &V);
+    double tau = mxo_siddon(&V, q, dl, ray->E, NULL, NULL, 0, NULL);
+    ray->w = ray->w * exp(-tau);
+}
+
+/* Rectangular (or circular) aperture in the local plane z = 0; edges pass. */
+static int comp_slit(const mxo_comp *c, mxo_ray *ray)
+{
+    double q[3], dl[3];
+    to_local(c, ray->r, ray->d, q, dl);
+    if (!to_plane_z0(q, dl))
+        return 0;
+    if (c->flags & MXO_SLIT_CIRCULAR) {
+        double rr = c->par[2];
+        if (!(q[0] * q[0] + q[1] * q[1] <= rr * rr))
+            return 0;
+    } else {
+        if (!(fabs(q[0]) <= 0.5 * c->par[0] && fabs(q[1]) <= 0.5 * c->par[1]))
+            return 0;
+    }
+    to_lab(c, q, dl, ray->r, ray->d);
+    return 1;
+}
+
+/* Elliptic-cylinder mirror (meridional focusing).  Local frame: origin at
+ * the mirror pole P, z along the incoming central ray, y towards the
+ * reflected side.  Foci F1 = (0, 0, -p) and F2 = q (0, sin 2t0, cos 2t0);
+ * semi-axes a = (p + q)/2 and b^2 = p q sin^2 t0; half focal distance
+ * c = |F2 - F1|/2.  Reflectivity from a table on n nodes over [0, tmax]
+ * by linear interpolation, zero beyond. */
+static int comp_mirror(const mxo_comp *c, mxo_ray *ray)
+{
+    double p = c->par[0], qd = c->par[1], t0 = c->par[2];
+    double len = c->par[3], wid = c->par[4], tmax = c->par[5];
+    const double *table = (const double *)c->data0;
+    int64_t nt = c->n0;
+
+    double a = 0.5 * (p + qd);
+    double b2 = p * qd * (sin(t0) * sin(t0));
+    double F2y = qd * sin(2.0 * t0), F2z = qd * cos(2.0 * t0);
+    double fy = F2y, fz = F2z + p;
+    double two_c = sqrt(fy * fy + fz * fz);
+    double uy = fy / two_c, uz = fz / two_c; /* major axis (y,z) */
+    double vy = uz, vz = -uy;                /* minor axis (y,z) */
+    double Cy = 0.5 * F2y, Cz = 0.5 * (F2z - p);
+
+    double q[3], dl[3];
+    to_local(c, ray->r, ray->d, q, dl);
+    double gy = q[1] - Cy, gz = q[2] - Cz;
+    double s0 = gy * uy + gz * uz, n0 = gy * vy + gz * vz;
+    double ds = dl[1] * uy + dl[2] * uz, dn = dl[1] * vy + dl[2] * vz;
+    double ia2 = 1.0 / (a * a), ib2 = 1.0 / b2;
+    double A = ds * ds * ia2 + dn * dn * ib2;
+    double B = 2.0 * (s0 * ds * ia2 + n0 * dn * ib2);
+    double C = s0 * s0 * ia2 + n0 * n0 * ib2 - 1.0;
+    double disc = B * B - 4.0 * A * C;
+    if (!(disc >= 0.0))
+        return 0;
+    double t = (-B + sqrt(disc)) / (2.0 * A);
+    if (!(t > 0.0))
+        return 0;
+    double X[3] = {q[0] + t * dl[0], q[1] + t * dl[1], q[2] + t * dl[2]};
+    double along = X[1] * sin(t0) + X[2] * cos(t0);
+    if (!(fabs(X[0]) <= 0.5 * wid && fabs(along) <= 0.5 * len))
+        return 0;
+    double hy = X[1] - Cy, hz = X[2] - Cz;
+    double hs = (hy * uy + hz * uz) * ia2, hn = (hy * vy + hz * vz) * ib2;
+    double N[3] = {0.0, hs * uy + hn * vy, hs * uz + hn * vz};
+    double nn = cross_dot_norm(N);
+    N[1] = N[1] / nn;
+    N[2] = N[2] / nn;
+    double dd = dl[0] * N[0] + dl[1] * N[1] + dl[2] * N[2];
+    if (dd > 0.0) {
+        N[1] = -N[1];
+        N[2] = -N[2];
+        dd = -dd;
+    }
+    double theta = asin(-dd);
+    double R = 0.0;
+    double h = tmax / (double)(nt - 1);
+    double uu = theta / h;
+    if (uu <= (double)(nt - 1)) {
+        int64_t k = (int64_t)floor(uu);
+        if (k > nt - 2)
+            k = nt - 2;
+        double f = uu - (double)k;
+        R = table[k] * (1.0 - f) + table[k + 1] * f;
+    }
+    double out[3];
+    for (int i = 0; i < 3; ++i)
+        out[i] = dl[i] - 2.0 * dd * N[i];
+    ray->w = ray->w * R;
+    to_lab(c, X, out, ray->r, ray->d);
+    return 1;
+}
+
+/* Darwin reflectivity of a thick perfect crystal without absorption, as a
+ * function of x = offset / (half plateau width): 1 on the plateau, and
+ * (|x| - sqrt(x^2 - 1))^2 = 1 / (|x| + sqrt(x^2 - 1))^2 outside. */
+static double darwin(double x)
+{
+    double ax = fabs(x);
+    if (ax <= 1.0)
+        return 1.0;
+    double den = ax + sqrt(ax * ax - 1.0);
+    return 1.0 / (den * den);
+}
+
+/* Bragg reflection off the crystal plane through point P with unit normal
+ * N (facing the incoming ray). */
+static int bragg_bounce(double q[3], double dl[3], const double P[3], const double N[3],
+                        double dspace, double width, double E, double *R)
+{
+    double dn = dl[0] * N[0] + dl[1] * N[1] + dl[2] * N[2];
+    if (!(dn < 0.0))
+        return 0;
+    double rel[3] = {q[0] - P[0], q[1] - P[1], q[2] - P[2]};
+    double t = -(rel[0] * N[0] + rel[1] * N[1] + rel[2] * N[2]) / dn;
+    if (!(t >= 0.0))
+        return 0;
+    for (int i = 0; i < 3; ++i)
+        q[i] = q[i] + t * dl[i];
+    double theta_in = asin(-dn);
+    double theta_b = asin(HC_KEV_ANGSTROM / (2.0 * dspace * E));
+    double x = (theta_in - theta_b) / (0.5 * width);
+    *R = darwin(x);
+    for (int i = 0; i < 3; ++i)
+        dl[i] = dl[i] - 2.0 * dn * N[i];
+    return 1;
+}
+
+/* Two-bounce monochromator of parallel crystals.  Local frame: origin at
+ * the first crystal's pole, z along the incoming beam axis, y up.  Crystal
+ * 1 normal n1 = (0, cos tc, -sin tc) at the setting angle tc; crystal 2 is
+ * the parallel plane through g n1 facing -n1. */
+static int comp_dcm(const mxo_comp *c, mxo_ray *ray)
+{
+    double dsp = c->par[0], tc = c->par[1], wd = c->par[2], g = c->par[3];
+    double n1[3] = {0.0, cos(tc), -sin(tc)};
+    double n2[3] = {-n1[0], -n1[1], -n1[2]};
+    double P1[3] = {0.0, 0.0, 0.0};
+    double P2[3] = {g * n1[0], g * n1[1], g * n1[2]};
+    double q[3], dl[3], R1, R2;
+    to_local(c, ray->r, ray->d, q, dl);
+    if (!bragg_bounce(q, dl, P1, n1, dsp, wd, ray->E, &R1))
+        return 0;
+    if (!bragg_bounce(q, dl, P2, n2, dsp, wd, ray->E, &R2))
+        return 0;
+    ray->w = ray->w * R1;
+    ray->w = ray->w * R2;
+    to_lab(c, q, dl, ray->r, ray->d);
+    return 1;
+}
+
+/* Thin powder plate in the local plane z = 0: one of the tabulated
+ * d-spacings is picked uniformly, the ray is turned by the Bragg angle 2
+ * theta = 2 asin(lambda / 2d) onto the Debye-Scherrer cone at a uniform
+ * azimuth.  Draws: index then azimuth. */
+static int comp_powder(const mxo_comp *c, mxo_stream *s, int draw0, mxo_ray *ray)
+{
+    const double *dsp = (const double *)c->data0;
+    int64_t nd = c->n0;
+    double q[3], dl[3];
+    to_local(c, ray->r, ray->d, q, dl);
+    if (!to_plane_z0(q, dl))
+        return 0;
+    if (!(fabs(q[0]) <= 0.5 * c->par[0] && fabs(q[1]) <= 0.5 * c->par[1]))
+        return 0;
+    int64_t j = (int64_t)floor((double)nd * stream_uniform(s, draw0));
+    if (j > nd - 1)
+        j = nd - 1;
+    double lambda = HC_KEV_ANGSTROM / ray->E;
+    double sarg = lambda / (2.0 * dsp[j]);
+    if (!(sarg <= 1.0))
+        return 0;
+    double tth = 2.0 * asin(sarg);
+    double eta = (2.0 * M_PI) * stream_uniform(s, draw0 + 1);
+    /* e1 = normalize(dl x y_hat), e2 = dl x e1 */
+    double e1[3] = {-dl[2], 0.0, dl[0]};
+    double n1 = cross_dot_norm(e1);
+    e1[0] = e1[0] / n1;
+    e1[2] = e1[2] / n1;
+    double e2[3] = {dl[1] * e1[2] - dl[2] * e1[1], dl[2] * e1[0] - dl[0] * e1[2],
+                    dl[0] * e1[1] - dl[1] * e1[0]};
+    double ct = cos(tth), st = sin(tth), ce = cos(eta), se = sin(eta);
+    double out[3];
+    for (int i = 0; i < 3; ++i)
+        out[i] = ct * dl[i] + st * (ce * e1[i] + se * e2[i]);
+    to_lab(c, q, out, ray->r, ray->d);
+    return 1;
+}
+
+/* half-open bin of x on [lo, hi) with n bins, or -1 */
+static int64_t bin_of(double x, double lo, double hi, int64_t n)
+{
+    double f = floor((x - lo) * ((double)n / (hi - lo)));
+    if (!(f >= 0.0 && f < (double)n))
+        return -1;
+    return (int64_t)f;
+}
+
+/* Ideal energy/position-sensitive monitor in the local plane z = 0: bins
+ * (x, y, E) -- or wavelength when flagged -- with the tally index
+ * (iy * nx + ix) * ne + ie.  Monitors do not absorb. */
+static int comp_detector(const mxo_comp *c, mxo_ray *ray, int64_t *bin)
+{
+    double q[3], dl[3];
+    to_local(c, ray->r, ray->d, q, dl);
+    if (!to_plane_z0(q, dl))
+        return 0;
+    int64_t nx = c->dims[0], ny = c->dims[1], ne = c->dims[2];
+    double ev = (c->flags & MXO_DET_WAVELENGTH) ? HC_KEV_ANGSTROM / ray->E : ray->E;
+    int64_t ix = bin_of(q[0], c->par[0], c->par[1], nx);
+    int64_t iy = bin_of(q[1], c->par[2], c->par[3], ny);
+    int64_t ie = bin_of(ev, c->par[4], c->par[5], ne);
+    if (ix >= 0 && iy >= 0 && ie >= 0)
+        *bin = (iy * nx + ix) * ne + ie;
+    else
+        *bin = -1;
+    to_lab(c, q, dl, ray->r, ray->d);
+    return 1;
+}
+
+static int draws_of(int type)
+{
+    switch (type) {
+    case MXO_SRC_RECT_CONE: return 5;
+    case MXO_SRC_CONE_BEAM: return 3;
+    case MXO_SRC_GAUSSIAN: return 5;
+    case MXO_POWDER: return 2;
+    default: return 0;
+    }
+}
+
+/* ------------------------------------------------------------ ledger ---- */
+/* Neumaier-compensated sums of weight: per component k, slots
+ * [0] weight entering (for the source: weight emitted), [1] weight of rays
+ * absorbed at k, [2] weight removed by attenuation at k, [3] weight tallied
+ * at k; one last slot [4K] holds the weight of rays leaving the instrument. */
+typedef struct {
+    double s, c;
+} ksum;
+
+static void kadd(ksum *k, double x)
+{
+    double t = k->s + x;
+    if (fabs(k->s) >= fabs(x))
+        k->c += (k->s - t) + x;
+    else
+        k->c += (x - t) + k->s;
+    k->s = t;
+}
+
+/* ---------------------------------------------------- one ray, in order -- */
+
+typedef struct {
+    const mxo_comp *comps;
+    int ncomp;
+    uint64_t seed, n_total;
+    uint32_t purpose, job;
+} mxo_instr;
+
+static void trace_one(const mxo_instr *I, uint64_t ray_id, mxo_ray *ray, mxo_tally *tallies, ksum *ledger)
+{
+    mxo_stream s;
+    stream_init(&s, I->seed, ray_id, I->purpose, I->job);
+    ray->status = MXO_ALIVE;
+    ray->dead_at = -1;
+    ray->bin = -1;
+    int draw = 0, det = 0;
+    for (int k = 0; k < I->ncomp; ++k) {
+        const mxo_comp *c = &I->comps[k];
+        double w_in = ray->w;
+        mxo_ray before = *ray;
+        int ok = 1;
+        int64_t bin = -1;
+        switch (c->type) {
+        case MXO_SRC_RECT_CONE: src_rect_cone(c, &s, ray); w_in = ray->w; break;
+        case MXO_SRC_CONE_BEAM: src_cone_beam(c, &s, ray, ray_id, I->n_total); w_in = ray->w; break;
+        case MXO_SRC_GAUSSIAN: src_gaussian(c, &s, ray); w_in = ray->w; break;
+        case MXO_SLIT: ok = comp_slit(c, ray); break;
+        case MXO_BOX: comp_box(c, ray); break;
+        case MXO_PHANTOM: comp_phantom(c, ray); break;
+        case MXO_MIRROR_ELLIPTIC: ok = comp_mirror(c, ray); break;
+        case MXO_DCM: ok = comp_dcm(c, ray); break;
+        case MXO_POWDER: ok = comp_powder(c, &s, draw, ray); break;
+        case MXO_DETECTOR: ok = comp_detector(c, ray, &bin); break;
+        default: ok = 0; break;
+        }
+        draw += draws_of(c->type);
+        if (ledger)
+            kadd(&ledger[4 * k + 0], w_in);
+        if (!ok) {
+            *ray = before;
+            ray->status = MXO_ABSORBED;
+            ray->dead_at = k;
+            if (ledger)
+                kadd(&ledger[4 * k + 1], w_in);
+            return;
+        }
+        if (ledger && c->type != MXO_SRC_RECT_CONE && c->type != MXO_SRC_CONE_BEAM &&
+            c->type != MXO_SRC_GAUSSIAN)
+            kadd(&ledger[4 * k + 2], w_in - ray->w);
+        if (c->type == MXO_DETECTOR) {
+            if (bin >= 0) {
+                ray->bin = bin;
+                if (tallies) {
+                    tallies[det].count[bin] += 1;
+                    tallies[det].sum_w[bin] += ray->w;
+                    tallies[det].sum_w2[bin] += ray->w * ray->w;
+                }
+                if (ledger)
+                    kadd(&ledger[4 * k + 3], ray->w);
+            }
+            det++;
+        }
+    }
+    ray->status = MXO_EXITED;
+    if (ledger)
+        kadd(&ledger[4 * I->ncomp], ray->w);
+}
+
+/* ----------------------------------------------------- exported runs ---- */
+
+typedef struct {
+    const mxo_instr *I;
+    uint64_t begin, end;
+    mxo_tally *tallies;
+    int n_det;
+    ksum *ledger;
+} worker_arg;
+
+static void *worker(void *p)
+{
+    worker_arg *a = (worker_arg *)p;
+    mxo_ray ray;
+    for (uint64_t r = a->begin; r < a->end; ++r) {
+        memset(&ray, 0, sizeof ray);
+        trace_one(a->I, r, &ray, a->tallies, a->ledger);
+    }
+    return NULL;
+}
+
+static int count_detectors(const mxo_comp *comps, int ncomp)
+{
+    int n = 0;
+    for (int k = 0; k < ncomp; ++k)
+        n += comps[k].type == MXO_DETECTOR;
+    return n;
+}
+
+/* Trace rays [first, first + n) of an n_total-ray run, adding their
+ * histograms into the caller's tallies (one per detector, in order) and,
+ * when ledger is non-null, their weight ledger (4 * ncomp + 1 doubles).
+ * The work is split over n_threads threads by contiguous ray ranges, each
+ * with private histograms that are summed at the end. */
+int mxo_run(const mxo_comp *comps, int ncomp, uint64_t seed, uint64_t first, uint64_t n,
+            uint64_t n_total, uint32_t purpose, uint32_t job, mxo_tally *tallies, double *ledger,
+            int n_threads)
+{
+    if (n_threads < 1)
+        n_threads = 1;
+    mxo_instr I = {comps, ncomp, seed, n_total, purpose, job};
+    int n_det = count_detectors(comps, ncomp);
+    int n_slots = 4 * ncomp + 1;
+    worker_arg *args = (worker_arg *)calloc((size_t)n_threads, sizeof(worker_arg));
+    pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+    for (int t = 0; t < n_threads; ++t) {
+        args[t].I = &I;
+        args[t].begin = first + (n * (uint64_t)t) / (uint64_t)n_threads;
+        args[t].end = first + (n * (uint64_t)(t + 1)) / (uint64_t)n_threads;
+        args[t].n_det = n_det;
+        args[t].tallies = (mxo_tally *)calloc((size_t)(n_det > 0 ? n_det : 1), sizeof(mxo_tally));
+        for (int d = 0; d < n_det; ++d) {
+            int64_t nb = tallies[d].n_bins;
+            args[t].tallies[d].n_bins = nb;
+            args[t].tallies[d].count = (uint64_t *)calloc((size_t)nb, sizeof(uint64_t));
+            args[t].tallies[d].sum_w = (double *)calloc((size_t)nb, sizeof(double));
+            args[t].tallies[d].sum_w2 = (double *)calloc((size_t)nb, sizeof(double));
+        }
+        args[t].ledger = (ksum *)calloc((size_t)n_slots, sizeof(ksum));
+        pthread_create(&th[t], NULL, worker, &args[t]);
+    }
+    ksum *total = (ksum *)calloc((size_t)n_slots, sizeof(ksum));
+    for (int t = 0; t < n_threads; ++t) {
+        pthread_join(th[t], NULL);
+        for (int d = 0; d < n_det; ++d) {
+            for (int64_t b = 0; b < tallies[d].n_bins; ++b) {
+                tallies[d].count[b] += args[t].tallies[d].count[b];
+                tallies[d].sum_w[b] += args[t].tallies[d].sum_w[b];
+                tallies[d].sum_w2[b] += args[t].tallies[d].sum_w2[b];
+            }
+            free(args[t].tallies[d].count);
+            free(args[t].tallies[d].sum_w);
+            free(args[t].tallies[d].sum_w2);
+        }
+        for (int i = 0; i < n_slots; ++i) {
+            kadd(&total[i], args[t].ledger[i].s);
+            kadd(&total[i], args[t].ledger[i].c);
+        }
+        free(args[t].tallies);
+        free(args[t].ledger);
+    }
+    if (ledger)
+        for (int i = 0; i < n_slots; ++i)
+            ledger[i] += total[i].s + total[i].c;
+    free(total);
+    free(args);
+    free(th);
+    return 0;
+}
+
+/* Trace the listed rays one by one and report their final states. */
+int mxo_trace_rays(const mxo_comp *comps, int ncomp, uint64_t seed, uint64_t n_total, uint32_t purpose,
+                   uint32_t job, const uint64_t *ids, int64_t n, double *r_out, double *d_out,
+                   double *E_out, double *w_out, int32_t *status_out, int32_t *dead_out, int64_t *bin_out)
+{
+    mxo_instr I = {comps, ncomp, seed, n_total, purpose, job};
+    for (int64_t i = 0; i < n; ++i) {
+        mxo_ray ray;
+        memset(&ray, 0, sizeof ray);
+        trace_one(&I, ids[i], &ray, NULL, NULL);
+        for (int k = 0; k < 3; ++k) {
+            r_out[3 * i + k] = ray.r[k];
+            d_out[3 * i + k] = ray.d[k];
+        }
+        E_out[i] = ray.E;
+        w_out[i] = ray.w;
+        status_out[i] = ray.status;
+        dead_out[i] = ray.dead_at;
+        bin_out[i] = ray.bin;
+    }
+    return 0;
+}

@@ -1,0 +1,251 @@
+"""Seeded synthetic inputs and instrument descriptions.
+
+This module is the one thing the HIP library's tests and the CPU oracle
+share: plain parameter values, geometry placement and seeded input arrays
+(voxel phantoms, attenuation tables, reflectivity tables, d-spacings).  It
+holds none of the tracing arithmetic.  Instruments are neutral dicts::
+
+    {"components": [{"type": ..., "pos": (x, y, z), "rot": 3x3, ...}, ...]}
+
+with ``rot`` the lab-to-local rotation (local = rot @ (lab - pos)), lengths
+in mm, energies in keV, angles in rad, attenuation in 1/cm.
+
+The paper's own workloads (section 3: a basic source + monitor instrument, a
+focusing beamline, an energy-dispersive CT scanner with a voxel phantom)
+need data that is not available here (tungsten spectrum, water, iron and
+lead attenuation, the test piece geometry); the generators below stand in
+for them with the shapes the paper gives (1 mm voxels, 128 energy bins,
+1e6-1e9 rays).
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Sequence
+
+import numpy as np
+
+HC_KEV_ANGSTROM = 12.398419843320026
+SI_LATTICE_ANGSTROM = 5.431020511
+
+
+def rot_y(phi: float) -> np.ndarray:
+    """Lab-to-local rotation for an object turned by phi about +y."""
+    c, s = math.cos(phi), math.sin(phi)
+    # the object's axes in the lab are R_y(phi) e_i; local = R_y(phi)^T lab
+    return np.array([[c, 0.0, -s], [0.0, 1.0, 0.0], [s, 0.0, c]], dtype=np.float64)
+
+
+def frame_along(axis: Sequence[float]) -> np.ndarray:
+    """Lab-to-local rotation whose local z is ``axis`` (in the y-z plane) and
+    local x is lab x."""
+    z = np.asarray(axis, dtype=np.float64)
+    z = z / np.linalg.norm(z)
+    x = np.array([1.0, 0.0, 0.0])
+    y = np.cross(z, x)
+    return np.stack([x, y, z])
+
+
+# ---------------------------------------------------------------- inputs --
+
+def make_mu_tables(seed: int = 1, n_mat: int = 8, n_ebin: int = 256, emin: float = 20.0,
+                   emax: float = 150.0) -> np.ndarray:
+    """Per-material attenuation tables mu[m, e] in 1/cm at the energy-bin
+    centres: a power law with one absorption edge,
+    mu_m(E) = A (E/60)^-p * (J if E >= E_edge) + B.
+
+    Material 0 is air (mu(60) = 2e-4), 1 the bag shell (mu(60) = 0.3), and
+    2.. objects with mu(60) log-uniform in [0.05, 5]; p ~ U(2.6, 3.2),
+    E_edge ~ U(20, 90), J ~ U(2, 8), B = f mu(60) with f ~ U(0.05, 0.2).
+    """
+    rng = np.random.default_rng(seed)
+    centres = emin + (np.arange(n_ebin) + 0.5) * ((emax - emin) / n_ebin)
+    tab = np.zeros((n_mat, n_ebin))
+    for m in range(n_mat):
+        p = rng.uniform(2.6, 3.2)
+        e_edge = rng.uniform(20.0, 90.0)
+        jump = rng.uniform(2.0, 8.0)
+        frac_b = rng.uniform(0.05, 0.2)
+        if m == 0:
+            mu60, jump = 2e-4, 1.0
+        elif m == 1:
+            mu60, jump = 0.3, 1.0
+        else:
+            mu60 = math.exp(rng.uniform(math.log(0.05), math.log(5.0)))
+        B = frac_b * mu60
+        j60 = jump if 60.0 >= e_edge else 1.0
+        A = (mu60 - B) / j60
+        jf = np.where(centres >= e_edge, jump, 1.0)
+        tab[m] = A * (centres / 60.0) ** (-p) * jf + B
+    return tab
+
+
+def _random_rotation(rng) -> np.ndarray:
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+def make_phantom(n: int, seed: int = 1, n_objects: int = 32, n_mat: int = 8) -> np.ndarray:
+    """Seeded luggage-like phantom: an n^3 uint8 material-id volume (array
+    shape (z, y, x)).  A bag shell (material 1, 3 voxels thick) spans voxels
+    [16, n - 16) on every axis; inside and outside is air (material 0).
+    Then n_objects objects are painted in order: each an ellipsoid (randomly
+    rotated, uniform quaternion) or an axis-aligned box with probability
+    1/2, centre uniform inside the bag, semi-axes U(8, 40) voxels scaled by
+    n/256, material uniform in {2, ..., n_mat - 1}; a voxel belongs to an
+    object when its centre does."""
+    rng = np.random.default_rng(seed)
+    vol = np.zeros((n, n, n), dtype=np.uint8)
+    lo, hi, wall = 16, n - 16, 3
+    if hi - lo > 2 * wall:
+        vol[lo:hi, lo:hi, lo:hi] = 1
+        vol[lo + wall:hi - wall, lo + wall:hi - wall, lo + wall:hi - wall] = 0
+    scale = n / 256.0
+    for _ in range(n_objects):
+        is_ellipsoid = rng.random() < 0.5
+        centre = rng.uniform(lo + wall, hi - wall, size=3)
+        semi = rng.uniform(8.0, 40.0, size=3) * scale
+        mat = int(rng.integers(2, n_mat))
+        rot = _random_rotation(rng) if is_ellipsoid else np.eye(3)
+        reach = float(semi.max()) if is_ellipsoid else None
+        if is_ellipsoid:
+            b0 = np.floor(centre - reach).astype(int)
+            b1 = np.ceil(centre + reach).astype(int) + 1
+        else:
+            b0 = np.floor(centre - semi).astype(int)
+            b1 = np.ceil(centre + semi).astype(int) + 1
+        b0 = np.clip(b0, 0, n)
+        b1 = np.clip(b1, 0, n)
+        if np.any(b1 <= b0):
+            continue
+        # voxel centres, order (x, y, z) -> array axes (z, y, x)
+        xs = np.arange(b0[0], b1[0]) + 0.5 - centre[0]
+        ys = np.arange(b0[1], b1[1]) + 0.5 - centre[1]
+        zs = np.arange(b0[2], b1[2]) + 0.5 - centre[2]
+        Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+        if is_ellipsoid:
+            # coordinates in the ellipsoid's own axes: rot^T (p - c)
+            u = rot[0, 0] * X + rot[1, 0] * Y + rot[2, 0] * Z
+            v = rot[0, 1] * X + rot[1, 1] * Y + rot[2, 1] * Z
+            w = rot[0, 2] * X + rot[1, 2] * Y + rot[2, 2] * Z
+            inside = (u / semi[0]) ** 2 + (v / semi[1]) ** 2 + (w / semi[2]) ** 2 <= 1.0
+        else:
+            inside = (np.abs(X) <= semi[0]) & (np.abs(Y) <= semi[1]) & (np.abs(Z) <= semi[2])
+        sub = vol[b0[2]:b1[2], b0[1]:b1[1], b0[0]:b1[0]]
+        sub[inside] = mat
+    return vol
+
+
+def make_d_spacings(seed: int = 1, n: int = 200, lo: float = 0.8, hi: float = 4.0) -> np.ndarray:
+    """n powder d-spacings uniform in [lo, hi] Angstrom."""
+    return np.random.default_rng(seed).uniform(lo, hi, size=n)
+
+
+def make_mirror_reflectivity(n: int = 512, theta_max: float = 6e-3, delta: float = 1.6e-5,
+                             beta: float = 1.5e-6) -> np.ndarray:
+    """Grazing-incidence Fresnel reflectivity of a mirror coating with
+    refractive index 1 - delta + i beta on n angles over [0, theta_max]:
+    R = |(t - t_t) / (t + t_t)|^2, t_t = sqrt(t^2 - 2 delta + 2 i beta)."""
+    th = np.linspace(0.0, theta_max, n)
+    tt = np.sqrt(th.astype(np.complex128) ** 2 - 2 * delta + 2j * beta)
+    r = np.abs((th - tt) / (th + tt)) ** 2
+    return r.astype(np.float64)
+
+
+# ----------------------------------------------------------- instruments --
+
+def _c(type_: str, pos=(0.0, 0.0, 0.0), rot=None, **kw) -> Dict:
+    d = {"type": type_, "pos": tuple(float(x) for x in pos),
+         "rot": np.eye(3) if rot is None else np.asarray(rot, dtype=np.float64)}
+    d.update(kw)
+    return d
+
+
+def basic_absorber() -> Dict:
+    """Plain tracer, first workload: 1x1 mm emitter, 20-80 keV flat, 5 mrad
+    half-angle cone; 1x1 mm slit at 1 m; 10 mm cube at 1.5 m with
+    mu(E) = 2e4 E^-3 + 0.2 1/cm; 128x128 monitor, 100x100 mm, at 2 m."""
+    return {"name": "basic_absorber", "components": [
+        _c("source_rect_cone", wx=1.0, wy=1.0, half_angle=5e-3, emin=20.0, emax=80.0),
+        _c("slit", pos=(0, 0, 1000.0), w=1.0, h=1.0),
+        _c("box", pos=(0, 0, 1500.0), hx=5.0, hy=5.0, hz=5.0, mu_a=2e4, mu_b=0.2),
+        _c("detector", pos=(0, 0, 2000.0), xmin=-50.0, xmax=50.0, ymin=-50.0, ymax=50.0,
+           emin=0.0, emax=1000.0, nx=128, ny=128, ne=1),
+    ]}
+
+
+EDCT_SOD = 800.0      # source to phantom centre (mm)
+EDCT_SDD = 1200.0     # source to detector (mm)
+EDCT_NX, EDCT_NY, EDCT_NE = 256, 64, 128
+EDCT_PITCH = 1.6      # mm
+
+
+def edct_half_angle() -> float:
+    hx = 0.5 * EDCT_NX * EDCT_PITCH
+    hy = 0.5 * EDCT_NY * EDCT_PITCH
+    return math.atan(math.sqrt(hx * hx + hy * hy) / EDCT_SDD)
+
+
+def edct_projection(volume: np.ndarray, mu_table: np.ndarray, angle: float = 0.0,
+                    strata: int = 1024, nx: int = EDCT_NX, ny: int = EDCT_NY, ne: int = EDCT_NE) -> Dict:
+    """Energy-dispersive CT projection: cone-beam point source (Kramers
+    continuum (150 - E)/E on 20-150 keV plus lines at 59.3 and 67.2 keV,
+    sigma 0.3 keV, 10 % of the photons each), voxel phantom of 1 mm voxels
+    centred 0.8 m from the source and turned by ``angle`` about +y, ideal
+    energy-resolving detector of nx x ny pixels of 1.6 mm and ne energy bins
+    over [20, 150) keV at 1.2 m.  The cone circumscribes the detector."""
+    hx = 0.5 * nx * EDCT_PITCH
+    hy = 0.5 * ny * EDCT_PITCH
+    return {"name": "edct_projection", "components": [
+        _c("source_cone_beam", half_angle=math.atan(math.sqrt(hx * hx + hy * hy) / EDCT_SDD),
+           emin=20.0, emax=150.0, e0=150.0, f_cont=0.8, e_line1=59.3, f_line1=0.1,
+           e_line2=67.2, f_line2=0.1, line_sigma=0.3, strata=strata),
+        _c("phantom", pos=(0, 0, EDCT_SOD), rot=rot_y(angle), voxel=1.0, volume=volume,
+           mu_table=mu_table, table_emin=20.0, table_emax=150.0),
+        _c("detector", pos=(0, 0, EDCT_SDD), xmin=-hx, xmax=hx, ymin=-hy, ymax=hy,
+           emin=20.0, emax=150.0, nx=nx, ny=ny, ne=ne),
+    ]}
+
+
+def beamline(d_spacings: np.ndarray = None, reflectivity: np.ndarray = None) -> Dict:
+    """Beamline optics: Gaussian undulator-like source (sigma 50 um,
+    divergence 20 urad, 12.4 keV +-1 %); elliptic mirror at 30 m focusing at
+    40 m (glancing 3 mrad, 1 m long, 512-angle reflectivity table); two-bounce
+    Si(111) monochromator at 35 m (Darwin plateau 30 urad, 10 mm gap); powder
+    plate of 200 d-spacings at the focus; 1024x1024 detector of 100 um pixels
+    100 mm behind it, normal to the exit beam."""
+    if d_spacings is None:
+        d_spacings = make_d_spacings(1)
+    if reflectivity is None:
+        reflectivity = make_mirror_reflectivity()
+    p, q, t0 = 30000.0, 10000.0, 3e-3
+    beam = np.array([0.0, math.sin(2 * t0), math.cos(2 * t0)])
+    pole = np.array([0.0, 0.0, p])
+    d_si = SI_LATTICE_ANGSTROM / math.sqrt(3.0)
+    theta_c = math.asin(HC_KEV_ANGSTROM / (2.0 * d_si * 12.4))
+    gap = 10.0
+    R = frame_along(beam)
+    dcm_pos = pole + 5000.0 * beam
+    n1_lab = R.T @ np.array([0.0, math.cos(theta_c), -math.sin(theta_c)])
+    focus = pole + q * beam + 2.0 * gap * n1_lab
+    det_pos = focus + 100.0 * beam
+    return {"name": "beamline", "components": [
+        _c("source_gaussian", sigma_x=0.05, sigma_y=0.05, sigma_xp=20e-6, sigma_yp=20e-6,
+           e0=12.4, rel_halfwidth=0.01),
+        _c("mirror_elliptic", pos=pole, p=p, q=q, theta0=t0, length=1000.0, width=50.0,
+           theta_max=6e-3, reflectivity=reflectivity),
+        _c("dcm", pos=dcm_pos, rot=R, d_spacing=d_si, theta_c=theta_c, darwin_width=30e-6, gap=gap),
+        _c("powder", pos=focus, rot=R, w=1.0, h=1.0, d_spacings=d_spacings),
+        _c("detector", pos=det_pos, rot=R, xmin=-51.2, xmax=51.2, ymin=-51.2, ymax=51.2,
+           emin=0.0, emax=1000.0, nx=1024, ny=1024, ne=1),
+    ]}
+
+
+# batched CT: projection angles x phantoms of uneven size
+BATCH_SIZES = (64, 128, 256, 512)
+BATCH_ANGLES = 360
