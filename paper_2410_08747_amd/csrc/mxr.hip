@@ -1,0 +1,661 @@
+// mxr.hip -- fused per-ray tracing kernels and the C ABI of include/mxr.h.
+//
+// One kernel launch traces a contiguous range of ray ids.  Each lane takes a
+// ray from the source through every component to the monitors with all
+// state in registers (paper, section 2.2: independent rays, local
+// intermediates; the monitor arrays are the only shared data and are updated
+// atomically).  The launch is XCD-aware: work-groups are dealt to the eight
+// XCDs round-robin, so work-group b works on the (b mod 8)-th eighth of the
+// ray range and neighbouring ray ids -- which the stratified cone-beam
+// source sends through neighbouring voxels -- share one XCD's L2.
+//
+// Component sequences that the library knows are compiled as fixed chains
+// (no per-component dispatch); any other sequence of supported components
+// runs through a generic chain that dispatches on the component type, which
+// is wave-uniform.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "mxr.h"
+#include "mxr_device.h"
+
+using namespace mxr;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kDynamic = -1;
+
+// ---------------------------------------------------------------- state --
+
+struct RayEnd {
+    int32_t status, dead_at;
+    int64_t bin;
+};
+
+struct LedgerLds {
+    double *slots;  // 4 * ncomp + 1 doubles in LDS, or null
+};
+
+template <bool LEDGER>
+__device__ __forceinline__ void ledger_add(const LedgerLds &L, int slot, double v) {
+    if constexpr (LEDGER) atomicAdd(L.slots + slot, v);
+}
+
+// Apply component k of type T.  Returns false when the ray is absorbed.
+template <int T, bool LEDGER, bool TRACE>
+__device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream &s, uint64_t ray_id,
+                                      const RunArgs &a, const double *mu_lds, uint32_t n_mat, uint32_t n_ebin,
+                                      RayEnd &end, const LedgerLds &L) {
+    if constexpr (T == MXR_SRC_RECT_CONE || T == MXR_SRC_CONE_BEAM || T == MXR_SRC_GAUSSIAN) {
+        if constexpr (T == MXR_SRC_RECT_CONE) src_rect_cone(c, s, ray);
+        if constexpr (T == MXR_SRC_CONE_BEAM) src_cone_beam(c, s, ray, ray_id, a);
+        if constexpr (T == MXR_SRC_GAUSSIAN) src_gaussian(c, s, ray);
+        ledger_add<LEDGER>(L, 4 * k, ray.w);
+        return true;
+    } else {
+        const double w_in = ray.w;
+        Ray before = ray;
+        bool ok = true;
+        int64_t bin = -1;
+        if constexpr (T == MXR_SLIT) ok = comp_slit(c, ray);
+        if constexpr (T == MXR_BOX) comp_box(c, ray);
+        if constexpr (T == MXR_PHANTOM) {
+            double q[3], dl[3];
+            to_local(c, ray, q, dl);
+            PhantomGeo g;
+            g.vol = (const uint8_t *)c.data0;
+            g.n[0] = (int)c.dims[0];
+            g.n[1] = (int)c.dims[1];
+            g.n[2] = (int)c.dims[2];
+            g.v = c.par[0];
+            g.corner[0] = c.aux[0];
+            g.corner[1] = c.aux[1];
+            g.corner[2] = c.aux[2];
+            double f = floor((ray.E - c.par[1]) * c.aux[3]);
+            int e = (int)fmin(fmax(f, 0.0), (double)(n_ebin - 1));
+            double tau = siddon_tau(g, q, dl, mu_lds + e * n_mat);
+            ray.w = ray.w * exp(-tau);
+        }
+        if constexpr (T == MXR_MIRROR_ELLIPTIC) ok = comp_mirror(c, ray);
+        if constexpr (T == MXR_DCM) ok = comp_dcm(c, ray);
+        if constexpr (T == MXR_POWDER) ok = comp_powder(c, s, ray);
+        if constexpr (T == MXR_DETECTOR) ok = comp_detector(c, ray, bin);
+        ledger_add<LEDGER>(L, 4 * k, w_in);
+        if (!ok) {
+            ray = before;
+            end.status = kAbsorbed;
+            end.dead_at = k;
+            ledger_add<LEDGER>(L, 4 * k + 1, w_in);
+            return false;
+        }
+        ledger_add<LEDGER>(L, 4 * k + 2, w_in - ray.w);
+        if constexpr (T == MXR_DETECTOR) {
+            if (bin >= 0) {
+                end.bin = bin;
+                if constexpr (!TRACE) {
+                    const uint32_t sl = c.slot;
+                    atomicAdd(a.tally.count[sl] + bin, 1ull);
+                    atomicAdd(a.tally.sum_w[sl] + bin, ray.w);
+                    atomicAdd(a.tally.sum_w2[sl] + bin, ray.w * ray.w);
+                }
+                ledger_add<LEDGER>(L, 4 * k + 3, ray.w);
+            }
+        }
+        return true;
+    }
+}
+
+template <bool LEDGER, bool TRACE>
+__device__ __forceinline__ bool apply_dynamic(const DevComp &c, int k, Ray &ray, Stream &s, uint64_t ray_id,
+                                              const RunArgs &a, const double *mu_lds, uint32_t n_mat,
+                                              uint32_t n_ebin, RayEnd &end, const LedgerLds &L) {
+#define MXR_CASE(T) \
+    case T: return apply<T, LEDGER, TRACE>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
+    switch (c.type) {
+        MXR_CASE(MXR_SRC_RECT_CONE)
+        MXR_CASE(MXR_SRC_CONE_BEAM)
+        MXR_CASE(MXR_SRC_GAUSSIAN)
+        MXR_CASE(MXR_SLIT)
+        MXR_CASE(MXR_BOX)
+        MXR_CASE(MXR_PHANTOM)
+        MXR_CASE(MXR_MIRROR_ELLIPTIC)
+        MXR_CASE(MXR_DCM)
+        MXR_CASE(MXR_POWDER)
+        MXR_CASE(MXR_DETECTOR)
+        default: break;
+    }
+#undef MXR_CASE
+    end.status = kAbsorbed;
+    end.dead_at = k;
+    return false;
+}
+
+// Fixed chains: the component types in instrument order.
+template <int... Ts>
+struct Chain {};
+
+template <bool LEDGER, bool TRACE, int T, int... Rest>
+__device__ __forceinline__ bool run_fixed(const DevInstr *ins, int k, Ray &ray, Stream &s, uint64_t ray_id,
+                                          const RunArgs &a, const double *mu_lds, uint32_t n_mat,
+                                          uint32_t n_ebin, RayEnd &end, const LedgerLds &L) {
+    if (!apply<T, LEDGER, TRACE>(ins->c[k], k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L)) return false;
+    if constexpr (sizeof...(Rest) > 0)
+        return run_fixed<LEDGER, TRACE, Rest...>(ins, k + 1, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
+    return true;
+}
+
+template <bool LEDGER, bool TRACE, int... Ts>
+__device__ __forceinline__ bool run_chain(Chain<Ts...>, const DevInstr *ins, Ray &ray, Stream &s, uint64_t ray_id,
+                                          const RunArgs &a, const double *mu_lds, uint32_t n_mat,
+                                          uint32_t n_ebin, RayEnd &end, const LedgerLds &L) {
+    if constexpr (sizeof...(Ts) == 1 && ((Ts == kDynamic) && ...)) {
+        const uint32_t n = ins->ncomp;
+        for (uint32_t k = 0; k < n; ++k)
+            if (!apply_dynamic<LEDGER, TRACE>(ins->c[k], (int)k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L))
+                return false;
+        return true;
+    } else {
+        return run_fixed<LEDGER, TRACE, Ts...>(ins, 0, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
+    }
+}
+
+template <class C, bool LEDGER, bool TRACE>
+__global__ __launch_bounds__(kBlock) void k_trace(RunArgs a) {
+    extern __shared__ double smem[];
+    const DevInstr *ins = a.ins;
+    const uint32_t n_mat = ins->n_mat, n_ebin = ins->n_ebin;
+    double *mu_lds = smem;
+    const uint32_t n_mu = (ins->phantom >= 0) ? n_mat * n_ebin : 0u;
+    if (n_mu) {
+        // stage mu / 10 (per mm), energy-major: row e holds every material
+        const double *T = (const double *)ins->c[ins->phantom].data1;
+        for (uint32_t i = threadIdx.x; i < n_mu; i += kBlock) {
+            uint32_t m = i / n_ebin, e = i - m * n_ebin;
+            mu_lds[e * n_mat + m] = T[i] / 10.0;
+        }
+    }
+    LedgerLds L{nullptr};
+    const uint32_t n_slots = 4 * ins->ncomp + 1;
+    if constexpr (LEDGER) {
+        L.slots = smem + n_mu;
+        for (uint32_t i = threadIdx.x; i < n_slots; i += kBlock) L.slots[i] = 0.0;
+    }
+    __syncthreads();
+
+    const uint32_t xcd = blockIdx.x & 7u, lb = blockIdx.x >> 3;
+    const uint64_t chunk = (a.n + 7) / 8;
+    const uint64_t lo = (uint64_t)xcd * chunk;
+    const uint64_t hi = lo + chunk < a.n ? lo + chunk : a.n;
+    const uint64_t stride = (uint64_t)a.blocks_per_xcd * kBlock;
+    for (uint64_t i = lo + (uint64_t)lb * kBlock + threadIdx.x; i < hi; i += stride) {
+        const uint64_t ray_id = TRACE ? a.ids[i] : a.first + i;
+        Stream s;
+        s.init(a.seed, ray_id, a.word3);
+        Ray ray;
+        ray.r[0] = ray.r[1] = ray.r[2] = 0.0;
+        ray.d[0] = ray.d[1] = ray.d[2] = 0.0;
+        ray.E = 0.0;
+        ray.w = 0.0;
+        RayEnd end{kExited, -1, -1};
+        bool alive = run_chain<LEDGER, TRACE>(C{}, ins, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
+        if constexpr (LEDGER) {
+            if (alive) atomicAdd(L.slots + 4 * ins->ncomp, ray.w);
+        }
+        if constexpr (TRACE) {
+            a.dump.x[i] = ray.r[0];
+            a.dump.y[i] = ray.r[1];
+            a.dump.z[i] = ray.r[2];
+            a.dump.dx[i] = ray.d[0];
+            a.dump.dy[i] = ray.d[1];
+            a.dump.dz[i] = ray.d[2];
+            a.dump.E[i] = ray.E;
+            a.dump.w[i] = ray.w;
+            a.dump.status[i] = end.status;
+            a.dump.dead_at[i] = end.dead_at;
+            a.dump.bin[i] = end.bin;
+        }
+        (void)alive;
+    }
+    if constexpr (LEDGER) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < n_slots; i += kBlock) {
+            double v = L.slots[i];
+            if (v != 0.0) atomicAdd(a.ledger + i, v);
+        }
+    }
+}
+
+// Largest material id in a volume (run once at create).
+__global__ __launch_bounds__(kBlock) void k_max_id(const uint8_t *vol, uint64_t n, unsigned int *out) {
+    unsigned int m = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock)
+        m = m > vol[i] ? m : vol[i];
+    __shared__ unsigned int red[kBlock];
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + w] ? red[threadIdx.x] : red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, red[0]);
+}
+
+// ------------------------------------------------------------- recipes --
+
+using ChainGeneric = Chain<kDynamic>;
+using ChainBasic = Chain<MXR_SRC_RECT_CONE, MXR_SLIT, MXR_BOX, MXR_DETECTOR>;
+using ChainEdct = Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR>;
+using ChainBeamline = Chain<MXR_SRC_GAUSSIAN, MXR_MIRROR_ELLIPTIC, MXR_DCM, MXR_POWDER, MXR_DETECTOR>;
+
+enum Recipe { kRecipeGeneric = 0, kRecipeBasic, kRecipeEdct, kRecipeBeamline, kNumRecipes };
+
+typedef void (*KernelFn)(RunArgs);
+
+template <class C>
+struct KernelSet {
+    static KernelFn get(bool ledger, bool trace) {
+        if (trace) return ledger ? k_trace<C, true, true> : k_trace<C, false, true>;
+        return ledger ? k_trace<C, true, false> : k_trace<C, false, false>;
+    }
+};
+
+KernelFn pick_kernel(int recipe, bool ledger, bool trace) {
+    switch (recipe) {
+        case kRecipeBasic: return KernelSet<ChainBasic>::get(ledger, trace);
+        case kRecipeEdct: return KernelSet<ChainEdct>::get(ledger, trace);
+        case kRecipeBeamline: return KernelSet<ChainBeamline>::get(ledger, trace);
+        default: return KernelSet<ChainGeneric>::get(ledger, trace);
+    }
+}
+
+int match_recipe(const DevInstr &d) {
+    auto is = [&](std::initializer_list<int> seq) {
+        if (d.ncomp != seq.size()) return false;
+        int k = 0;
+        for (int t : seq)
+            if ((int)d.c[k++].type != t) return false;
+        return true;
+    };
+    if (is({MXR_SRC_RECT_CONE, MXR_SLIT, MXR_BOX, MXR_DETECTOR})) return kRecipeBasic;
+    if (is({MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR})) return kRecipeEdct;
+    if (is({MXR_SRC_GAUSSIAN, MXR_MIRROR_ELLIPTIC, MXR_DCM, MXR_POWDER, MXR_DETECTOR})) return kRecipeBeamline;
+    return kRecipeGeneric;
+}
+
+// --------------------------------------------------------------- errors --
+
+thread_local std::string g_error = "no error";
+
+mxr_status fail(mxr_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return st;
+}
+
+mxr_status hip_fail(hipError_t e, const char *what) {
+    return fail(MXR_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_all(const double *p, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+bool is_source(uint32_t t) { return t == MXR_SRC_RECT_CONE || t == MXR_SRC_CONE_BEAM || t == MXR_SRC_GAUSSIAN; }
+
+int draws_of(uint32_t t) {
+    switch (t) {
+        case MXR_SRC_RECT_CONE: return 5;
+        case MXR_SRC_CONE_BEAM: return 3;
+        case MXR_SRC_GAUSSIAN: return 5;
+        case MXR_POWDER: return 2;
+        default: return 0;
+    }
+}
+
+}  // namespace
+
+struct mxr_instrument {
+    int device;
+    DevInstr host;
+    DevInstr *dev;
+    int recipe;
+    uint32_t n_det;
+    uint64_t det_bins[MXR_MAX_DETECTORS];
+    uint64_t strata;  // G of the cone-beam source, 0 if none
+};
+
+// Derive per-component constants on the host (glibc), validate ranges.
+static mxr_status derive(const mxr_component_desc &s, DevComp &c, int k, uint32_t &n_mat, uint32_t &n_ebin) {
+    c.type = s.type;
+    c.flags = s.flags;
+    std::memcpy(c.pos, s.pos, sizeof c.pos);
+    std::memcpy(c.rot, s.rot, sizeof c.rot);
+    std::memcpy(c.par, s.par, sizeof c.par);
+    std::memset(c.aux, 0, sizeof c.aux);
+    c.data0 = s.data[0];
+    c.data1 = s.data[1];
+    c.n0 = s.data_len[0];
+    c.n1 = s.data_len[1];
+    std::memcpy(c.dims, s.dims, sizeof c.dims);
+    if (!finite_all(s.pos, 3) || !finite_all(s.rot, 9) || !finite_all(s.par, 16))
+        return fail(MXR_E_INVALID, "component %d: non-finite position, rotation or parameter", k);
+    const double *p = s.par;
+    switch (s.type) {
+        case MXR_SRC_RECT_CONE:
+            if (!(p[0] >= 0 && p[1] >= 0 && p[2] > 0 && p[2] < kPi && p[4] > p[3] && p[3] > 0))
+                return fail(MXR_E_INVALID, "component %d: bad rectangular source parameters", k);
+            c.aux[0] = std::sin(0.5 * p[2]);
+            c.aux[1] = p[4] - p[3];
+            break;
+        case MXR_SRC_CONE_BEAM:
+            if (!(p[0] > 0 && p[0] < kPi && p[2] > p[1] && p[1] > 0 && p[3] >= p[2] && p[9] > 0))
+                return fail(MXR_E_INVALID, "component %d: bad cone-beam source parameters", k);
+            if (s.dims[0] < 1 || s.dims[0] > 65536)
+                return fail(MXR_E_INVALID, "component %d: strata per side must be in [1, 65536]", k);
+            c.aux[0] = std::sin(0.5 * p[0]);
+            c.aux[1] = p[2] - p[1];
+            c.aux[2] = p[3] * std::log(p[2] / p[1]) - (p[2] - p[1]);
+            c.aux[3] = p[9] * std::sqrt(2.0 * M_PI);
+            break;
+        case MXR_SRC_GAUSSIAN:
+            if (!(p[0] >= 0 && p[1] >= 0 && p[2] >= 0 && p[3] >= 0 && p[4] > 0 && p[5] >= 0 && p[5] < 1))
+                return fail(MXR_E_INVALID, "component %d: bad Gaussian source parameters", k);
+            break;
+        case MXR_SLIT:
+            if (s.flags & 1u) {
+                if (!(p[2] >= 0)) return fail(MXR_E_INVALID, "component %d: bad slit radius", k);
+                c.aux[2] = p[2] * p[2];
+            } else {
+                if (!(p[0] >= 0 && p[1] >= 0)) return fail(MXR_E_INVALID, "component %d: bad slit size", k);
+                c.aux[0] = 0.5 * p[0];
+                c.aux[1] = 0.5 * p[1];
+            }
+            break;
+        case MXR_BOX:
+            if (!(p[0] > 0 && p[1] > 0 && p[2] > 0)) return fail(MXR_E_INVALID, "component %d: bad box size", k);
+            break;
+        case MXR_PHANTOM: {
+            if (!s.data[0] || !s.data[1]) return fail(MXR_E_INVALID, "component %d: phantom needs volume and mu table", k);
+            uint64_t nvox = (uint64_t)s.dims[0] * s.dims[1] * s.dims[2];
+            if (s.dims[0] < 1 || s.dims[1] < 1 || s.dims[2] < 1 || nvox != s.data_len[0])
+                return fail(MXR_E_INVALID, "component %d: volume size does not match dims", k);
+            if (nvox >= (1ull << 31) || s.dims[0] + s.dims[1] + s.dims[2] > (1u << 20))
+                return fail(MXR_E_UNSUPPORTED, "component %d: volume too large", k);
+            if (s.dims[3] < 1 || s.dims[3] > 16) return fail(MXR_E_UNSUPPORTED, "component %d: 1..16 materials", k);
+            if (s.data_len[1] % s.dims[3] != 0 || s.data_len[1] / s.dims[3] < 1 || s.data_len[1] / s.dims[3] > 256)
+                return fail(MXR_E_UNSUPPORTED, "component %d: 1..256 energy bins per material", k);
+            if (!(p[0] > 0 && p[2] > p[1])) return fail(MXR_E_INVALID, "component %d: bad voxel size or table range", k);
+            n_mat = s.dims[3];
+            n_ebin = (uint32_t)(s.data_len[1] / s.dims[3]);
+            for (int i = 0; i < 3; ++i) c.aux[i] = -0.5 * ((double)s.dims[i] * p[0]);
+            c.aux[3] = (double)n_ebin / (p[2] - p[1]);
+            break;
+        }
+        case MXR_MIRROR_ELLIPTIC: {
+            double P = p[0], Q = p[1], t0 = p[2];
+            if (!(P > 0 && Q > 0 && t0 > 0 && t0 < 0.5 && p[3] > 0 && p[4] > 0 && p[5] > 0) || !s.data[0] ||
+                s.data_len[0] < 2)
+                return fail(MXR_E_INVALID, "component %d: bad mirror parameters", k);
+            double a = 0.5 * (P + Q);
+            double b2 = P * Q * (std::sin(t0) * std::sin(t0));
+            double F2y = Q * std::sin(2.0 * t0), F2z = Q * std::cos(2.0 * t0);
+            double fy = F2y, fz = F2z + P;
+            double two_c = std::sqrt(fy * fy + fz * fz);
+            double uy = fy / two_c, uz = fz / two_c;
+            c.aux[0] = 0.5 * F2y;
+            c.aux[1] = 0.5 * (F2z - P);
+            c.aux[2] = uy;
+            c.aux[3] = uz;
+            c.aux[4] = uz;
+            c.aux[5] = -uy;
+            c.aux[6] = 1.0 / (a * a);
+            c.aux[7] = 1.0 / b2;
+            c.aux[8] = std::sin(t0);
+            c.aux[9] = std::cos(t0);
+            c.aux[10] = 0.5 * p[3];
+            c.aux[11] = 0.5 * p[4];
+            c.aux[12] = p[5] / (double)(s.data_len[0] - 1);
+            break;
+        }
+        case MXR_DCM: {
+            if (!(p[0] > 0 && p[1] > 0 && p[1] < 0.5 * kPi && p[2] > 0 && p[3] > 0))
+                return fail(MXR_E_INVALID, "component %d: bad monochromator parameters", k);
+            double n1[3] = {0.0, std::cos(p[1]), -std::sin(p[1])};
+            for (int i = 0; i < 3; ++i) {
+                c.aux[i] = n1[i];
+                c.aux[3 + i] = -n1[i];
+                c.aux[6 + i] = p[3] * n1[i];
+            }
+            c.aux[9] = 2.0 * p[0];
+            c.aux[10] = 0.5 * p[2];
+            break;
+        }
+        case MXR_POWDER:
+            if (!(p[0] >= 0 && p[1] >= 0) || !s.data[0] || s.data_len[0] < 1)
+                return fail(MXR_E_INVALID, "component %d: bad powder parameters", k);
+            c.aux[0] = 0.5 * p[0];
+            c.aux[1] = 0.5 * p[1];
+            break;
+        case MXR_DETECTOR:
+            if (s.dims[0] < 1 || s.dims[1] < 1 || s.dims[2] < 1 || !(p[1] > p[0] && p[3] > p[2] && p[5] > p[4]))
+                return fail(MXR_E_INVALID, "component %d: bad monitor binning", k);
+            c.aux[0] = (double)s.dims[0] / (p[1] - p[0]);
+            c.aux[1] = (double)s.dims[1] / (p[3] - p[2]);
+            c.aux[2] = (double)s.dims[2] / (p[5] - p[4]);
+            break;
+        default:
+            return fail(MXR_E_INVALID, "component %d: unknown type %u", k, s.type);
+    }
+    return MXR_OK;
+}
+
+extern "C" {
+
+uint32_t mxr_abi_version(void) { return MXR_ABI_VERSION; }
+
+const char *mxr_last_error(void) { return g_error.c_str(); }
+
+mxr_status mxr_instrument_create(const mxr_instrument_desc *desc, mxr_instrument **out) {
+    if (!desc || !out) return fail(MXR_E_INVALID, "null descriptor or output pointer");
+    *out = nullptr;
+    if (desc->abi_version != MXR_ABI_VERSION)
+        return fail(MXR_E_INVALID, "descriptor ABI version %u, library %u", desc->abi_version, MXR_ABI_VERSION);
+    if (desc->n_components < 1 || desc->n_components > MXR_MAX_COMPONENTS || !desc->components)
+        return fail(MXR_E_INVALID, "need 1..%u components", MXR_MAX_COMPONENTS);
+    mxr_instrument *ins = new (std::nothrow) mxr_instrument();
+    if (!ins) return fail(MXR_E_NOMEM, "host allocation failed");
+    std::memset(&ins->host, 0, sizeof ins->host);
+    DevInstr &d = ins->host;
+    d.ncomp = desc->n_components;
+    d.phantom = -1;
+    uint32_t draw = 0, n_det = 0, n_phantom = 0;
+    for (uint32_t k = 0; k < desc->n_components; ++k) {
+        const mxr_component_desc &s = desc->components[k];
+        if ((k == 0) != is_source(s.type)) {
+            delete ins;
+            return fail(MXR_E_INVALID, "component %u: the first component, and only it, must be a source", k);
+        }
+        uint32_t nm = 0, ne = 0;
+        mxr_status st = derive(s, d.c[k], (int)k, nm, ne);
+        if (st != MXR_OK) {
+            delete ins;
+            return st;
+        }
+        d.c[k].draw0 = draw;
+        draw += draws_of(s.type);
+        if (s.type == MXR_PHANTOM) {
+            if (++n_phantom > 1) {
+                delete ins;
+                return fail(MXR_E_UNSUPPORTED, "at most one phantom per instrument");
+            }
+            d.phantom = (int32_t)k;
+            d.n_mat = nm;
+            d.n_ebin = ne;
+        }
+        if (s.type == MXR_DETECTOR) {
+            if (n_det >= MXR_MAX_DETECTORS) {
+                delete ins;
+                return fail(MXR_E_UNSUPPORTED, "at most %u monitors", MXR_MAX_DETECTORS);
+            }
+            d.c[k].slot = n_det;
+            ins->det_bins[n_det] = (uint64_t)s.dims[0] * s.dims[1] * s.dims[2];
+            n_det++;
+        }
+        if (s.type == MXR_SRC_CONE_BEAM) ins->strata = s.dims[0];
+    }
+    ins->n_det = n_det;
+    ins->recipe = match_recipe(d);
+    hipError_t e = hipGetDevice(&ins->device);
+    if (e != hipSuccess) {
+        delete ins;
+        return hip_fail(e, "hipGetDevice");
+    }
+    e = hipMalloc((void **)&ins->dev, sizeof(DevInstr));
+    if (e != hipSuccess) {
+        delete ins;
+        return fail(MXR_E_NOMEM, "hipMalloc of the instrument block: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpy(ins->dev, &d, sizeof(DevInstr), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(ins->dev);
+        delete ins;
+        return hip_fail(e, "hipMemcpy of the instrument block");
+    }
+    if (d.phantom >= 0) {
+        // every material id must index the mu table
+        const DevComp &c = d.c[d.phantom];
+        unsigned int *dmax = nullptr, hmax = 0;
+        e = hipMalloc((void **)&dmax, sizeof(unsigned int));
+        if (e == hipSuccess) e = hipMemset(dmax, 0, sizeof(unsigned int));
+        if (e == hipSuccess) {
+            uint64_t nb = std::min<uint64_t>((c.n0 + kBlock - 1) / kBlock, 4096);
+            hipLaunchKernelGGL(k_max_id, dim3((unsigned)nb), dim3(kBlock), 0, 0, (const uint8_t *)c.data0, c.n0, dmax);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpy(&hmax, dmax, sizeof(unsigned int), hipMemcpyDeviceToHost);
+        if (dmax) (void)hipFree(dmax);
+        if (e != hipSuccess) {
+            (void)hipFree(ins->dev);
+            delete ins;
+            return hip_fail(e, "phantom id check");
+        }
+        if (hmax >= d.n_mat) {
+            (void)hipFree(ins->dev);
+            delete ins;
+            return fail(MXR_E_INVALID, "phantom holds material id %u but the table has %u materials", hmax, d.n_mat);
+        }
+    }
+    *out = ins;
+    return MXR_OK;
+}
+
+void mxr_instrument_destroy(mxr_instrument *ins) {
+    if (!ins) return;
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != ins->device) (void)hipSetDevice(ins->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ins->dev);
+    if (cur >= 0 && cur != ins->device) (void)hipSetDevice(cur);
+    delete ins;
+}
+
+static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, bool ledger, bool trace,
+                         hipStream_t stream) {
+    RunArgs a = base;
+    // work-groups: enough to cover n with one ray per lane, capped at a few
+    // waves of resident work-groups per CU; a multiple of the 8 XCDs
+    uint64_t want = (n + kBlock - 1) / kBlock;
+    uint64_t cap = 256ull * 8 * 4;
+    uint64_t blocks = std::min(want, cap);
+    blocks = std::max<uint64_t>(8, (blocks + 7) / 8 * 8);
+    a.blocks_per_xcd = (uint32_t)(blocks / 8);
+    size_t shmem = 0;
+    if (ins->host.phantom >= 0) shmem += (size_t)ins->host.n_mat * ins->host.n_ebin * sizeof(double);
+    if (ledger) shmem += (size_t)(4 * ins->host.ncomp + 1) * sizeof(double);
+    KernelFn k = pick_kernel(ins->recipe, ledger, trace);
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kBlock), shmem, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return MXR_OK;
+}
+
+static mxr_status common_args(mxr_instrument *ins, uint64_t n_total, uint64_t seed, uint32_t purpose, uint32_t job,
+                              RunArgs &a) {
+    if (!ins) return fail(MXR_E_INVALID, "null instrument");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != ins->device) return fail(MXR_E_STATE, "instrument lives on device %d, device %d is current", ins->device, cur);
+    if (purpose > 255 || job > 0xFFFFFFu) return fail(MXR_E_INVALID, "purpose must be < 256 and job < 2^24");
+    if (n_total < 1) return fail(MXR_E_INVALID, "n_total must be positive");
+    std::memset(&a, 0, sizeof a);
+    a.ins = ins->dev;
+    a.n_total = n_total;
+    a.seed = seed;
+    a.word3 = (purpose << 24) | job;
+    uint64_t G = ins->strata ? ins->strata : 1;
+    while (G > 1 && G * G > n_total) G -= 1;
+    a.G = G;
+    a.G2 = G * G;
+    if (a.G2 > 1 && n_total > (~0ull) / a.G2) return fail(MXR_E_INVALID, "n_total * strata^2 must stay below 2^64");
+    return MXR_OK;
+}
+
+mxr_status mxr_run(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays, uint64_t n_total, uint64_t seed,
+                   uint32_t purpose, uint32_t job, const mxr_tally *tallies, uint32_t n_tallies, double *ledger,
+                   void *hip_stream) {
+    RunArgs a;
+    mxr_status st = common_args(ins, n_total, seed, purpose, job, a);
+    if (st != MXR_OK) return st;
+    if (first_ray > n_total || n_rays > n_total - first_ray)
+        return fail(MXR_E_INVALID, "rays [%llu, %llu) exceed n_total %llu", (unsigned long long)first_ray,
+                    (unsigned long long)(first_ray + n_rays), (unsigned long long)n_total);
+    if (n_tallies != ins->n_det) return fail(MXR_E_INVALID, "%u tallies given, instrument has %u monitors", n_tallies, ins->n_det);
+    if (n_tallies && !tallies) return fail(MXR_E_INVALID, "null tallies");
+    for (uint32_t i = 0; i < n_tallies; ++i) {
+        if (!tallies[i].count || !tallies[i].sum_w || !tallies[i].sum_w2)
+            return fail(MXR_E_INVALID, "tally %u has a null array", i);
+        if (tallies[i].n_bins != ins->det_bins[i])
+            return fail(MXR_E_INVALID, "tally %u has %llu bins, monitor needs %llu", i,
+                        (unsigned long long)tallies[i].n_bins, (unsigned long long)ins->det_bins[i]);
+        a.tally.count[i] = (unsigned long long *)tallies[i].count;
+        a.tally.sum_w[i] = tallies[i].sum_w;
+        a.tally.sum_w2[i] = tallies[i].sum_w2;
+    }
+    if (n_rays == 0) return MXR_OK;
+    a.first = first_ray;
+    a.n = n_rays;
+    a.ledger = ledger;
+    return launch(ins, a, n_rays, ledger != nullptr, false, (hipStream_t)hip_stream);
+}
+
+mxr_status mxr_trace_rays(mxr_instrument *ins, const uint64_t *ray_ids, uint64_t n, uint64_t n_total, uint64_t seed,
+                          uint32_t purpose, uint32_t job, const mxr_ray_soa *out, void *hip_stream) {
+    RunArgs a;
+    mxr_status st = common_args(ins, n_total, seed, purpose, job, a);
+    if (st != MXR_OK) return st;
+    if (n == 0) return MXR_OK;
+    if (!ray_ids || !out) return fail(MXR_E_INVALID, "null ray ids or output");
+    const mxr_ray_soa &o = *out;
+    if (!o.x || !o.y || !o.z || !o.dx || !o.dy || !o.dz || !o.E || !o.w || !o.status || !o.dead_at || !o.bin)
+        return fail(MXR_E_INVALID, "null output array");
+    a.n = n;
+    a.ids = ray_ids;
+    a.dump = o;
+    return launch(ins, a, n, false, true, (hipStream_t)hip_stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,544 @@
+// mxr_device.h -- per-ray device code for gfx950: counter-based RNG, ray
+// state in registers, the component models and the voxel traversal.
+//
+// One lane carries one ray from the source to the end of the component list
+// (paper, section 2.2: rays are independent; every per-ray intermediate is
+// local).  Component parameters live in a small device block read with
+// wave-uniform (scalar) loads; the only shared writable state is the monitor
+// histograms, updated with FP64 atomics (paper, section 2.2.2: the monitor
+// arrays are the one structure threads must share).
+//
+// The library is compiled with -ffp-contract=off: every expression rounds as
+// written, so wherever a formula is the same as in an independent
+// implementation the two agree bit for bit; FMA is spelled out only in the
+// traversal's inner loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mxr.h"
+
+namespace mxr {
+
+constexpr double kHc = 12.398419843320026;  // keV * Angstrom (CODATA 2018)
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 2.0 * 3.14159265358979323846;
+constexpr double kInf = __builtin_huge_val();
+
+enum RayStatus : int32_t { kAlive = 0, kExited = 1, kAbsorbed = 2 };
+
+// Device copy of one component: the caller's parameters plus constants the
+// host derives once (aux), the first uniform index it draws, and for a
+// monitor its tally slot.
+struct DevComp {
+    uint32_t type, flags, draw0, slot;
+    double pos[3];
+    double rot[9];
+    double par[16];
+    double aux[16];
+    const void *data0;
+    const void *data1;
+    uint64_t n0, n1;
+    uint32_t dims[4];
+};
+
+struct DevInstr {
+    uint32_t ncomp;
+    int32_t phantom;  // index of the phantom component or -1
+    uint32_t n_mat, n_ebin;
+    DevComp c[MXR_MAX_COMPONENTS];
+};
+
+struct TallyPtrs {
+    unsigned long long *count[MXR_MAX_DETECTORS];
+    double *sum_w[MXR_MAX_DETECTORS];
+    double *sum_w2[MXR_MAX_DETECTORS];
+};
+
+struct RunArgs {
+    const DevInstr *ins;
+    uint64_t first, n, n_total, seed;
+    uint64_t G, G2;  // strata per side used, and its square
+    uint32_t word3;  // purpose << 24 | job
+    uint32_t blocks_per_xcd;
+    TallyPtrs tally;
+    double *ledger;
+    const uint64_t *ids;  // trace mode: ray ids
+    mxr_ray_soa dump;     // trace mode: outputs
+};
+
+// ------------------------------------------------------------- Philox ----
+// Philox4x32-10 (Salmon et al., SC'11).  The 32x32->64 products map to
+// v_mad_u64_u32.
+struct Philox {
+    uint32_t k0, k1, c1, c2, c3;
+
+    __device__ __forceinline__ void block(uint32_t j, uint32_t out[4]) const {
+        uint32_t x0 = j, x1 = c1, x2 = c2, x3 = c3, a = k0, b = k1;
+#pragma unroll
+        for (int r = 0; r < 10; ++r) {
+            uint64_t pa = (uint64_t)0xD2511F53u * x0;
+            uint64_t pb = (uint64_t)0xCD9E8D57u * x2;
+            uint32_t y0 = (uint32_t)(pb >> 32) ^ x1 ^ a;
+            uint32_t y2 = (uint32_t)(pa >> 32) ^ x3 ^ b;
+            x1 = (uint32_t)pb;
+            x3 = (uint32_t)pa;
+            x0 = y0;
+            x2 = y2;
+            a += 0x9E3779B9u;
+            b += 0xBB67AE85u;
+        }
+        out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+    }
+};
+
+__device__ __forceinline__ double u01(uint32_t lo, uint32_t hi) {
+    uint64_t w = ((uint64_t)hi << 32) | lo;
+    return ((double)(w >> 12) + 0.5) * 0x1.0p-52;
+}
+
+// Uniforms of one ray, produced two at a time on demand.
+struct Stream {
+    Philox ph;
+    int blk;
+    uint32_t w[4];
+
+    __device__ __forceinline__ void init(uint64_t seed, uint64_t ray, uint32_t word3) {
+        ph.k0 = (uint32_t)seed;
+        ph.k1 = (uint32_t)(seed >> 32);
+        ph.c1 = (uint32_t)ray;
+        ph.c2 = (uint32_t)(ray >> 32);
+        ph.c3 = word3;
+        blk = -1;
+    }
+    __device__ __forceinline__ double u(int index) {
+        int b = index >> 1;
+        if (b != blk) {
+            ph.block((uint32_t)b, w);
+            blk = b;
+        }
+        return (index & 1) ? u01(w[2], w[3]) : u01(w[0], w[1]);
+    }
+};
+
+// ---------------------------------------------------------------- ray ----
+struct Ray {
+    double r[3], d[3];
+    double E, w;
+};
+
+__device__ __forceinline__ void to_local(const DevComp &c, const Ray &ray, double q[3], double dl[3]) {
+    double v0 = ray.r[0] - c.pos[0], v1 = ray.r[1] - c.pos[1], v2 = ray.r[2] - c.pos[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double *R = c.rot + 3 * i;
+        q[i] = R[0] * v0 + R[1] * v1 + R[2] * v2;
+        dl[i] = R[0] * ray.d[0] + R[1] * ray.d[1] + R[2] * ray.d[2];
+    }
+}
+
+__device__ __forceinline__ void to_lab(const DevComp &c, const double q[3], const double dl[3], Ray &ray) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        ray.r[i] = c.rot[i] * q[0] + c.rot[3 + i] * q[1] + c.rot[6 + i] * q[2] + c.pos[i];
+        ray.d[i] = c.rot[i] * dl[0] + c.rot[3 + i] * dl[1] + c.rot[6 + i] * dl[2];
+    }
+}
+
+__device__ __forceinline__ bool plane_z0(double q[3], const double dl[3]) {
+    if (!(dl[2] > 0.0)) return false;
+    double t = -q[2] / dl[2];
+    if (!(t >= 0.0)) return false;
+    q[0] = q[0] + t * dl[0];
+    q[1] = q[1] + t * dl[1];
+    q[2] = 0.0;
+    return true;
+}
+
+// ------------------------------------------------------------ sources ----
+// Square emitter, cone uniform in solid angle: with s = sqrt(U) sin(a/2) =
+// sin(theta/2), sin(theta) = 2 s sqrt(1 - s^2) and cos(theta) = 1 - 2 s^2,
+// free of the cancellation of 1 - cos at small angles.
+__device__ __forceinline__ void src_rect_cone(const DevComp &c, Stream &s, Ray &ray) {
+    double q[3], dl[3];
+    q[0] = (s.u(0) - 0.5) * c.par[0];
+    q[1] = (s.u(1) - 0.5) * c.par[1];
+    q[2] = 0.0;
+    double sh = sqrt(s.u(2)) * c.aux[0];
+    double ch = sqrt(1.0 - sh * sh);
+    double sinp, cosp;
+    sincos(kTwoPi * s.u(3), &sinp, &cosp);
+    double st = 2.0 * sh * ch;
+    dl[0] = st * cosp;
+    dl[1] = st * sinp;
+    dl[2] = 1.0 - 2.0 * (sh * sh);
+    ray.E = c.par[3] + c.aux[1] * s.u(4);
+    ray.w = 1.0;
+    to_lab(c, q, dl, ray);
+}
+
+__device__ __forceinline__ double spectrum(const DevComp &c, double E) {
+    double z1 = (E - c.par[5]) / c.par[9];
+    double z2 = (E - c.par[7]) / c.par[9];
+    double g1 = exp(-0.5 * z1 * z1) / c.aux[3];
+    double g2 = exp(-0.5 * z2 * z2) / c.aux[3];
+    return c.par[4] * ((c.par[3] - E) / E) / c.aux[2] + c.par[6] * g1 + c.par[8] * g2;
+}
+
+// Cone-beam point source, stratified: ray r lies in cell floor(r G^2 / N);
+// the cell's square is mapped to the unit disk by the concentric map and the
+// disk radius rho to the cone by sin(theta/2) = rho sin(alpha/2).  Then
+// (dx, dy) = sin(theta) (px, py) / rho = 2 sin(alpha/2) cos(theta/2) (px, py).
+__device__ __forceinline__ void src_cone_beam(const DevComp &c, Stream &s, Ray &ray, uint64_t ray_id,
+                                              const RunArgs &a) {
+    uint64_t cell = (ray_id * a.G2) / a.n_total;
+    uint64_t first = (cell * a.n_total + a.G2 - 1) / a.G2;
+    uint64_t next = ((cell + 1) * a.n_total + a.G2 - 1) / a.G2;
+    double factor = ((double)a.n_total / (double)a.G2) / (double)(next - first);
+    double u = ((double)(cell % a.G) + s.u(0)) / (double)a.G;
+    double v = ((double)(cell / a.G) + s.u(1)) / (double)a.G;
+    double ca = 2.0 * u - 1.0, cb = 2.0 * v - 1.0;
+    double rad, ang;
+    if (ca == 0.0 && cb == 0.0) {
+        rad = 0.0;
+        ang = 0.0;
+    } else if (fabs(ca) > fabs(cb)) {
+        rad = ca;
+        ang = (kPi / 4.0) * (cb / ca);
+    } else {
+        rad = cb;
+        ang = (kPi / 2.0) - (kPi / 4.0) * (ca / cb);
+    }
+    double sa, cs;
+    sincos(ang, &sa, &cs);
+    double px = rad * cs, py = rad * sa;
+    double sh = fabs(rad) * c.aux[0];
+    double ch = sqrt(1.0 - sh * sh);
+    double k = 2.0 * c.aux[0] * ch;
+    ray.r[0] = c.pos[0];
+    ray.r[1] = c.pos[1];
+    ray.r[2] = c.pos[2];
+    double dl[3] = {k * px, k * py, 1.0 - 2.0 * (sh * sh)};
+    double q[3] = {0.0, 0.0, 0.0};
+    ray.E = c.par[1] + c.aux[1] * s.u(2);
+    ray.w = (c.aux[1] * spectrum(c, ray.E)) * factor;
+    to_lab(c, q, dl, ray);
+}
+
+__device__ __forceinline__ void src_gaussian(const DevComp &c, Stream &s, Ray &ray) {
+    double r1 = sqrt(-2.0 * log(s.u(0)));
+    double s1, c1, s2, c2;
+    sincos(kTwoPi * s.u(1), &s1, &c1);
+    double r2 = sqrt(-2.0 * log(s.u(2)));
+    sincos(kTwoPi * s.u(3), &s2, &c2);
+    double q[3], dl[3];
+    q[0] = c.par[0] * (r1 * c1);
+    q[1] = c.par[1] * (r1 * s1);
+    q[2] = 0.0;
+    double tx = tan(c.par[2] * (r2 * c2));
+    double ty = tan(c.par[3] * (r2 * s2));
+    double nrm = sqrt(tx * tx + ty * ty + 1.0);
+    dl[0] = tx / nrm;
+    dl[1] = ty / nrm;
+    dl[2] = 1.0 / nrm;
+    ray.E = c.par[4] * ((1.0 - c.par[5]) + 2.0 * c.par[5] * s.u(4));
+    ray.w = 1.0;
+    to_lab(c, q, dl, ray);
+}
+
+// ---------------------------------------------------------- apertures ----
+__device__ __forceinline__ bool comp_slit(const DevComp &c, Ray &ray) {
+    double q[3], dl[3];
+    to_local(c, ray, q, dl);
+    if (!plane_z0(q, dl)) return false;
+    if (c.flags & 1u) {
+        if (!(q[0] * q[0] + q[1] * q[1] <= c.aux[2])) return false;
+    } else {
+        if (!(fabs(q[0]) <= c.aux[0] && fabs(q[1]) <= c.aux[1])) return false;
+    }
+    to_lab(c, q, dl, ray);
+    return true;
+}
+
+__device__ __forceinline__ void comp_box(const DevComp &c, Ray &ray) {
+    double q[3], dl[3];
+    to_local(c, ray, q, dl);
+    double a_in = 0.0, a_out = kInf;
+    bool miss = false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double h = c.par[i];
+        if (dl[i] == 0.0) {
+            if (!(q[i] > -h && q[i] < h)) miss = true;
+        } else {
+            double inv = 1.0 / dl[i];
+            double a0 = (-h - q[i]) * inv, a1 = (h - q[i]) * inv;
+            double lo = a0 < a1 ? a0 : a1, hi = a0 < a1 ? a1 : a0;
+            if (lo > a_in) a_in = lo;
+            if (hi < a_out) a_out = hi;
+        }
+    }
+    double L = (!miss && a_out > a_in) ? a_out - a_in : 0.0;
+    double E = ray.E;
+    double mu = c.par[3] / (E * E * E) + c.par[4];
+    ray.w = ray.w * exp(-(mu * L) / 10.0);
+}
+
+// ------------------------------------------------------------ phantom ----
+// Exact radiological path through the voxel grid as an incremental 3-D
+// traversal (Amanatides & Woo 1987; Jacobs et al. 1998): the next crossing
+// of each axis is kept, the nearest one is taken, the voxel index steps by
+// one.  Every crossing parameter is computed from its plane index,
+// alpha = (corner + i v - q) / d with the reciprocal precomputed, never
+// accumulated, so it is the same number whichever order the planes are
+// visited in.  mu_tab points to the ray's energy row (mu / 10, per mm)
+// staged in LDS; the loop is bounded by nx + ny + nz + 3 visits.
+struct PhantomGeo {
+    const uint8_t *vol;
+    int n[3];
+    double v;
+    double corner[3];
+};
+
+__device__ __forceinline__ double plane_at(double corner, int i, double v) {
+    return corner + (double)i * v;
+}
+
+__device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q[3], const double dl[3],
+                                             const double *__restrict__ mu_row) {
+    double inv[3];
+    double a_in = 0.0, a_out = kInf;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double lo_p = g.corner[i];
+        double hi_p = g.corner[i] + (double)g.n[i] * g.v;
+        if (dl[i] == 0.0) {
+            inv[i] = 0.0;
+            if (!(q[i] > lo_p && q[i] < hi_p)) return 0.0;
+        } else {
+            inv[i] = 1.0 / dl[i];
+            double a0 = (lo_p - q[i]) * inv[i], a1 = (hi_p - q[i]) * inv[i];
+            double lo = a0 < a1 ? a0 : a1, hi = a0 < a1 ? a1 : a0;
+            if (lo > a_in) a_in = lo;
+            if (hi < a_out) a_out = hi;
+        }
+    }
+    if (!(a_out > a_in)) return 0.0;
+
+    // per axis: voxel index, step, next plane index and its crossing
+    int idx[3], step[3], nxt[3];
+    double an[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int n = g.n[i];
+        if (dl[i] == 0.0) {
+            double f = floor((q[i] - g.corner[i]) / g.v);
+            int k = (int)fmin(fmax(f, 0.0), (double)(n - 1));
+            idx[i] = k;
+            step[i] = 0;
+            nxt[i] = 0;
+            an[i] = kInf;
+            continue;
+        }
+        double x_in = q[i] + a_in * dl[i];
+        double f = (x_in - g.corner[i]) / g.v;
+        if (dl[i] > 0.0) {
+            // first plane p in [1, n] with alpha(p) > a_in
+            int p = (int)fmin(fmax(floor(f) + 1.0, 1.0), (double)n);
+            if (p > 1 && (plane_at(g.corner[i], p - 1, g.v) - q[i]) * inv[i] > a_in) p -= 1;
+            if (p < n && !((plane_at(g.corner[i], p, g.v) - q[i]) * inv[i] > a_in)) p += 1;
+            idx[i] = p - 1;
+            step[i] = 1;
+            nxt[i] = p;
+        } else {
+            // last plane p in [0, n-1] with alpha(p) > a_in (planes visited downwards)
+            int p = (int)fmin(fmax(ceil(f) - 1.0, 0.0), (double)(n - 1));
+            if (p < n - 1 && (plane_at(g.corner[i], p + 1, g.v) - q[i]) * inv[i] > a_in) p += 1;
+            if (p > 0 && !((plane_at(g.corner[i], p, g.v) - q[i]) * inv[i] > a_in)) p -= 1;
+            idx[i] = p;
+            step[i] = -1;
+            nxt[i] = p;
+        }
+        an[i] = (plane_at(g.corner[i], nxt[i], g.v) - q[i]) * inv[i];
+    }
+
+    const int nx = g.n[0], nxy = g.n[0] * g.n[1];
+    const uint32_t nvox_m1 = (uint32_t)(nxy * g.n[2] - 1);
+    int off = idx[0] + nx * idx[1] + nxy * idx[2];
+    const int doff[3] = {step[0], step[1] * nx, step[2] * nxy};
+    double tau = 0.0, acur = a_in;
+    const int max_visits = g.n[0] + g.n[1] + g.n[2] + 3;
+    for (int it = 0; it < max_visits; ++it) {
+        double amin = fmin(an[0], fmin(an[1], an[2]));
+        double aend = fmin(amin, a_out);
+        double len = aend - acur;
+        if (len > 0.0) {
+            uint32_t o = (uint32_t)off;
+            o = o < nvox_m1 ? o : nvox_m1;
+            tau = fma(mu_row[g.vol[o]], len, tau);
+        }
+        acur = aend;
+        if (amin >= a_out) break;
+        int ax = (an[0] == amin) ? 0 : ((an[1] == amin) ? 1 : 2);
+        // step the chosen axis
+        if (ax == 0) {
+            off += doff[0];
+            nxt[0] += step[0];
+            an[0] = (nxt[0] < 0 || nxt[0] > g.n[0]) ? kInf : (plane_at(g.corner[0], nxt[0], g.v) - q[0]) * inv[0];
+        } else if (ax == 1) {
+            off += doff[1];
+            nxt[1] += step[1];
+            an[1] = (nxt[1] < 0 || nxt[1] > g.n[1]) ? kInf : (plane_at(g.corner[1], nxt[1], g.v) - q[1]) * inv[1];
+        } else {
+            off += doff[2];
+            nxt[2] += step[2];
+            an[2] = (nxt[2] < 0 || nxt[2] > g.n[2]) ? kInf : (plane_at(g.corner[2], nxt[2], g.v) - q[2]) * inv[2];
+        }
+    }
+    return tau;
+}
+
+// ------------------------------------------------------------- mirror ----
+__device__ __forceinline__ bool comp_mirror(const DevComp &c, Ray &ray) {
+    // aux: 0 Cy, 1 Cz, 2 uy, 3 uz, 4 vy, 5 vz, 6 1/a^2, 7 1/b^2,
+    //      8 sin t0, 9 cos t0, 10 length/2, 11 width/2, 12 node step
+    double q[3], dl[3];
+    to_local(c, ray, q, dl);
+    const double Cy = c.aux[0], Cz = c.aux[1], uy = c.aux[2], uz = c.aux[3], vy = c.aux[4], vz = c.aux[5];
+    const double ia2 = c.aux[6], ib2 = c.aux[7];
+    double gy = q[1] - Cy, gz = q[2] - Cz;
+    double s0 = gy * uy + gz * uz, n0 = gy * vy + gz * vz;
+    double ds = dl[1] * uy + dl[2] * uz, dn = dl[1] * vy + dl[2] * vz;
+    double A = ds * ds * ia2 + dn * dn * ib2;
+    double B = 2.0 * (s0 * ds * ia2 + n0 * dn * ib2);
+    double C = s0 * s0 * ia2 + n0 * n0 * ib2 - 1.0;
+    double disc = B * B - 4.0 * A * C;
+    if (!(disc >= 0.0)) return false;
+    double t = (-B + sqrt(disc)) / (2.0 * A);
+    if (!(t > 0.0)) return false;
+    double X[3] = {q[0] + t * dl[0], q[1] + t * dl[1], q[2] + t * dl[2]};
+    double along = X[1] * c.aux[8] + X[2] * c.aux[9];
+    if (!(fabs(X[0]) <= c.aux[11] && fabs(along) <= c.aux[10])) return false;
+    double hy = X[1] - Cy, hz = X[2] - Cz;
+    double hs = (hy * uy + hz * uz) * ia2, hn = (hy * vy + hz * vz) * ib2;
+    double N1 = hs * uy + hn * vy, N2 = hs * uz + hn * vz;
+    double nn = sqrt(0.0 * 0.0 + N1 * N1 + N2 * N2);
+    N1 = N1 / nn;
+    N2 = N2 / nn;
+    double dd = dl[0] * 0.0 + dl[1] * N1 + dl[2] * N2;
+    if (dd > 0.0) {
+        N1 = -N1;
+        N2 = -N2;
+        dd = -dd;
+    }
+    double theta = asin(-dd);
+    const double *tab = (const double *)c.data0;
+    const int64_t nt = (int64_t)c.n0;
+    double R = 0.0;
+    double uu = theta / c.aux[12];
+    if (uu <= (double)(nt - 1)) {
+        int64_t k = (int64_t)floor(uu);
+        if (k > nt - 2) k = nt - 2;
+        double f = uu - (double)k;
+        R = tab[k] * (1.0 - f) + tab[k + 1] * f;
+    }
+    double out[3] = {dl[0] - 2.0 * dd * 0.0, dl[1] - 2.0 * dd * N1, dl[2] - 2.0 * dd * N2};
+    ray.w = ray.w * R;
+    to_lab(c, X, out, ray);
+    return true;
+}
+
+// --------------------------------------------------------- crystals ----
+__device__ __forceinline__ double darwin(double x) {
+    double ax = fabs(x);
+    if (ax <= 1.0) return 1.0;
+    double den = ax + sqrt(ax * ax - 1.0);
+    return 1.0 / (den * den);
+}
+
+__device__ __forceinline__ bool bragg(double q[3], double dl[3], const double P[3], const double N[3],
+                                      double two_d, double half_w, double E, double &R) {
+    double dn = dl[0] * N[0] + dl[1] * N[1] + dl[2] * N[2];
+    if (!(dn < 0.0)) return false;
+    double rel0 = q[0] - P[0], rel1 = q[1] - P[1], rel2 = q[2] - P[2];
+    double t = -(rel0 * N[0] + rel1 * N[1] + rel2 * N[2]) / dn;
+    if (!(t >= 0.0)) return false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) q[i] = q[i] + t * dl[i];
+    double th_in = asin(-dn);
+    double th_b = asin(kHc / (two_d * E));
+    R = darwin((th_in - th_b) / half_w);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dl[i] = dl[i] - 2.0 * dn * N[i];
+    return true;
+}
+
+__device__ __forceinline__ bool comp_dcm(const DevComp &c, Ray &ray) {
+    // aux: 0..2 n1, 3..5 n2 = -n1, 6..8 crystal-2 point, 9 2d, 10 width/2
+    double q[3], dl[3], R1, R2;
+    to_local(c, ray, q, dl);
+    const double P1[3] = {0.0, 0.0, 0.0};
+    if (!bragg(q, dl, P1, c.aux + 0, c.aux[9], c.aux[10], ray.E, R1)) return false;
+    if (!bragg(q, dl, c.aux + 6, c.aux + 3, c.aux[9], c.aux[10], ray.E, R2)) return false;
+    ray.w = ray.w * R1;
+    ray.w = ray.w * R2;
+    to_lab(c, q, dl, ray);
+    return true;
+}
+
+// ------------------------------------------------------------- powder ----
+__device__ __forceinline__ bool comp_powder(const DevComp &c, Stream &s, Ray &ray) {
+    double q[3], dl[3];
+    to_local(c, ray, q, dl);
+    if (!plane_z0(q, dl)) return false;
+    if (!(fabs(q[0]) <= c.aux[0] && fabs(q[1]) <= c.aux[1])) return false;
+    const double *dsp = (const double *)c.data0;
+    const int64_t nd = (int64_t)c.n0;
+    int64_t j = (int64_t)floor((double)nd * s.u((int)c.draw0));
+    if (j > nd - 1) j = nd - 1;
+    double lambda = kHc / ray.E;
+    double sarg = lambda / (2.0 * dsp[j]);
+    if (!(sarg <= 1.0)) return false;
+    double tth = 2.0 * asin(sarg);
+    double eta = kTwoPi * s.u((int)c.draw0 + 1);
+    double e1x = -dl[2], e1z = dl[0];
+    double n1 = sqrt(e1x * e1x + 0.0 * 0.0 + e1z * e1z);
+    e1x = e1x / n1;
+    e1z = e1z / n1;
+    const double e1y = 0.0;
+    double e2x = dl[1] * e1z - dl[2] * e1y;
+    double e2y = dl[2] * e1x - dl[0] * e1z;
+    double e2z = dl[0] * e1y - dl[1] * e1x;
+    double st, ct, se, ce;
+    sincos(tth, &st, &ct);
+    sincos(eta, &se, &ce);
+    double out[3] = {ct * dl[0] + st * (ce * e1x + se * e2x), ct * dl[1] + st * (ce * e1y + se * e2y),
+                     ct * dl[2] + st * (ce * e1z + se * e2z)};
+    to_lab(c, q, out, ray);
+    return true;
+}
+
+// ----------------------------------------------------------- monitors ----
+__device__ __forceinline__ int64_t bin_of(double x, double lo, double scale, uint32_t n) {
+    double f = floor((x - lo) * scale);
+    if (!(f >= 0.0 && f < (double)n)) return -1;
+    return (int64_t)f;
+}
+
+// returns false if the ray cannot reach the plane; bin = -1 outside
+__device__ __forceinline__ bool comp_detector(const DevComp &c, Ray &ray, int64_t &bin) {
+    // aux: 0 nx/(xmax-xmin), 1 ny/(ymax-ymin), 2 ne/(emax-emin)
+    double q[3], dl[3];
+    to_local(c, ray, q, dl);
+    if (!plane_z0(q, dl)) return false;
+    double ev = (c.flags & 1u) ? kHc / ray.E : ray.E;
+    int64_t ix = bin_of(q[0], c.par[0], c.aux[0], c.dims[0]);
+    int64_t iy = bin_of(q[1], c.par[2], c.aux[1], c.dims[1]);
+    int64_t ie = bin_of(ev, c.par[4], c.aux[2], c.dims[2]);
+    bin = (ix >= 0 && iy >= 0 && ie >= 0) ? (iy * (int64_t)c.dims[0] + ix) * (int64_t)c.dims[2] + ie : -1;
+    to_lab(c, q, dl, ray);
+    return true;
+}
+
+}  // namespace mxr

@@ -1,0 +1,257 @@
+"""Parity of the HIP library with the CPU oracle, through the C ABI.
+
+Per ray (mxr_trace_rays vs the oracle's per-ray trace, the same Philox
+streams): identical status, absorbing component and tally bin; position,
+direction, energy and weight within 1e-12 relative (floors: 1 mm, 1, 1 keV,
+1).  Per bin (mxr_run vs the oracle's run): identical counts; sums of w and
+w^2 within 1e-9 relative, zero bins zero on both sides -- every summand is
+non-negative, so atomic reordering moves a sum by at most (n - 1) 2^-53.
+
+The full-size projection (256^3 phantom, 256 x 64 x 128 detector, 1e9 rays)
+is checked on sampled rays and on sampled ray ranges of the 1e9-ray run, in
+the launch configuration the benchmark times.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+REL_RAY = 1e-12
+REL_BIN = 1e-9
+
+
+def mxr():
+    import paper_2410_08747_amd as m
+    return m
+
+
+def announce(*what):
+    print("[gpu case]", *what, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def cpu(t):
+    return t.detach().cpu().numpy()
+
+
+def compare_rays(gpu, ora, label, w_rel=None):
+    st_g, st_o = cpu(gpu["status"]), ora["status"]
+    assert np.array_equal(st_g, st_o), f"{label}: status differs for {np.sum(st_g != st_o)} rays"
+    assert np.array_equal(cpu(gpu["dead_at"]), ora["dead_at"]), f"{label}: dead_at differs"
+    assert np.array_equal(cpu(gpu["bin"]), ora["bin"]), f"{label}: bin differs"
+    pairs = [("x", ora["r"][:, 0], 1.0), ("y", ora["r"][:, 1], 1.0), ("z", ora["r"][:, 2], 1.0),
+             ("dx", ora["d"][:, 0], 1.0), ("dy", ora["d"][:, 1], 1.0), ("dz", ora["d"][:, 2], 1.0),
+             ("E", ora["E"], 1.0), ("w", ora["w"], 1.0)]
+    for name, ref, floor in pairs:
+        got = cpu(gpu[name])
+        err = np.abs(got - ref) / np.maximum(np.abs(ref), floor)
+        tol = REL_RAY if (name != "w" or w_rel is None) else w_rel
+        bad = err > tol
+        i = int(np.argmax(err - tol))
+        assert not bad.any(), f"{label}: {name} ray {i}: gpu {got[i]!r} oracle {ref[i]!r} rel {err[i]:.3e}"
+
+
+def darwin_weight_tolerance(ins, ids, seed, n_total):
+    """Per-ray weight tolerance through the two-crystal monochromator.
+
+    The Darwin reflectivity R(x) = (|x| + sqrt(x^2 - 1))^-2 has
+    d ln R / dx = -2 / sqrt(x^2 - 1) beyond the plateau, unbounded at its
+    edge.  The CPU and GPU math libraries differ by an ulp or two in the
+    sin/cos/tan/asin that produce the incidence angle, i.e. by up to
+    ~5e-16 rad (18 ulp of the 0.16 rad Bragg angle); through two bounces that
+    moves ln w by 2 * 2 / sqrt(x^2 - 1) * 5e-16 / (width / 2).  Rays within
+    1e-6 of the plateau edge are near-ties and skipped (None); the incidence
+    angle comes from an oracle trace of the instrument cut after the
+    monochromator (same random streams up to there).
+    """
+    comps = ins["components"]
+    k = [c["type"] for c in comps].index("dcm")
+    dcm = comps[k]
+    cut = oracle.trace_rays({"components": comps[:k + 1]}, ids, seed=seed, n_total=n_total)
+    d_loc = cut["d"] @ np.asarray(dcm["rot"]).T
+    n1 = np.array([0.0, math.cos(dcm["theta_c"]), -math.sin(dcm["theta_c"])])
+    theta_in = np.arcsin(np.clip(-(d_loc @ n1), -1, 1))
+    theta_b = np.arcsin(12.398419843320026 / (2 * dcm["d_spacing"] * cut["E"]))
+    x = np.abs((theta_in - theta_b) / (0.5 * dcm["darwin_width"]))
+    dx = 5e-16 / (0.5 * dcm["darwin_width"])
+    slope = np.where(x > 1 + 1e-6, 2.0 / np.sqrt(np.maximum(x * x - 1, 1e-300)), 0.0)
+    tol = REL_RAY + 2 * slope * dx
+    near_tie = np.abs(x - 1) <= 1e-6
+    tol[near_tie] = np.inf
+    return tol, int(near_tie.sum())
+
+
+def compare_bins(gpu_tally, ora_tally, label):
+    cg = cpu(gpu_tally["count"]).astype(np.uint64)
+    assert np.array_equal(cg, ora_tally["count"]), f"{label}: counts differ in {np.sum(cg != ora_tally['count'])} bins"
+    for key in ("sum_w", "sum_w2"):
+        g, o = cpu(gpu_tally[key]), ora_tally[key]
+        assert np.array_equal(g == 0, o == 0), f"{label}: {key} zero pattern differs"
+        nz = o != 0
+        if nz.any():
+            err = np.abs(g[nz] - o[nz]) / np.abs(o[nz])
+            assert err.max() <= REL_BIN, f"{label}: {key} max rel err {err.max():.3e}"
+
+
+@pytest.fixture(scope="module")
+def small_edct():
+    vol = workloads.make_phantom(64, seed=1)
+    mu = workloads.make_mu_tables(1)
+    return workloads.edct_projection(vol, mu, angle=0.4, strata=64)
+
+
+@pytest.fixture(scope="module")
+def full_edct():
+    vol = workloads.make_phantom(256, seed=1)
+    mu = workloads.make_mu_tables(1)
+    return workloads.edct_projection(vol, mu, angle=0.0, strata=1024)
+
+
+def instruments(small_edct):
+    return {
+        "basic_absorber": workloads.basic_absorber(),
+        "edct_64": small_edct,
+        "beamline": workloads.beamline(),
+    }
+
+
+@pytest.mark.parametrize("name", ["basic_absorber", "edct_64", "beamline"])
+def test_per_ray_parity(torch_cuda, small_edct, name):
+    ins = instruments(small_edct)[name]
+    n = 100003  # ragged: not a multiple of the work-group or XCD count
+    ids = np.arange(n, dtype=np.uint64)
+    announce("per-ray", name, "n", n, "seed 7")
+    g = mxr().Instrument(ins).trace_rays(ids, seed=7, n_total=n)
+    torch_cuda.cuda.synchronize()
+    o = oracle.trace_rays(ins, ids, seed=7, n_total=n)
+    w_rel = None
+    if name == "beamline":
+        w_rel, near = darwin_weight_tolerance(ins, ids, 7, n)
+        print(f"beamline: {near} near-tie rays at the Darwin plateau edge", flush=True)
+        assert near < 10
+    compare_rays(g, o, name, w_rel)
+
+
+@pytest.mark.parametrize("name,n", [("basic_absorber", 1000000), ("edct_64", 300001), ("beamline", 1000000)])
+def test_per_bin_parity(torch_cuda, small_edct, name, n):
+    ins = instruments(small_edct)[name]
+    announce("per-bin", name, "n", n, "seed 1")
+    I = mxr().Instrument(ins)
+    led = I.new_ledger()
+    t = I.run(n, seed=1, ledger=led)
+    torch_cuda.cuda.synchronize()
+    o, oled = oracle.run(ins, n, seed=1, ledger=True)
+    for k, (gt, ot) in enumerate(zip(t, o)):
+        compare_bins(gt, ot, f"{name} monitor {k}")
+    gl = cpu(led)
+    nz = oled != 0
+    assert np.array_equal(gl == 0, oled == 0)
+    assert np.max(np.abs(gl[nz] - oled[nz]) / np.abs(oled[nz])) <= REL_BIN
+    K = len(ins["components"])
+    lost = sum(gl[4 * k + 1] + gl[4 * k + 2] for k in range(K))
+    assert abs(gl[0] - (lost + gl[4 * K])) <= 1e-12 * gl[0]
+
+
+def test_full_size_sampled_rays(torch_cuda, full_edct):
+    """Rays sampled across a 1e9-ray run of the 256^3 projection."""
+    n_total = 10**9
+    rng = np.random.default_rng(3)
+    ids = np.unique(np.concatenate([rng.integers(0, n_total, 20000), np.arange(0, 64), np.arange(n_total - 64, n_total)]))
+    announce("full-size sampled rays", "n_total", n_total, "samples", ids.size)
+    g = mxr().Instrument(full_edct).trace_rays(ids.astype(np.uint64), seed=1, n_total=n_total)
+    torch_cuda.cuda.synchronize()
+    o = oracle.trace_rays(full_edct, ids, seed=1, n_total=n_total)
+    compare_rays(g, o, "edct_256 full-size")
+
+
+@pytest.mark.parametrize("first,n", [(0, 200000), (499_999_937, 150001), (10**9 - 100000, 100000)])
+def test_full_size_sampled_ranges(torch_cuda, full_edct, first, n):
+    """Ray ranges of the 1e9-ray run through the run kernel the benchmark times."""
+    n_total = 10**9
+    announce("full-size range", first, n, "n_total", n_total)
+    I = mxr().Instrument(full_edct)
+    t = I.run(n, seed=1, first_ray=first, n_total=n_total)
+    torch_cuda.cuda.synchronize()
+    o = oracle.run(full_edct, n, seed=1, first=first, n_total=n_total)
+    compare_bins(t[0], o[0], f"edct_256 rays [{first}, {first + n})")
+
+
+def test_chunked_runs_equal_one_run(torch_cuda, small_edct):
+    n = 400000
+    announce("chunking", "n", n)
+    I = mxr().Instrument(small_edct)
+    one = I.run(n, seed=9)
+    parts = I.new_tallies()
+    for a, b in [(0, 1), (1, 150000), (150000, 150000), (150000, 399999), (399999, 400000)]:
+        I.run(b - a, seed=9, first_ray=a, n_total=n, tallies=parts)
+    torch_cuda.cuda.synchronize()
+    assert np.array_equal(cpu(one[0]["count"]), cpu(parts[0]["count"]))
+    g, o = cpu(parts[0]["sum_w"]), cpu(one[0]["sum_w"])
+    nz = o != 0
+    assert np.array_equal(g == 0, o == 0)
+    assert np.max(np.abs(g[nz] - o[nz]) / o[nz]) <= REL_BIN
+
+
+def test_edge_cases(torch_cuda, small_edct):
+    m = mxr()
+    I = m.Instrument(small_edct)
+    announce("edge cases")
+    # empty run: tallies untouched
+    t = I.run(0, seed=1, n_total=10)
+    torch_cuda.cuda.synchronize()
+    assert int(t[0]["count"].sum()) == 0
+    # one ray, and n_total below the strata count (G reduced to 1)
+    for n_total in (1, 2, 5, 4095):
+        g = I.trace_rays(np.array([n_total - 1], np.uint64), seed=2, n_total=n_total)
+        torch_cuda.cuda.synchronize()
+        o = oracle.trace_rays(small_edct, [n_total - 1], seed=2, n_total=n_total)
+        compare_rays(g, o, f"single ray n_total={n_total}")
+    # ids in any order
+    ids = np.array([5, 3, 99999, 0, 7], np.uint64)
+    g = I.trace_rays(ids, seed=3, n_total=100000)
+    torch_cuda.cuda.synchronize()
+    compare_rays(g, oracle.trace_rays(small_edct, ids, seed=3, n_total=100000), "unordered ids")
+    # purpose and job select other streams
+    g = I.trace_rays(np.arange(1000, dtype=np.uint64), seed=3, n_total=1000, purpose=2, job=77)
+    torch_cuda.cuda.synchronize()
+    compare_rays(g, oracle.trace_rays(small_edct, np.arange(1000), seed=3, n_total=1000, purpose=2, job=77), "purpose/job")
+
+
+def test_errors(torch_cuda, small_edct):
+    m = mxr()
+    announce("error paths")
+    I = m.Instrument(small_edct)
+    tallies = I.new_tallies()
+    with pytest.raises(m.MxrError):
+        I.run(10, seed=1, first_ray=5, n_total=12, tallies=tallies)  # range beyond n_total
+    with pytest.raises(m.MxrError):
+        m.mxr_run(I.handle, 0, 10, 10, 1, 0, 0, [])  # wrong tally count
+    bad = I.tally_structs(tallies)
+    bad[0].n_bins -= 1
+    with pytest.raises(m.MxrError):
+        m.mxr_run(I.handle, 0, 10, 10, 1, 0, 0, bad)
+    with pytest.raises(m.MxrError):
+        I.run(10, seed=1, purpose=300)
+    # material ids beyond the table, detector without a source, NaN parameters
+    vol = np.full((4, 4, 4), 9, np.uint8)
+    ins = workloads.edct_projection(vol, workloads.make_mu_tables(1))
+    with pytest.raises(m.MxrError):
+        m.Instrument(ins)
+    with pytest.raises(m.MxrError):
+        m.Instrument({"components": [workloads.basic_absorber()["components"][3]]})
+    b = workloads.basic_absorber()
+    b["components"][2]["mu_a"] = float("nan")
+    with pytest.raises(m.MxrError):
+        m.Instrument(b)
+    assert "non-finite" in m.mxr_last_error()
