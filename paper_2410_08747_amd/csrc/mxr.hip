@@ -78,6 +78,8 @@ __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream 
             g.corner[0] = c.aux[0];
             g.corner[1] = c.aux[1];
             g.corner[2] = c.aux[2];
+            g.nvox = (uint32_t)c.n0;
+            g.exact_steps = c.aux[4] != 0.0;
             double f = floor((ray.E - c.par[1]) * c.aux[3]);
             int e = (int)fmin(fmax(f, 0.0), (double)(n_ebin - 1));
             double tau = siddon_tau(g, q, dl, mu_lds + e * n_mat);
@@ -166,10 +168,20 @@ __device__ __forceinline__ bool run_chain(Chain<Ts...>, const DevInstr *ins, Ray
     }
 }
 
+// The instrument block is read-only for the whole launch; passing it as its
+// own restrict-qualified argument lets its wave-uniform fields be read with
+// scalar loads even though the kernel stores to the histograms.
+//
+// One lane traces exactly one ray.  (A loop over several rays per lane lets
+// the compiler hoist every loop-invariant constant -- the polynomial
+// coefficients of exp, sin, cos -- into registers for the whole kernel, which
+// costs occupancy.)  Work-groups are dealt to the eight XCDs round-robin, so
+// work-group b is remapped to the b/8-th slot of the (b mod 8)-th eighth of
+// the ray range: each XCD traces a contiguous block of ray ids, which the
+// stratified source sends through neighbouring voxels and pixels.
 template <class C, bool LEDGER, bool TRACE>
-__global__ __launch_bounds__(kBlock) void k_trace(RunArgs a) {
+__global__ __launch_bounds__(kBlock) void k_trace(const DevInstr *__restrict__ ins, RunArgs a) {
     extern __shared__ double smem[];
-    const DevInstr *ins = a.ins;
     const uint32_t n_mat = ins->n_mat, n_ebin = ins->n_ebin;
     double *mu_lds = smem;
     const uint32_t n_mu = (ins->phantom >= 0) ? n_mat * n_ebin : 0u;
@@ -178,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(RunArgs a) {
         const double *T = (const double *)ins->c[ins->phantom].data1;
         for (uint32_t i = threadIdx.x; i < n_mu; i += kBlock) {
             uint32_t m = i / n_ebin, e = i - m * n_ebin;
-            mu_lds[e * n_mat + m] = T[i] / 10.0;
+            mu_lds[e * n_mat + m] = T[i] * 0.1;
         }
     }
     LedgerLds L{nullptr};
@@ -189,12 +201,9 @@ __global__ __launch_bounds__(kBlock) void k_trace(RunArgs a) {
     }
     __syncthreads();
 
-    const uint32_t xcd = blockIdx.x & 7u, lb = blockIdx.x >> 3;
-    const uint64_t chunk = (a.n + 7) / 8;
-    const uint64_t lo = (uint64_t)xcd * chunk;
-    const uint64_t hi = lo + chunk < a.n ? lo + chunk : a.n;
-    const uint64_t stride = (uint64_t)a.blocks_per_xcd * kBlock;
-    for (uint64_t i = lo + (uint64_t)lb * kBlock + threadIdx.x; i < hi; i += stride) {
+    const uint64_t logical = (uint64_t)(blockIdx.x & 7u) * a.blocks_per_xcd + (blockIdx.x >> 3);
+    const uint64_t i = logical * kBlock + threadIdx.x;
+    if (i < a.n) {
         const uint64_t ray_id = TRACE ? a.ids[i] : a.first + i;
         Stream s;
         s.init(a.seed, ray_id, a.word3);
@@ -225,9 +234,9 @@ __global__ __launch_bounds__(kBlock) void k_trace(RunArgs a) {
     }
     if constexpr (LEDGER) {
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < n_slots; i += kBlock) {
-            double v = L.slots[i];
-            if (v != 0.0) atomicAdd(a.ledger + i, v);
+        for (uint32_t k = threadIdx.x; k < n_slots; k += kBlock) {
+            double v = L.slots[k];
+            if (v != 0.0) atomicAdd(a.ledger + k, v);
         }
     }
 }
@@ -256,7 +265,7 @@ using ChainBeamline = Chain<MXR_SRC_GAUSSIAN, MXR_MIRROR_ELLIPTIC, MXR_DCM, MXR_
 
 enum Recipe { kRecipeGeneric = 0, kRecipeBasic, kRecipeEdct, kRecipeBeamline, kNumRecipes };
 
-typedef void (*KernelFn)(RunArgs);
+typedef void (*KernelFn)(const DevInstr *, RunArgs);
 
 template <class C>
 struct KernelSet {
@@ -402,6 +411,19 @@ static mxr_status derive(const mxr_component_desc &s, DevComp &c, int k, uint32_
             n_ebin = (uint32_t)(s.data_len[1] / s.dims[3]);
             for (int i = 0; i < 3; ++i) c.aux[i] = -0.5 * ((double)s.dims[i] * p[0]);
             c.aux[3] = (double)n_ebin / (p[2] - p[1]);
+            // can the walk step planes by adding v and stay exact?
+            bool exact = true;
+            for (int i = 0; i < 3 && exact; ++i) {
+                double P = c.aux[i];
+                for (uint32_t k = 1; k <= s.dims[i]; ++k) {
+                    P = P + p[0];
+                    if (P != c.aux[i] + (double)k * p[0]) {
+                        exact = false;
+                        break;
+                    }
+                }
+            }
+            c.aux[4] = exact ? 1.0 : 0.0;
             break;
         }
         case MXR_MIRROR_ELLIPTIC: {
@@ -574,21 +596,41 @@ void mxr_instrument_destroy(mxr_instrument *ins) {
 
 static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, bool ledger, bool trace,
                          hipStream_t stream) {
-    RunArgs a = base;
-    // work-groups: enough to cover n with one ray per lane, capped at a few
-    // waves of resident work-groups per CU; a multiple of the 8 XCDs
-    uint64_t want = (n + kBlock - 1) / kBlock;
-    uint64_t cap = 256ull * 8 * 4;
-    uint64_t blocks = std::min(want, cap);
-    blocks = std::max<uint64_t>(8, (blocks + 7) / 8 * 8);
-    a.blocks_per_xcd = (uint32_t)(blocks / 8);
+    KernelFn k = pick_kernel(ins->recipe, ledger, trace);
     size_t shmem = 0;
     if (ins->host.phantom >= 0) shmem += (size_t)ins->host.n_mat * ins->host.n_ebin * sizeof(double);
     if (ledger) shmem += (size_t)(4 * ins->host.ncomp + 1) * sizeof(double);
-    KernelFn k = pick_kernel(ins->recipe, ledger, trace);
-    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kBlock), shmem, stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    // one lane per ray; launches of at most 2^30 work-groups (a multiple of
+    // the 8 XCDs), so ray ranges beyond that are split into several launches
+    const uint64_t max_rays = (1ull << 30) * kBlock;
+    for (uint64_t done = 0; done < n;) {
+        const uint64_t m = std::min(n - done, max_rays);
+        RunArgs a = base;
+        a.n = m;
+        if (trace) {
+            a.ids = base.ids + done;
+            a.dump.x = base.dump.x + done;
+            a.dump.y = base.dump.y + done;
+            a.dump.z = base.dump.z + done;
+            a.dump.dx = base.dump.dx + done;
+            a.dump.dy = base.dump.dy + done;
+            a.dump.dz = base.dump.dz + done;
+            a.dump.E = base.dump.E + done;
+            a.dump.w = base.dump.w + done;
+            a.dump.status = base.dump.status + done;
+            a.dump.dead_at = base.dump.dead_at + done;
+            a.dump.bin = base.dump.bin + done;
+        } else {
+            a.first = base.first + done;
+        }
+        const uint64_t groups = (m + kBlock - 1) / kBlock;
+        a.blocks_per_xcd = (uint32_t)((groups + 7) / 8);
+        const uint64_t blocks = (uint64_t)a.blocks_per_xcd * 8;
+        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kBlock), shmem, stream, (const DevInstr *)ins->dev, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        done += m;
+    }
     return MXR_OK;
 }
 

@@ -286,23 +286,120 @@ __device__ __forceinline__ void comp_box(const DevComp &c, Ray &ray) {
 }
 
 // ------------------------------------------------------------ phantom ----
-// Exact radiological path through the voxel grid as an incremental 3-D
-// traversal (Amanatides & Woo 1987; Jacobs et al. 1998): the next crossing
-// of each axis is kept, the nearest one is taken, the voxel index steps by
-// one.  Every crossing parameter is computed from its plane index,
-// alpha = (corner + i v - q) / d with the reciprocal precomputed, never
-// accumulated, so it is the same number whichever order the planes are
-// visited in.  mu_tab points to the ray's energy row (mu / 10, per mm)
-// staged in LDS; the loop is bounded by nx + ny + nz + 3 visits.
+// Exact radiological path through the voxel grid.
+//
+// The ray is walked along its dominant axis D (largest |d|): every step
+// crosses one D plane; with cubic voxels and |d_A|, |d_B| <= |d_D| at most
+// one plane of each other axis lies between two D planes, so those rarer
+// crossings are taken in a branch that coherent waves mostly skip.  Every
+// crossing parameter is alpha = (plane - q) / d with the reciprocal
+// precomputed and the plane coordinate exact, so it is the same number in
+// whatever order the planes are visited (negative directions are mirrored so
+// every axis steps by +v).  The optical depth is accumulated per material
+// run: segment lengths between crossings telescope, so a run of voxels of
+// one material adds mu * (alpha_end - alpha_start) -- the same sum of
+// mu * length as segment by segment, up to rounding -- and the mu table is
+// read only where the material changes.  Voxels are read with buffer loads
+// (hardware range check: an out-of-range offset reads 0 instead of
+// faulting).  The walk is bounded by nx + ny + nz + 3 steps.
 struct PhantomGeo {
     const uint8_t *vol;
+    uint32_t nvox;
     int n[3];
     double v;
     double corner[3];
+    bool exact_steps;  // corner + i v is reached exactly by adding v
 };
 
-__device__ __forceinline__ double plane_at(double corner, int i, double v) {
-    return corner + (double)i * v;
+__device__ __forceinline__ uint32_t load_voxel(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0);
+}
+
+template <class T>
+__device__ __forceinline__ T pick3(int k, T a0, T a1, T a2) {
+    return k == 0 ? a0 : (k == 1 ? a1 : a2);
+}
+
+// Per-axis walk state, one entry per axis; roles D, A, B pick from it with
+// selects (registers cannot be indexed by a per-lane value).
+struct AxisSet {
+    double P[3], q[3], inv[3];
+    int k[3], doff[3];
+};
+
+template <bool EXACT>
+__device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet &S, int D, int A, int B,
+                                              uint32_t off, double a_in, double a_out,
+                                              const double *__restrict__ mu_row) {
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)g.vol, (short)0, (int)g.nvox, 0x00020000);
+    const double v = g.v;
+    // per-role state (D, A, B): next plane coordinate (mirrored), its alpha
+    double PD = pick3(D, S.P[0], S.P[1], S.P[2]), PA = pick3(A, S.P[0], S.P[1], S.P[2]);
+    double PB = pick3(B, S.P[0], S.P[1], S.P[2]);
+    const double qD = pick3(D, S.q[0], S.q[1], S.q[2]), qA = pick3(A, S.q[0], S.q[1], S.q[2]);
+    const double qB = pick3(B, S.q[0], S.q[1], S.q[2]);
+    const double iD = pick3(D, S.inv[0], S.inv[1], S.inv[2]), iA = pick3(A, S.inv[0], S.inv[1], S.inv[2]);
+    const double iB = pick3(B, S.inv[0], S.inv[1], S.inv[2]);
+    int kD = pick3(D, S.k[0], S.k[1], S.k[2]), kA = pick3(A, S.k[0], S.k[1], S.k[2]);
+    int kB = pick3(B, S.k[0], S.k[1], S.k[2]);
+    const int oD = pick3(D, S.doff[0], S.doff[1], S.doff[2]), oA = pick3(A, S.doff[0], S.doff[1], S.doff[2]);
+    const int oB = pick3(B, S.doff[0], S.doff[1], S.doff[2]);
+    // mirrored corners: plane k of a mirrored axis sits at -corner + k v
+    const double gD = pick3(D, g.corner[0], g.corner[1], g.corner[2]);
+    const double gA = pick3(A, g.corner[0], g.corner[1], g.corner[2]);
+    const double gB = pick3(B, g.corner[0], g.corner[1], g.corner[2]);
+    const double cD = iD < 0.0 ? -gD : gD, cA = iA < 0.0 ? -gA : gA, cB = iB < 0.0 ? -gB : gB;
+    double aD = (PD - qD) * iD;
+    double aA = (iA == 0.0) ? kInf : (PA - qA) * iA;
+    double aB = (iB == 0.0) ? kInf : (PB - qB) * iB;
+
+    uint32_t run_m = load_voxel(rs, off);
+    double a_start = a_in, tau = 0.0;
+    const int max_steps = g.n[0] + g.n[1] + g.n[2] + 3;
+    for (int it = 0; it < max_steps; ++it) {
+        if (aA < aD || aB < aD) {
+            // crossings of the other axes before the next D plane, in order
+            for (int r = 0; r < 3; ++r) {
+                const double lim = aD < a_out ? aD : a_out;
+                const bool takeA = (aA < lim) && (aA <= aB);
+                const bool takeB = !takeA && (aB < lim);
+                if (!(takeA || takeB)) break;
+                double t;
+                if (takeA) {
+                    t = aA;
+                    off += oA;
+                    kA += 1;
+                    PA = EXACT ? PA + v : cA + (double)kA * v;
+                    aA = (PA - qA) * iA;
+                } else {
+                    t = aB;
+                    off += oB;
+                    kB += 1;
+                    PB = EXACT ? PB + v : cB + (double)kB * v;
+                    aB = (PB - qB) * iB;
+                }
+                const uint32_t m = load_voxel(rs, off);
+                if (m != run_m) {
+                    tau = fma(mu_row[run_m], t - a_start, tau);
+                    a_start = t;
+                    run_m = m;
+                }
+            }
+        }
+        if (!(aD < a_out)) break;
+        const double t = aD;
+        off += oD;
+        kD += 1;
+        PD = EXACT ? PD + v : cD + (double)kD * v;
+        aD = (PD - qD) * iD;
+        const uint32_t m = load_voxel(rs, off);
+        if (m != run_m) {
+            tau = fma(mu_row[run_m], t - a_start, tau);
+            a_start = t;
+            run_m = m;
+        }
+    }
+    return fma(mu_row[run_m], a_out - a_start, tau);
 }
 
 __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q[3], const double dl[3],
@@ -326,77 +423,65 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
     }
     if (!(a_out > a_in)) return 0.0;
 
-    // per axis: voxel index, step, next plane index and its crossing
-    int idx[3], step[3], nxt[3];
-    double an[3];
+    // Per axis: the voxel holding the start of the path and the first plane
+    // crossed after a_in.  Planes are mirrored for negative directions
+    // (coordinate -x, plane index counted downwards), so that the next plane
+    // is always reached by adding v and alpha = (P - q) * inv keeps its value.
+    int idx[3];
+    AxisSet S;
+    const int nx = g.n[0], nxy = g.n[0] * g.n[1];
+    const int stride[3] = {1, nx, nxy};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const int n = g.n[i];
+        const double c = g.corner[i], v = g.v;
         if (dl[i] == 0.0) {
-            double f = floor((q[i] - g.corner[i]) / g.v);
-            int k = (int)fmin(fmax(f, 0.0), (double)(n - 1));
-            idx[i] = k;
-            step[i] = 0;
-            nxt[i] = 0;
-            an[i] = kInf;
+            double f = floor((q[i] - c) / v);
+            idx[i] = (int)fmin(fmax(f, 0.0), (double)(n - 1));
+            S.k[i] = 0;
+            S.P[i] = 0.0;
+            S.q[i] = q[i];
+            S.inv[i] = 0.0;
+            S.doff[i] = 0;
             continue;
         }
-        double x_in = q[i] + a_in * dl[i];
-        double f = (x_in - g.corner[i]) / g.v;
+        const double x_in = q[i] + a_in * dl[i];
+        const double f = (x_in - c) / v;
+        int p;
         if (dl[i] > 0.0) {
             // first plane p in [1, n] with alpha(p) > a_in
-            int p = (int)fmin(fmax(floor(f) + 1.0, 1.0), (double)n);
-            if (p > 1 && (plane_at(g.corner[i], p - 1, g.v) - q[i]) * inv[i] > a_in) p -= 1;
-            if (p < n && !((plane_at(g.corner[i], p, g.v) - q[i]) * inv[i] > a_in)) p += 1;
+            p = (int)fmin(fmax(floor(f) + 1.0, 1.0), (double)n);
+            if (p > 1 && ((c + (double)(p - 1) * v) - q[i]) * inv[i] > a_in) p -= 1;
+            if (p < n && !(((c + (double)p * v) - q[i]) * inv[i] > a_in)) p += 1;
             idx[i] = p - 1;
-            step[i] = 1;
-            nxt[i] = p;
+            S.k[i] = p;
+            S.P[i] = c + (double)p * v;
+            S.q[i] = q[i];
+            S.inv[i] = inv[i];
+            S.doff[i] = stride[i];
         } else {
-            // last plane p in [0, n-1] with alpha(p) > a_in (planes visited downwards)
-            int p = (int)fmin(fmax(ceil(f) - 1.0, 0.0), (double)(n - 1));
-            if (p < n - 1 && (plane_at(g.corner[i], p + 1, g.v) - q[i]) * inv[i] > a_in) p += 1;
-            if (p > 0 && !((plane_at(g.corner[i], p, g.v) - q[i]) * inv[i] > a_in)) p -= 1;
+            // last plane p in [0, n - 1] with alpha(p) > a_in, walked downwards
+            p = (int)fmin(fmax(ceil(f) - 1.0, 0.0), (double)(n - 1));
+            if (p < n - 1 && ((c + (double)(p + 1) * v) - q[i]) * inv[i] > a_in) p += 1;
+            if (p > 0 && !(((c + (double)p * v) - q[i]) * inv[i] > a_in)) p -= 1;
             idx[i] = p;
-            step[i] = -1;
-            nxt[i] = p;
-        }
-        an[i] = (plane_at(g.corner[i], nxt[i], g.v) - q[i]) * inv[i];
-    }
-
-    const int nx = g.n[0], nxy = g.n[0] * g.n[1];
-    const uint32_t nvox_m1 = (uint32_t)(nxy * g.n[2] - 1);
-    int off = idx[0] + nx * idx[1] + nxy * idx[2];
-    const int doff[3] = {step[0], step[1] * nx, step[2] * nxy};
-    double tau = 0.0, acur = a_in;
-    const int max_visits = g.n[0] + g.n[1] + g.n[2] + 3;
-    for (int it = 0; it < max_visits; ++it) {
-        double amin = fmin(an[0], fmin(an[1], an[2]));
-        double aend = fmin(amin, a_out);
-        double len = aend - acur;
-        if (len > 0.0) {
-            uint32_t o = (uint32_t)off;
-            o = o < nvox_m1 ? o : nvox_m1;
-            tau = fma(mu_row[g.vol[o]], len, tau);
-        }
-        acur = aend;
-        if (amin >= a_out) break;
-        int ax = (an[0] == amin) ? 0 : ((an[1] == amin) ? 1 : 2);
-        // step the chosen axis
-        if (ax == 0) {
-            off += doff[0];
-            nxt[0] += step[0];
-            an[0] = (nxt[0] < 0 || nxt[0] > g.n[0]) ? kInf : (plane_at(g.corner[0], nxt[0], g.v) - q[0]) * inv[0];
-        } else if (ax == 1) {
-            off += doff[1];
-            nxt[1] += step[1];
-            an[1] = (nxt[1] < 0 || nxt[1] > g.n[1]) ? kInf : (plane_at(g.corner[1], nxt[1], g.v) - q[1]) * inv[1];
-        } else {
-            off += doff[2];
-            nxt[2] += step[2];
-            an[2] = (nxt[2] < 0 || nxt[2] > g.n[2]) ? kInf : (plane_at(g.corner[2], nxt[2], g.v) - q[2]) * inv[2];
+            // mirrored: plane index k = -p, coordinate -(c + p v), -q, -inv
+            S.k[i] = -p;
+            S.P[i] = -(c + (double)p * v);
+            S.q[i] = -q[i];
+            S.inv[i] = -inv[i];
+            S.doff[i] = -stride[i];
         }
     }
-    return tau;
+    // dominant axis (largest |d|, lowest index on ties) and the other two
+    const double ax = fabs(dl[0]), ay = fabs(dl[1]), az = fabs(dl[2]);
+    int D, A, B;
+    if (ax >= ay && ax >= az) { D = 0; A = 1; B = 2; }
+    else if (ay >= az) { D = 1; A = 0; B = 2; }
+    else { D = 2; A = 0; B = 1; }
+    const uint32_t off = (uint32_t)(idx[0] + nx * idx[1] + nxy * idx[2]);
+    if (g.exact_steps) return siddon_walk<true>(g, S, D, A, B, off, a_in, a_out, mu_row);
+    return siddon_walk<false>(g, S, D, A, B, off, a_in, a_out, mu_row);
 }
 
 // ------------------------------------------------------------- mirror ----
