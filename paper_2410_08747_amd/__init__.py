@@ -234,11 +234,18 @@ class Instrument:
         with torch.cuda.device(self.device):
             self.handle = mxr_instrument_create(desc)
 
-    def __del__(self):
+    def close(self) -> None:
+        """Free the library handle (also done on garbage collection)."""
         h = getattr(self, "handle", None)
-        if h:
-            mxr_instrument_destroy(h)
-            self.handle = None
+        if h and lib is not None:
+            lib.mxr_instrument_destroy(h)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass  # interpreter shutdown: module globals may already be gone
 
     def new_tallies(self):
         """Zeroed histograms (count, sum_w, sum_w2) for every monitor."""

@@ -49,7 +49,7 @@ __device__ __forceinline__ void ledger_add(const LedgerLds &L, int slot, double 
 }
 
 // Apply component k of type T.  Returns false when the ray is absorbed.
-template <int T, bool LEDGER, bool TRACE>
+template <int T, bool LEDGER, bool TRACE, bool EXACT>
 __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream &s, uint64_t ray_id,
                                       const RunArgs &a, const double *mu_lds, uint32_t n_mat, uint32_t n_ebin,
                                       RayEnd &end, const LedgerLds &L) {
@@ -79,10 +79,9 @@ __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream 
             g.corner[1] = c.aux[1];
             g.corner[2] = c.aux[2];
             g.nvox = (uint32_t)c.n0;
-            g.exact_steps = c.aux[4] != 0.0;
             double f = floor((ray.E - c.par[1]) * c.aux[3]);
             int e = (int)fmin(fmax(f, 0.0), (double)(n_ebin - 1));
-            double tau = siddon_tau(g, q, dl, mu_lds + e * n_mat);
+            double tau = siddon_tau<EXACT>(g, q, dl, mu_lds + e * n_mat);
             ray.w = ray.w * exp(-tau);
         }
         if constexpr (T == MXR_MIRROR_ELLIPTIC) ok = comp_mirror(c, ray);
@@ -114,12 +113,12 @@ __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream 
     }
 }
 
-template <bool LEDGER, bool TRACE>
+template <bool LEDGER, bool TRACE, bool EXACT>
 __device__ __forceinline__ bool apply_dynamic(const DevComp &c, int k, Ray &ray, Stream &s, uint64_t ray_id,
                                               const RunArgs &a, const double *mu_lds, uint32_t n_mat,
                                               uint32_t n_ebin, RayEnd &end, const LedgerLds &L) {
 #define MXR_CASE(T) \
-    case T: return apply<T, LEDGER, TRACE>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
+    case T: return apply<T, LEDGER, TRACE, EXACT>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
     switch (c.type) {
         MXR_CASE(MXR_SRC_RECT_CONE)
         MXR_CASE(MXR_SRC_CONE_BEAM)
@@ -143,28 +142,41 @@ __device__ __forceinline__ bool apply_dynamic(const DevComp &c, int k, Ray &ray,
 template <int... Ts>
 struct Chain {};
 
-template <bool LEDGER, bool TRACE, int T, int... Rest>
+// Occupancy hint per chain (waves per SIMD the compiler must fit).  The
+// projection chain is latency-bound in its voxel walk: 8 waves (64 VGPRs,
+// a few bytes of scratch for the ray state held across the walk) measured
+// faster than the 6 its natural 76 VGPRs allow.
+template <class C>
+struct WavesHint {
+    static constexpr int value = 1;
+};
+template <>
+struct WavesHint<Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR>> {
+    static constexpr int value = 8;
+};
+
+template <bool LEDGER, bool TRACE, bool EXACT, int T, int... Rest>
 __device__ __forceinline__ bool run_fixed(const DevInstr *ins, int k, Ray &ray, Stream &s, uint64_t ray_id,
                                           const RunArgs &a, const double *mu_lds, uint32_t n_mat,
                                           uint32_t n_ebin, RayEnd &end, const LedgerLds &L) {
-    if (!apply<T, LEDGER, TRACE>(ins->c[k], k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L)) return false;
+    if (!apply<T, LEDGER, TRACE, EXACT>(ins->c[k], k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L)) return false;
     if constexpr (sizeof...(Rest) > 0)
-        return run_fixed<LEDGER, TRACE, Rest...>(ins, k + 1, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
+        return run_fixed<LEDGER, TRACE, EXACT, Rest...>(ins, k + 1, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
     return true;
 }
 
-template <bool LEDGER, bool TRACE, int... Ts>
+template <bool LEDGER, bool TRACE, bool EXACT, int... Ts>
 __device__ __forceinline__ bool run_chain(Chain<Ts...>, const DevInstr *ins, Ray &ray, Stream &s, uint64_t ray_id,
                                           const RunArgs &a, const double *mu_lds, uint32_t n_mat,
                                           uint32_t n_ebin, RayEnd &end, const LedgerLds &L) {
     if constexpr (sizeof...(Ts) == 1 && ((Ts == kDynamic) && ...)) {
         const uint32_t n = ins->ncomp;
         for (uint32_t k = 0; k < n; ++k)
-            if (!apply_dynamic<LEDGER, TRACE>(ins->c[k], (int)k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L))
+            if (!apply_dynamic<LEDGER, TRACE, EXACT>(ins->c[k], (int)k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L))
                 return false;
         return true;
     } else {
-        return run_fixed<LEDGER, TRACE, Ts...>(ins, 0, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
+        return run_fixed<LEDGER, TRACE, EXACT, Ts...>(ins, 0, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
     }
 }
 
@@ -179,8 +191,8 @@ __device__ __forceinline__ bool run_chain(Chain<Ts...>, const DevInstr *ins, Ray
 // work-group b is remapped to the b/8-th slot of the (b mod 8)-th eighth of
 // the ray range: each XCD traces a contiguous block of ray ids, which the
 // stratified source sends through neighbouring voxels and pixels.
-template <class C, bool LEDGER, bool TRACE>
-__global__ __launch_bounds__(kBlock) void k_trace(const DevInstr *__restrict__ ins, RunArgs a) {
+template <class C, bool LEDGER, bool TRACE, bool EXACT>
+__global__ __launch_bounds__(kBlock, WavesHint<C>::value) void k_trace(const DevInstr *__restrict__ ins, RunArgs a) {
     extern __shared__ double smem[];
     const uint32_t n_mat = ins->n_mat, n_ebin = ins->n_ebin;
     double *mu_lds = smem;
@@ -213,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_trace(const DevInstr *__restrict__ i
         ray.E = 0.0;
         ray.w = 0.0;
         RayEnd end{kExited, -1, -1};
-        bool alive = run_chain<LEDGER, TRACE>(C{}, ins, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
+        bool alive = run_chain<LEDGER, TRACE, EXACT>(C{}, ins, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
         if constexpr (LEDGER) {
             if (alive) atomicAdd(L.slots + 4 * ins->ncomp, ray.w);
         }
@@ -267,20 +279,25 @@ enum Recipe { kRecipeGeneric = 0, kRecipeBasic, kRecipeEdct, kRecipeBeamline, kN
 
 typedef void (*KernelFn)(const DevInstr *, RunArgs);
 
-template <class C>
+template <class C, bool EXACT>
 struct KernelSet {
     static KernelFn get(bool ledger, bool trace) {
-        if (trace) return ledger ? k_trace<C, true, true> : k_trace<C, false, true>;
-        return ledger ? k_trace<C, true, false> : k_trace<C, false, false>;
+        if (trace) return ledger ? k_trace<C, true, true, EXACT> : k_trace<C, false, true, EXACT>;
+        return ledger ? k_trace<C, true, false, EXACT> : k_trace<C, false, false, EXACT>;
     }
 };
 
-KernelFn pick_kernel(int recipe, bool ledger, bool trace) {
+// exact: the phantom's planes are reached exactly by adding the voxel edge
+// (chains without a phantom ignore it)
+KernelFn pick_kernel(int recipe, bool ledger, bool trace, bool exact) {
     switch (recipe) {
-        case kRecipeBasic: return KernelSet<ChainBasic>::get(ledger, trace);
-        case kRecipeEdct: return KernelSet<ChainEdct>::get(ledger, trace);
-        case kRecipeBeamline: return KernelSet<ChainBeamline>::get(ledger, trace);
-        default: return KernelSet<ChainGeneric>::get(ledger, trace);
+        case kRecipeBasic: return KernelSet<ChainBasic, true>::get(ledger, trace);
+        case kRecipeEdct:
+            return exact ? KernelSet<ChainEdct, true>::get(ledger, trace) : KernelSet<ChainEdct, false>::get(ledger, trace);
+        case kRecipeBeamline: return KernelSet<ChainBeamline, true>::get(ledger, trace);
+        default:
+            return exact ? KernelSet<ChainGeneric, true>::get(ledger, trace)
+                         : KernelSet<ChainGeneric, false>::get(ledger, trace);
     }
 }
 
@@ -596,7 +613,8 @@ void mxr_instrument_destroy(mxr_instrument *ins) {
 
 static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, bool ledger, bool trace,
                          hipStream_t stream) {
-    KernelFn k = pick_kernel(ins->recipe, ledger, trace);
+    const bool exact = ins->host.phantom < 0 || ins->host.c[ins->host.phantom].aux[4] != 0.0;
+    KernelFn k = pick_kernel(ins->recipe, ledger, trace, exact);
     size_t shmem = 0;
     if (ins->host.phantom >= 0) shmem += (size_t)ins->host.n_mat * ins->host.n_ebin * sizeof(double);
     if (ledger) shmem += (size_t)(4 * ins->host.ncomp + 1) * sizeof(double);

@@ -302,13 +302,17 @@ __device__ __forceinline__ void comp_box(const DevComp &c, Ray &ray) {
 // read only where the material changes.  Voxels are read with buffer loads
 // (hardware range check: an out-of-range offset reads 0 instead of
 // faulting).  The walk is bounded by nx + ny + nz + 3 steps.
+#ifndef MXR_WALK_ROUND
+#define MXR_WALK_ROUND 2
+#endif
+constexpr int kWalkRound = MXR_WALK_ROUND;  // crossings per round of loads
+
 struct PhantomGeo {
     const uint8_t *vol;
     uint32_t nvox;
     int n[3];
     double v;
     double corner[3];
-    bool exact_steps;  // corner + i v is reached exactly by adding v
 };
 
 __device__ __forceinline__ uint32_t load_voxel(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
@@ -323,17 +327,26 @@ __device__ __forceinline__ T pick3(int k, T a0, T a1, T a2) {
 // Per-axis walk state, one entry per axis; roles D, A, B pick from it with
 // selects (registers cannot be indexed by a per-lane value).
 struct AxisSet {
-    double P[3], q[3], inv[3];
+    double P[3], q[3], inv[3], c[3];  // c: corner, mirrored (-corner) for negative directions
     int k[3], doff[3];
 };
 
-template <bool EXACT>
+// The walk in rounds of K crossings ("events").  Each event is the nearest
+// of the next D, A and B crossings (D first on ties with the others, A before
+// B), clipped to a_out; its alpha is computed from the plane index, so it is
+// the same number the merged order of all crossings would see.  When no lane
+// of the wave has an A or B crossing next, the event is a D step for the
+// whole wave (the common case); otherwise the lanes branch.  The K voxel
+// loads of a round are issued together and then folded into the material
+// runs in order.  Events past the exit carry t = a_out and keep stepping D:
+// their voxels (read through the range-checked buffer) can only open
+// zero-length runs, which add nothing.
+template <bool EXACT, int K>
 __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet &S, int D, int A, int B,
                                               uint32_t off, double a_in, double a_out,
                                               const double *__restrict__ mu_row) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)g.vol, (short)0, (int)g.nvox, 0x00020000);
     const double v = g.v;
-    // per-role state (D, A, B): next plane coordinate (mirrored), its alpha
     double PD = pick3(D, S.P[0], S.P[1], S.P[2]), PA = pick3(A, S.P[0], S.P[1], S.P[2]);
     double PB = pick3(B, S.P[0], S.P[1], S.P[2]);
     const double qD = pick3(D, S.q[0], S.q[1], S.q[2]), qA = pick3(A, S.q[0], S.q[1], S.q[2]);
@@ -344,64 +357,69 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
     int kB = pick3(B, S.k[0], S.k[1], S.k[2]);
     const int oD = pick3(D, S.doff[0], S.doff[1], S.doff[2]), oA = pick3(A, S.doff[0], S.doff[1], S.doff[2]);
     const int oB = pick3(B, S.doff[0], S.doff[1], S.doff[2]);
-    // mirrored corners: plane k of a mirrored axis sits at -corner + k v
-    const double gD = pick3(D, g.corner[0], g.corner[1], g.corner[2]);
-    const double gA = pick3(A, g.corner[0], g.corner[1], g.corner[2]);
-    const double gB = pick3(B, g.corner[0], g.corner[1], g.corner[2]);
-    const double cD = iD < 0.0 ? -gD : gD, cA = iA < 0.0 ? -gA : gA, cB = iB < 0.0 ? -gB : gB;
+    // plane k of a mirrored axis sits at -corner + k v
+    const double cD = pick3(D, S.c[0], S.c[1], S.c[2]), cA = pick3(A, S.c[0], S.c[1], S.c[2]);
+    const double cB = pick3(B, S.c[0], S.c[1], S.c[2]);
     double aD = (PD - qD) * iD;
     double aA = (iA == 0.0) ? kInf : (PA - qA) * iA;
     double aB = (iB == 0.0) ? kInf : (PB - qB) * iB;
 
     uint32_t run_m = load_voxel(rs, off);
     double a_start = a_in, tau = 0.0;
-    const int max_steps = g.n[0] + g.n[1] + g.n[2] + 3;
-    for (int it = 0; it < max_steps; ++it) {
-        if (aA < aD || aB < aD) {
-            // crossings of the other axes before the next D plane, in order
-            for (int r = 0; r < 3; ++r) {
-                const double lim = aD < a_out ? aD : a_out;
-                const bool takeA = (aA < lim) && (aA <= aB);
-                const bool takeB = !takeA && (aB < lim);
-                if (!(takeA || takeB)) break;
-                double t;
-                if (takeA) {
-                    t = aA;
-                    off += oA;
-                    kA += 1;
-                    PA = EXACT ? PA + v : cA + (double)kA * v;
-                    aA = (PA - qA) * iA;
-                } else {
-                    t = aB;
-                    off += oB;
-                    kB += 1;
-                    PB = EXACT ? PB + v : cB + (double)kB * v;
-                    aB = (PB - qB) * iB;
-                }
-                const uint32_t m = load_voxel(rs, off);
-                if (m != run_m) {
-                    tau = fma(mu_row[run_m], t - a_start, tau);
-                    a_start = t;
-                    run_m = m;
+    const int max_rounds = (g.n[0] + g.n[1] + g.n[2] + 3) / K + 2;
+    for (int round = 0; round < max_rounds; ++round) {
+        uint32_t o[K];
+        double t[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double lim = aD < a_out ? aD : a_out;
+            const bool secA = aA < lim, secB = aB < lim;
+            if (__builtin_amdgcn_ballot_w64(secA || secB) == 0) {
+                t[j] = lim;
+                off += (uint32_t)oD;
+                PD = EXACT ? PD + v : cD + (double)(++kD) * v;
+                aD = (PD - qD) * iD;
+            } else if (secA && aA <= aB) {
+                t[j] = aA;
+                off += (uint32_t)oA;
+                PA = EXACT ? PA + v : cA + (double)(++kA) * v;
+                aA = (PA - qA) * iA;
+            } else if (secB) {
+                t[j] = aB;
+                off += (uint32_t)oB;
+                PB = EXACT ? PB + v : cB + (double)(++kB) * v;
+                aB = (PB - qB) * iB;
+            } else {
+                t[j] = lim;
+                off += (uint32_t)oD;
+                PD = EXACT ? PD + v : cD + (double)(++kD) * v;
+                aD = (PD - qD) * iD;
+            }
+            o[j] = off;
+        }
+        uint32_t m[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) m[j] = load_voxel(rs, o[j]);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const bool change = m[j] != run_m;
+            if (__builtin_amdgcn_ballot_w64(change) != 0) {
+                if (change) {
+                    tau = fma(mu_row[run_m], t[j] - a_start, tau);
+                    a_start = t[j];
+                    run_m = m[j];
                 }
             }
         }
-        if (!(aD < a_out)) break;
-        const double t = aD;
-        off += oD;
-        kD += 1;
-        PD = EXACT ? PD + v : cD + (double)kD * v;
-        aD = (PD - qD) * iD;
-        const uint32_t m = load_voxel(rs, off);
-        if (m != run_m) {
-            tau = fma(mu_row[run_m], t - a_start, tau);
-            a_start = t;
-            run_m = m;
-        }
+        // every lane is past its exit once its last event sits at a_out
+        if (__builtin_amdgcn_ballot_w64(t[K - 1] < a_out) == 0) break;
     }
     return fma(mu_row[run_m], a_out - a_start, tau);
 }
 
+// EXACT: every plane coordinate corner + i v is reached exactly by adding v
+// (true for dyadic voxel sizes such as 1 mm); decided once per instrument.
+template <bool EXACT>
 __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q[3], const double dl[3],
                                              const double *__restrict__ mu_row) {
     double inv[3];
@@ -442,6 +460,7 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
             S.P[i] = 0.0;
             S.q[i] = q[i];
             S.inv[i] = 0.0;
+            S.c[i] = c;
             S.doff[i] = 0;
             continue;
         }
@@ -458,6 +477,7 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
             S.P[i] = c + (double)p * v;
             S.q[i] = q[i];
             S.inv[i] = inv[i];
+            S.c[i] = c;
             S.doff[i] = stride[i];
         } else {
             // last plane p in [0, n - 1] with alpha(p) > a_in, walked downwards
@@ -470,6 +490,7 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
             S.P[i] = -(c + (double)p * v);
             S.q[i] = -q[i];
             S.inv[i] = -inv[i];
+            S.c[i] = -c;
             S.doff[i] = -stride[i];
         }
     }
@@ -480,8 +501,7 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
     else if (ay >= az) { D = 1; A = 0; B = 2; }
     else { D = 2; A = 0; B = 1; }
     const uint32_t off = (uint32_t)(idx[0] + nx * idx[1] + nxy * idx[2]);
-    if (g.exact_steps) return siddon_walk<true>(g, S, D, A, B, off, a_in, a_out, mu_row);
-    return siddon_walk<false>(g, S, D, A, B, off, a_in, a_out, mu_row);
+    return siddon_walk<EXACT, kWalkRound>(g, S, D, A, B, off, a_in, a_out, mu_row);
 }
 
 // ------------------------------------------------------------- mirror ----

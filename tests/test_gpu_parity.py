@@ -115,7 +115,19 @@ def small_edct():
 def full_edct():
     vol = workloads.make_phantom(256, seed=1)
     mu = workloads.make_mu_tables(1)
-    return workloads.edct_projection(vol, mu, angle=0.0, strata=1024)
+    return workloads.edct_projection(vol, mu, angle=0.0, strata=4096)
+
+
+def odd_edct(angle, voxel):
+    """Projection through a phantom of unequal, odd dimensions; a voxel edge
+    of 0.8 mm is not dyadic, so planes are placed by multiplication."""
+    rng = np.random.default_rng(5)
+    vol = rng.integers(0, 8, size=(29, 23, 37)).astype(np.uint8)
+    vol[rng.random(vol.shape) < 0.6] = 0
+    ins = workloads.edct_projection(vol, workloads.make_mu_tables(2), angle=angle, strata=16, nx=32, ny=16, ne=16)
+    ins["components"][1]["voxel"] = voxel
+    ins["components"][0]["half_angle"] = 0.03
+    return ins
 
 
 def instruments(small_edct):
@@ -123,10 +135,12 @@ def instruments(small_edct):
         "basic_absorber": workloads.basic_absorber(),
         "edct_64": small_edct,
         "beamline": workloads.beamline(),
+        "edct_odd_45deg": odd_edct(math.pi / 4, 1.0),
+        "edct_odd_voxel0.8": odd_edct(1.1, 0.8),
     }
 
 
-@pytest.mark.parametrize("name", ["basic_absorber", "edct_64", "beamline"])
+@pytest.mark.parametrize("name", ["basic_absorber", "edct_64", "beamline", "edct_odd_45deg", "edct_odd_voxel0.8"])
 def test_per_ray_parity(torch_cuda, small_edct, name):
     ins = instruments(small_edct)[name]
     n = 100003  # ragged: not a multiple of the work-group or XCD count
@@ -143,7 +157,8 @@ def test_per_ray_parity(torch_cuda, small_edct, name):
     compare_rays(g, o, name, w_rel)
 
 
-@pytest.mark.parametrize("name,n", [("basic_absorber", 1000000), ("edct_64", 300001), ("beamline", 1000000)])
+@pytest.mark.parametrize("name,n", [("basic_absorber", 1000000), ("edct_64", 300001), ("beamline", 1000000),
+                                    ("edct_odd_45deg", 200000), ("edct_odd_voxel0.8", 200000)])
 def test_per_bin_parity(torch_cuda, small_edct, name, n):
     ins = instruments(small_edct)[name]
     announce("per-bin", name, "n", n, "seed 1")
