@@ -44,6 +44,12 @@ def parse():
     p.add_argument("--rays", type=int, default=N_RAYS)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=4_000_000)
+    p.add_argument("--workload", choices=("projection", "batch"), default="projection",
+                   help="projection: one 1e9-ray projection of the 256^3 phantom per step; batch: every angle "
+                        "of phantoms of uneven size in one captured launch per step, beside one launch per job")
+    p.add_argument("--batch-rays", type=int, default=10**8, help="rays per job of the batch")
+    p.add_argument("--batch-angles", type=int, default=360)
+    p.add_argument("--batch-sizes", default="64,128,256,512", help="phantom edges (voxels) of the batch")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="copy 1 GiB device to device before the timed region: a kernel of known traffic "
                         "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -69,12 +75,129 @@ def cpu_baseline(instr, n_sample: int, n_total: int):
                       f"({done} rays, {threads} host threads, {dt:.1f} s)"}
 
 
+def visits_per_ray(instr, samples: int = 200000, seed: int = 7) -> float:
+    """Mean number of voxels a source ray visits: directions uniform over
+    the cone's solid angle, chord through the phantom's box, one visit per
+    voxel the chord enters (1 + the voxel planes it crosses)."""
+    src, ph = instr["components"][0], instr["components"][1]
+    rng = np.random.default_rng(seed)
+    ct = 1.0 - rng.random(samples) * (1.0 - np.cos(src["half_angle"]))
+    st = np.sqrt(1.0 - ct * ct)
+    phi = 2.0 * np.pi * rng.random(samples)
+    d = np.stack([st * np.cos(phi), st * np.sin(phi), ct], axis=1)
+    R = np.asarray(ph["rot"], dtype=np.float64).reshape(3, 3)
+    pos = np.asarray(ph["pos"], dtype=np.float64)
+    o = R.T @ (-pos)            # source in the phantom frame (lab = R local + pos)
+    dl = d @ R                  # directions in the phantom frame
+    nz, ny, nx = ph["volume"].shape
+    v = ph["voxel"]
+    half = 0.5 * v * np.array([nx, ny, nz], dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t1 = (-half - o) / dl
+        t2 = (half - o) / dl
+    tmin = np.nanmax(np.minimum(t1, t2), axis=1)
+    tmax = np.nanmin(np.maximum(t1, t2), axis=1)
+    hit = tmax > np.maximum(tmin, 0.0)
+    a = o + np.maximum(tmin[hit], 0.0)[:, None] * dl[hit]
+    b = o + tmax[hit][:, None] * dl[hit]
+    n = np.array([nx, ny, nz])
+    ia = np.clip(np.floor((a + half) / v), 0, n - 1)
+    ib = np.clip(np.floor((b + half) / v), 0, n - 1)
+    return float(np.sum(1.0 + np.abs(ib - ia).sum(axis=1)) / samples)
+
+
+def batch_bench(args):
+    """Every angle of every phantom as one job; one captured launch per step
+    (autotuned shape), then the same jobs as one mxr_run each."""
+    import torch
+    import paper_2410_08747_amd as mxr
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    mu = workloads.make_mu_tables(1)
+    sizes = [int(x) for x in args.batch_sizes.split(",")]
+    n_ang = args.batch_angles
+    shared = {}
+    jobs, bytes_total = [], 0.0
+    for n in sizes:
+        vol = workloads.make_phantom(n, seed=1)
+        print(f"[bench] phantom {n}^3 built", file=sys.stderr, flush=True)
+        for k in range(n_ang):
+            ins = workloads.edct_projection(vol, mu, angle=2.0 * np.pi * k / n_ang, strata=STRATA)
+            vis = visits_per_ray(ins, samples=20000, seed=k)
+            I = mxr.Instrument(ins, dev, shared=shared)
+            jobs.append((I, args.batch_rays, 1 + len(jobs), len(jobs), I.new_tallies()))
+            bytes_total += args.batch_rays * (vis + 0.302 * 24)
+    n_rays = args.batch_rays * len(jobs)
+    stream = torch.cuda.current_stream()
+
+    def zero():
+        for j in jobs:
+            for v in j[4][0].values():
+                v.zero_()
+
+    B = mxr.Batch(jobs)
+    t_tune = time.perf_counter()
+    sched = B.autotune(0.01)
+    t_tune = time.perf_counter() - t_tune
+    print(f"[bench] autotuned {sched} in {t_tune:.1f} s", file=sys.stderr, flush=True)
+    times = {}
+    for mode in ("batch", "separate"):
+        for w in range(args.warmup + args.steps):
+            zero()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record(stream)
+            if mode == "batch":
+                B.run(stream)
+            else:
+                for I, nr, seed, job, t in jobs:
+                    I.run(nr, seed=seed, job=job, tallies=t, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            if w >= args.warmup:
+                times.setdefault(mode, []).append((wall, e0.elapsed_time(e1)))
+            print(f"[bench] {mode} pass {w}: {wall:.2f} s", file=sys.stderr, flush=True)
+    wall_b = float(np.mean([t[0] for t in times["batch"]]))
+    kern_b = float(np.mean([t[1] for t in times["batch"]]))
+    wall_s = float(np.mean([t[0] for t in times["separate"]]))
+    achieved = bytes_total / (kern_b * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": n_rays / wall_b,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall_b * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "batched_edct", "jobs": len(jobs), "angles": n_ang, "phantoms": sizes,
+                   "rays_per_job": args.batch_rays, "strata": STRATA, "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "schedule": {"groups_per_cu": sched[0], "tile_rays": sched[1], "autotune_s": t_tune},
+        "separate_launches": {"value": n_rays / wall_s, "unit": "rays/s", "ms_per_step": wall_s * 1e3},
+        "batch_over_separate": wall_s / wall_b,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the tracer is data-parallel over rays and the multi-GPU "
               "split (disjoint ray ranges + one histogram reduce) is not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        batch_bench(args)
+        return
     import torch
     import paper_2410_08747_amd as mxr
     import workloads

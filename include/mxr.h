@@ -89,8 +89,9 @@ typedef enum {
  *   material-major, energy bins uniform on [table E min, table E max),
  *   looked up piecewise constant.  par: 0 voxel edge, 1 table E min,
  *   2 table E max.  dims: 0 nx, 1 ny, 2 nz, 3 n_mat (1..16), n_ebin =
- *   data_len[1] / n_mat (1..256).  Ids >= n_mat are read as n_mat - 1.
- *   At most one phantom per instrument.
+ *   data_len[1] / n_mat (1..256).  A volume holding an id >= n_mat is
+ *   rejected at create (the volume is scanned once on the device).  At most
+ *   one phantom per instrument.
  * MXR_MIRROR_ELLIPTIC -- elliptic-cylinder mirror; local origin at the pole,
  *   z along the incoming axis, y to the reflected side; foci at (0,0,-p)
  *   and q (0, sin 2t0, cos 2t0).  Specular reflection, weight times the
@@ -204,6 +205,85 @@ mxr_status mxr_run(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays, uin
 mxr_status mxr_trace_rays(mxr_instrument *ins, const uint64_t *ray_ids, uint64_t n, uint64_t n_total,
                           uint64_t seed, uint32_t purpose, uint32_t job, const mxr_ray_soa *out,
                           void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Batched runs: many projections (angles) of many phantoms in one launch.
+ *
+ * A CT acquisition repeats one instrument for every projection angle of
+ * every sample (paper, section 3.3: a simulation per imaged line and
+ * rotational position; section 5.1: hundreds of projections per data set).
+ * A batch traces all jobs in one launch over a table of (job, ray range)
+ * tiles, longest jobs first, so phantoms of very different size share the
+ * GPU without one launch per job: either one work-group per tile (grid
+ * form) or persistent work-groups that pop tiles from a device counter.  The
+ * launch is captured once into a HIP graph and replayed by every
+ * mxr_batch_run.
+ */
+typedef struct mxr_batch mxr_batch;
+
+/* One job: trace rays [0, n_rays) of an n_rays-ray run of `instrument` with
+ * the given seed and RNG job field, adding into `tallies` (one per monitor,
+ * device arrays, as in mxr_run).  The result equals
+ * mxr_run(instrument, 0, n_rays, n_rays, seed, 0, job, tallies, ...) up to
+ * the order of the atomic additions. */
+typedef struct {
+    const mxr_instrument *instrument;
+    uint64_t n_rays;
+    uint64_t seed;
+    uint32_t job; /* < 2^24 */
+    mxr_tally tallies[MXR_MAX_DETECTORS];
+} mxr_batch_job;
+
+/* Launch shape of a batch.  It changes the order in which tiles are traced,
+ * never the set of rays or their results. */
+typedef struct {
+    /* 0: grid form -- one work-group per tile of 256 rays over a 2-D grid of
+     *    the whole batch, no loops, balanced by the hardware dispatcher;
+     * 1..8: persistent form -- that many work-groups per compute unit pop
+     *    tiles from a device counter until it passes the last tile. */
+    uint32_t groups_per_cu;
+    uint32_t tile_rays; /* persistent form: rays per tile, a multiple of 256 in
+                           [256, 2^24] (0 = 65536); grid form: 256 (0 = 256) */
+} mxr_batch_schedule;
+
+/* Validates the jobs (all instruments on the current device with the same
+ * component types in the same order; tally sizes; n_rays >= 1) and builds
+ * the job and tile tables on the device (owned by the handle).  schedule is
+ * nullable (grid form until tuned).  The
+ * instruments and tallies must outlive the handle.  Errors: MXR_E_INVALID,
+ * MXR_E_UNSUPPORTED (more than 2^31 tiles), MXR_E_NOMEM, MXR_E_HIP,
+ * MXR_E_STATE. */
+mxr_status mxr_batch_create(const mxr_batch_job *jobs, uint32_t n_jobs, const mxr_batch_schedule *schedule,
+                            mxr_batch **out);
+
+/* Traces every job once (tallies added to).  The first call on a handle
+ * captures the launch into a HIP graph; later calls replay it.  Asynchronous
+ * on hip_stream.  Calls on one handle must not overlap.  Errors: MXR_E_HIP,
+ * MXR_E_STATE. */
+mxr_status mxr_batch_run(mxr_batch *batch, void *hip_stream);
+
+/* Current launch shape. */
+mxr_status mxr_batch_get_schedule(const mxr_batch *batch, mxr_batch_schedule *out);
+
+/* Replaces the launch shape (the captured graph is rebuilt on the next run).
+ * Errors: MXR_E_INVALID for an out-of-range shape. */
+mxr_status mxr_batch_set_schedule(mxr_batch *batch, const mxr_batch_schedule *schedule);
+
+/* Synchronises the device, frees the handle and its device tables.  NULL is
+ * accepted. */
+void mxr_batch_destroy(mxr_batch *batch);
+
+/* Autotuner: times candidate launch shapes (the grid form, and persistent
+ * forms of 2/4/6/8 groups per CU x 16K/64K/256K-ray tiles) on
+ * the batch with every job's ray count scaled by rays_fraction (0 < f <= 1),
+ * keeps the fastest and records it under a key describing the batch (its
+ * component chain, job count, total rays and work estimate) in the text
+ * file cache_path (nullable: no cache), which later calls consult before
+ * timing anything.  The chosen shape is set on the batch and returned in
+ * out (nullable).  Timing runs ADD into the jobs' tallies: zero them before
+ * the production run.  Synchronous.  Errors: MXR_E_INVALID, MXR_E_HIP. */
+mxr_status mxr_batch_autotune(mxr_batch *batch, double rays_fraction, const char *cache_path,
+                              mxr_batch_schedule *out);
 
 #ifdef __cplusplus
 }

@@ -77,6 +77,23 @@ class mxr_ray_soa(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("x", "y", "z", "dx", "dy", "dz", "E", "w", "status", "dead_at", "bin")]
 
 
+MAX_DETECTORS = 4
+
+
+class mxr_batch_job(ctypes.Structure):
+    _fields_ = [
+        ("instrument", ctypes.c_void_p),
+        ("n_rays", ctypes.c_uint64),
+        ("seed", ctypes.c_uint64),
+        ("job", ctypes.c_uint32),
+        ("tallies", mxr_tally * MAX_DETECTORS),
+    ]
+
+
+class mxr_batch_schedule(ctypes.Structure):
+    _fields_ = [("groups_per_cu", ctypes.c_uint32), ("tile_rays", ctypes.c_uint32)]
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_2410_08747_amd/build.py (or __graft_entry__.build())")
@@ -98,6 +115,20 @@ def _load() -> ctypes.CDLL:
         ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(mxr_ray_soa), ctypes.c_void_p,
     ]
     lib.mxr_trace_rays.restype = ctypes.c_int
+    lib.mxr_batch_create.argtypes = [ctypes.POINTER(mxr_batch_job), ctypes.c_uint32,
+                                     ctypes.POINTER(mxr_batch_schedule), ctypes.POINTER(ctypes.c_void_p)]
+    lib.mxr_batch_create.restype = ctypes.c_int
+    lib.mxr_batch_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.mxr_batch_run.restype = ctypes.c_int
+    lib.mxr_batch_get_schedule.argtypes = [ctypes.c_void_p, ctypes.POINTER(mxr_batch_schedule)]
+    lib.mxr_batch_get_schedule.restype = ctypes.c_int
+    lib.mxr_batch_set_schedule.argtypes = [ctypes.c_void_p, ctypes.POINTER(mxr_batch_schedule)]
+    lib.mxr_batch_set_schedule.restype = ctypes.c_int
+    lib.mxr_batch_destroy.argtypes = [ctypes.c_void_p]
+    lib.mxr_batch_destroy.restype = None
+    lib.mxr_batch_autotune.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_char_p,
+                                       ctypes.POINTER(mxr_batch_schedule)]
+    lib.mxr_batch_autotune.restype = ctypes.c_int
     if lib.mxr_abi_version() != MXR_ABI_VERSION:
         raise ImportError(f"libmxr ABI {lib.mxr_abi_version()} != binding {MXR_ABI_VERSION}")
     return lib
@@ -148,6 +179,39 @@ def mxr_trace_rays(handle: int, ids_ptr: int, n: int, n_total: int, seed: int, p
                    out: mxr_ray_soa, stream=None) -> None:
     _check(lib.mxr_trace_rays(handle, ids_ptr, n, n_total, seed, purpose, job, ctypes.byref(out),
                               _stream_handle(stream)))
+
+
+def mxr_batch_create(jobs: Sequence[mxr_batch_job], schedule: Optional[mxr_batch_schedule] = None) -> int:
+    arr = (mxr_batch_job * max(1, len(jobs)))(*jobs)
+    h = ctypes.c_void_p()
+    _check(lib.mxr_batch_create(arr, len(jobs), ctypes.byref(schedule) if schedule is not None else None,
+                                ctypes.byref(h)))
+    return h.value
+
+
+def mxr_batch_run(handle: int, stream=None) -> None:
+    _check(lib.mxr_batch_run(handle, _stream_handle(stream)))
+
+
+def mxr_batch_get_schedule(handle: int) -> mxr_batch_schedule:
+    out = mxr_batch_schedule()
+    _check(lib.mxr_batch_get_schedule(handle, ctypes.byref(out)))
+    return out
+
+
+def mxr_batch_set_schedule(handle: int, schedule: mxr_batch_schedule) -> None:
+    _check(lib.mxr_batch_set_schedule(handle, ctypes.byref(schedule)))
+
+
+def mxr_batch_destroy(handle: int) -> None:
+    lib.mxr_batch_destroy(handle)
+
+
+def mxr_batch_autotune(handle: int, rays_fraction: float, cache_path: Optional[str] = None) -> mxr_batch_schedule:
+    out = mxr_batch_schedule()
+    _check(lib.mxr_batch_autotune(handle, rays_fraction, cache_path.encode() if cache_path else None,
+                                  ctypes.byref(out)))
+    return out
 
 
 # ------------------------------------------------------------ marshalling --
@@ -203,7 +267,9 @@ class Instrument:
     """An instrument on the current device: uploads the dict's arrays once
     (torch tensors own them) and holds the library handle."""
 
-    def __init__(self, instr: Dict, device=None):
+    def __init__(self, instr: Dict, device=None, shared: Optional[Dict] = None):
+        """``shared``: a dict reused across instruments so that the same
+        numpy array (e.g. one phantom seen at many angles) is uploaded once."""
         import torch
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self._tensors: List = []
@@ -213,10 +279,16 @@ class Instrument:
         self.detectors: List[Dict] = []
 
         def upload(arr, dtype):
-            a = np.ascontiguousarray(np.asarray(arr, dtype=dtype))
-            t = torch.from_numpy(a.reshape(-1)).to(self.device)
+            key = (id(arr), np.dtype(dtype).str)
+            if shared is not None and key in shared:
+                t = shared[key][1]
+            else:
+                a = np.ascontiguousarray(np.asarray(arr, dtype=dtype))
+                t = torch.from_numpy(a.reshape(-1)).to(self.device)
+                if shared is not None:
+                    shared[key] = (arr, t)  # holding arr keeps its id unique
             self._tensors.append(t)
-            return t.data_ptr(), a.size
+            return t.data_ptr(), t.numel()
 
         for k, c in enumerate(comps):
             s = descs[k]
@@ -294,3 +366,53 @@ class Instrument:
                                                          "dead_at", "bin")])
         mxr_trace_rays(self.handle, ids.data_ptr(), n, n_total, seed, purpose, job, soa, stream)
         return out
+
+
+class Batch:
+    """Many runs of instruments with one component chain (e.g. every angle
+    of every phantom of a CT acquisition) traced by one captured launch.
+
+    ``jobs`` is a list of (Instrument, n_rays, seed, job, tallies); the
+    instruments and tallies must stay alive as long as the batch."""
+
+    def __init__(self, jobs, schedule=None):
+        self._keep = [(j[0], j[4]) for j in jobs]
+        structs = []
+        for instr, n_rays, seed, job, tallies in jobs:
+            ts = Instrument.tally_structs(tallies)
+            js = mxr_batch_job(instr.handle, n_rays, seed, job)
+            for i, t in enumerate(ts):
+                js.tallies[i] = t
+            structs.append(js)
+        sched = None if schedule is None else mxr_batch_schedule(*schedule)
+        self.handle = mxr_batch_create(structs, sched)
+
+    def run(self, stream=None) -> None:
+        """Trace every job once, adding into its tallies.  Asynchronous."""
+        mxr_batch_run(self.handle, stream)
+
+    @property
+    def schedule(self):
+        s = mxr_batch_get_schedule(self.handle)
+        return (s.groups_per_cu, s.tile_rays)
+
+    @schedule.setter
+    def schedule(self, value) -> None:
+        mxr_batch_set_schedule(self.handle, mxr_batch_schedule(*value))
+
+    def autotune(self, rays_fraction: float, cache_path: Optional[str] = None):
+        """Pick the fastest launch shape (timing runs add into the tallies)."""
+        s = mxr_batch_autotune(self.handle, rays_fraction, cache_path)
+        return (s.groups_per_cu, s.tile_rays)
+
+    def close(self) -> None:
+        h = getattr(self, "handle", None)
+        if h and lib is not None:
+            lib.mxr_batch_destroy(h)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

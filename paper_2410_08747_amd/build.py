@@ -20,6 +20,9 @@ FLAGS = [
     "-munsafe-fp-atomics",
     # no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep loop-invariant constants (exp/sin/cos coefficients) where they are
+    # used instead of hoisting them into registers for the whole kernel
+    "-mllvm", "-disable-machine-licm",
     "-Wno-unused-command-line-argument",
 ]
 

@@ -21,6 +21,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "mxr.h"
 #include "mxr_device.h"
@@ -154,6 +156,17 @@ template <>
 struct WavesHint<Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR>> {
     static constexpr int value = 8;
 };
+// The batch kernels read their per-job arguments from memory rather than the
+// kernel-argument segment and hold more live values: the projection chain
+// fits 4 waves per SIMD without spilling there.
+template <class C>
+struct BatchWavesHint {
+    static constexpr int value = 1;
+};
+template <>
+struct BatchWavesHint<Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR>> {
+    static constexpr int value = 4;
+};
 
 template <bool LEDGER, bool TRACE, bool EXACT, int T, int... Rest>
 __device__ __forceinline__ bool run_fixed(const DevInstr *ins, int k, Ray &ray, Stream &s, uint64_t ray_id,
@@ -253,6 +266,127 @@ __global__ __launch_bounds__(kBlock, WavesHint<C>::value) void k_trace(const Dev
     }
 }
 
+// ---------------------------------------------------------------- batch --
+
+// One job of a batch: its instrument and the arguments of its run (read in
+// place from the job table, so their wave-uniform fields stay scalar loads).
+struct BatchJob {
+    RunArgs args;    // args.ins, n = n_total = rays of the job, seed, strata, tallies
+    uint64_t tile0;  // first tile of this job in the launch's tile order
+};
+
+__global__ void k_batch_reset(unsigned long long *counter) { *counter = 0ull; }
+
+// Persistent batched launch: each work-group pops tiles (job, range of
+// tile_rays ray ids) from one device counter until the counter passes the
+// last tile -- every work-group reaches that exit.  Jobs are stored
+// longest-first, so the costly tiles go out early and the short ones fill
+// the end.  The mu table is restaged in LDS when a work-group moves to a job
+// with another table.
+template <class C, bool EXACT>
+__global__ __launch_bounds__(kBlock, BatchWavesHint<C>::value) void k_batch(const BatchJob *__restrict__ jobs,
+                                                                     uint32_t n_jobs, uint64_t n_tiles,
+                                                                     uint32_t tile_rays,
+                                                                     unsigned long long *counter) {
+    extern __shared__ double smem[];
+    __shared__ unsigned long long s_tile;
+    double *mu_lds = smem;
+    const double *staged = nullptr;
+    const LedgerLds L{nullptr};
+    for (uint64_t iter = 0; iter <= n_tiles; ++iter) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1ull);
+        __syncthreads();
+        const uint64_t tile = s_tile;
+        __syncthreads();
+        if (tile >= n_tiles) break;
+        // job of this tile: the last job whose first tile is <= tile
+        uint32_t lo = 0, hi = n_jobs;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (jobs[mid].tile0 <= tile) lo = mid;
+            else hi = mid;
+        }
+        const BatchJob &J = jobs[lo];
+        const RunArgs &a = J.args;
+        const DevInstr *ins = a.ins;
+        const uint32_t n_mat = ins->n_mat, n_ebin = ins->n_ebin;
+        if (ins->phantom >= 0) {
+            const double *T = (const double *)ins->c[ins->phantom].data1;
+            if (T != staged) {
+                const uint32_t n_mu = n_mat * n_ebin;
+                for (uint32_t i = threadIdx.x; i < n_mu; i += kBlock) {
+                    uint32_t m = i / n_ebin, e = i - m * n_ebin;
+                    mu_lds[e * n_mat + m] = T[i] * 0.1;
+                }
+                staged = T;
+                __syncthreads();
+            }
+        }
+        const uint64_t r0 = (tile - J.tile0) * tile_rays;
+        const uint64_t r1 = r0 + tile_rays < a.n ? r0 + tile_rays : a.n;
+        for (uint64_t ray_id = r0 + threadIdx.x; ray_id < r1; ray_id += kBlock) {
+            Stream s;
+            s.init(a.seed, ray_id, a.word3);
+            Ray ray;
+            ray.r[0] = ray.r[1] = ray.r[2] = 0.0;
+            ray.d[0] = ray.d[1] = ray.d[2] = 0.0;
+            ray.E = 0.0;
+            ray.w = 0.0;
+            RayEnd end{kExited, -1, -1};
+            run_chain<false, false, EXACT>(C{}, ins, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
+        }
+        // the next tile may restage the table: everyone must be done with it
+        __syncthreads();
+    }
+}
+
+
+// Grid form of a batch: one work-group per tile of 256 rays, one ray per
+// lane and no loop (the whole batch is one 2-D grid; the hardware dispatcher
+// balances the uneven jobs).  Tiles are numbered longest job first; within
+// groups of 8 x 64 consecutive tiles, each XCD gets 64 consecutive tiles.
+template <class C, bool EXACT>
+__global__ __launch_bounds__(kBlock, BatchWavesHint<C>::value) void k_batch_grid(const BatchJob *__restrict__ jobs,
+                                                                          uint32_t n_jobs, uint64_t n_tiles) {
+    extern __shared__ double smem[];
+    constexpr uint64_t kRun = 64;
+    const uint64_t b = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const uint64_t group = b / (8 * kRun), in = b % (8 * kRun);
+    const uint64_t tile = group * (8 * kRun) + (in & 7) * kRun + (in >> 3);
+    if (tile >= n_tiles) return;  // whole work-group
+    uint32_t lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (jobs[mid].tile0 <= tile) lo = mid;
+        else hi = mid;
+    }
+    const RunArgs &a = jobs[lo].args;
+    const DevInstr *ins = a.ins;
+    const uint32_t n_mat = ins->n_mat, n_ebin = ins->n_ebin;
+    double *mu_lds = smem;
+    if (ins->phantom >= 0) {
+        const double *T = (const double *)ins->c[ins->phantom].data1;
+        const uint32_t n_mu = n_mat * n_ebin;
+        for (uint32_t i = threadIdx.x; i < n_mu; i += kBlock) {
+            uint32_t m = i / n_ebin, e = i - m * n_ebin;
+            mu_lds[e * n_mat + m] = T[i] * 0.1;
+        }
+    }
+    __syncthreads();
+    const uint64_t ray_id = (tile - jobs[lo].tile0) * kBlock + threadIdx.x;
+    if (ray_id >= a.n) return;
+    const LedgerLds L{nullptr};
+    Stream s;
+    s.init(a.seed, ray_id, a.word3);
+    Ray ray;
+    ray.r[0] = ray.r[1] = ray.r[2] = 0.0;
+    ray.d[0] = ray.d[1] = ray.d[2] = 0.0;
+    ray.E = 0.0;
+    ray.w = 0.0;
+    RayEnd end{kExited, -1, -1};
+    run_chain<false, false, EXACT>(C{}, ins, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
+}
+
 // Largest material id in a volume (run once at create).
 __global__ __launch_bounds__(kBlock) void k_max_id(const uint8_t *vol, uint64_t n, unsigned int *out) {
     unsigned int m = 0;
@@ -298,6 +432,27 @@ KernelFn pick_kernel(int recipe, bool ledger, bool trace, bool exact) {
         default:
             return exact ? KernelSet<ChainGeneric, true>::get(ledger, trace)
                          : KernelSet<ChainGeneric, false>::get(ledger, trace);
+    }
+}
+
+typedef void (*BatchKernelFn)(const BatchJob *, uint32_t, uint64_t, uint32_t, unsigned long long *);
+typedef void (*BatchGridFn)(const BatchJob *, uint32_t, uint64_t);
+
+BatchGridFn pick_batch_grid(int recipe, bool exact) {
+    switch (recipe) {
+        case kRecipeBasic: return k_batch_grid<ChainBasic, true>;
+        case kRecipeEdct: return exact ? k_batch_grid<ChainEdct, true> : k_batch_grid<ChainEdct, false>;
+        case kRecipeBeamline: return k_batch_grid<ChainBeamline, true>;
+        default: return exact ? k_batch_grid<ChainGeneric, true> : k_batch_grid<ChainGeneric, false>;
+    }
+}
+
+BatchKernelFn pick_batch_kernel(int recipe, bool exact) {
+    switch (recipe) {
+        case kRecipeBasic: return k_batch<ChainBasic, true>;
+        case kRecipeEdct: return exact ? k_batch<ChainEdct, true> : k_batch<ChainEdct, false>;
+        case kRecipeBeamline: return k_batch<ChainBeamline, true>;
+        default: return exact ? k_batch<ChainGeneric, true> : k_batch<ChainGeneric, false>;
     }
 }
 
@@ -716,6 +871,371 @@ mxr_status mxr_trace_rays(mxr_instrument *ins, const uint64_t *ray_ids, uint64_t
     a.ids = ray_ids;
     a.dump = o;
     return launch(ins, a, n, false, true, (hipStream_t)hip_stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batch --
+
+struct mxr_batch {
+    int device;
+    int recipe;
+    bool exact;
+    uint32_t n_jobs;
+    uint64_t total_rays, total_cost;
+    std::vector<BatchJob> host_jobs;  // longest-first
+    BatchJob *dev_jobs;
+    unsigned long long *counter;
+    size_t shmem;
+    uint32_t groups_per_cu, tile_rays;
+    uint64_t n_tiles;
+    int n_cu;
+    std::string key;  // describes the batch for the tuning cache
+    hipStream_t capture_stream;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    bool graph_ready;
+};
+
+static uint64_t batch_tiles(const std::vector<BatchJob> &jobs, uint32_t tile_rays, std::vector<uint64_t> *first) {
+    uint64_t t = 0;
+    for (const BatchJob &j : jobs) {
+        if (first) first->push_back(t);
+        t += (j.args.n + tile_rays - 1) / tile_rays;
+    }
+    return t;
+}
+
+static void batch_drop_graph(mxr_batch *b) {
+    if (b->graph_ready) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->graph_ready = false;
+    }
+}
+
+// Lays out the tiles for the current tile size and uploads the job table.
+static mxr_status batch_layout(mxr_batch *b) {
+    // a replay still in flight reads the table being replaced
+    hipError_t w = hipDeviceSynchronize();
+    if (w != hipSuccess) return hip_fail(w, "hipDeviceSynchronize before the job table upload");
+    std::vector<uint64_t> first;
+    const uint64_t n_tiles = batch_tiles(b->host_jobs, b->tile_rays, &first);
+    if (n_tiles >= (1ull << 31)) return fail(MXR_E_UNSUPPORTED, "batch needs %llu tiles (limit 2^31)", (unsigned long long)n_tiles);
+    for (size_t i = 0; i < first.size(); ++i) b->host_jobs[i].tile0 = first[i];
+    b->n_tiles = n_tiles;
+    hipError_t e = hipMemcpy(b->dev_jobs, b->host_jobs.data(), b->host_jobs.size() * sizeof(BatchJob), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy of the batch job table");
+    batch_drop_graph(b);
+    return MXR_OK;
+}
+
+// groups_per_cu 0 is the grid form, whose tiles are one work-group (256 rays)
+static bool schedule_ok(uint32_t g, uint32_t t) {
+    if (g == 0) return t == (uint32_t)kBlock;
+    return g >= 1 && g <= 8 && t >= (uint32_t)kBlock && t <= (1u << 24) && t % kBlock == 0;
+}
+
+// Capture counter reset + persistent kernel into a graph (once per shape).
+static mxr_status batch_capture(mxr_batch *b) {
+    hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    if (b->groups_per_cu == 0) {
+        // grid form: one work-group per 256-ray tile, 2-D grid
+        const uint64_t groups = (b->n_tiles + 511) / 512 * 512;
+        const uint32_t gx = (uint32_t)std::min<uint64_t>(groups, 1u << 16);
+        const uint32_t gy = (uint32_t)((groups + gx - 1) / gx);
+        hipLaunchKernelGGL(pick_batch_grid(b->recipe, b->exact), dim3(gx, gy), dim3(kBlock), b->shmem,
+                           b->capture_stream, (const BatchJob *)b->dev_jobs, b->n_jobs, b->n_tiles);
+    } else {
+        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, b->capture_stream, b->counter);
+        BatchKernelFn k = pick_batch_kernel(b->recipe, b->exact);
+        const unsigned grid = (unsigned)(b->groups_per_cu * (uint32_t)b->n_cu);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), b->shmem, b->capture_stream, (const BatchJob *)b->dev_jobs,
+                           b->n_jobs, b->n_tiles, b->tile_rays, b->counter);
+    }
+    hipError_t launch = hipGetLastError();
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->capture_stream, &g);
+    if (launch != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(launch, "batch kernel launch during capture");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    b->graph = g;
+    b->exec = x;
+    b->graph_ready = true;
+    return MXR_OK;
+}
+
+extern "C" {
+
+mxr_status mxr_batch_create(const mxr_batch_job *jobs, uint32_t n_jobs, const mxr_batch_schedule *schedule,
+                            mxr_batch **out) {
+    if (!jobs || !out || n_jobs == 0) return fail(MXR_E_INVALID, "null jobs or output, or no jobs");
+    *out = nullptr;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    const mxr_instrument *i0 = jobs[0].instrument;
+    if (!i0) return fail(MXR_E_INVALID, "job 0 has no instrument");
+    std::vector<std::pair<uint64_t, uint32_t>> order;  // (cost, index)
+    std::vector<BatchJob> hj(n_jobs);
+    uint64_t total_rays = 0, total_cost = 0;
+    for (uint32_t k = 0; k < n_jobs; ++k) {
+        const mxr_batch_job &j = jobs[k];
+        const mxr_instrument *ins = j.instrument;
+        if (!ins) return fail(MXR_E_INVALID, "job %u has no instrument", k);
+        if (ins->device != cur) return fail(MXR_E_STATE, "job %u: instrument on device %d, device %d current", k, ins->device, cur);
+        if (ins->host.ncomp != i0->host.ncomp) return fail(MXR_E_INVALID, "job %u: component chain differs from job 0", k);
+        for (uint32_t c = 0; c < ins->host.ncomp; ++c)
+            if (ins->host.c[c].type != i0->host.c[c].type) return fail(MXR_E_INVALID, "job %u: component chain differs from job 0", k);
+        if (j.n_rays < 1) return fail(MXR_E_INVALID, "job %u: n_rays must be positive", k);
+        if (j.job > 0xFFFFFFu) return fail(MXR_E_INVALID, "job %u: RNG job field must be < 2^24", k);
+        BatchJob &bj = hj[k];
+        std::memset(&bj, 0, sizeof bj);
+        RunArgs &b = bj.args;
+        b.ins = ins->dev;
+        b.first = 0;
+        b.n = j.n_rays;
+        b.n_total = j.n_rays;
+        b.seed = j.seed;
+        b.word3 = j.job;
+        uint64_t G = ins->strata ? ins->strata : 1;
+        while (G > 1 && G * G > j.n_rays) G -= 1;
+        if (G * G > 1 && j.n_rays > (~0ull) / (G * G)) return fail(MXR_E_INVALID, "job %u: n_rays * strata^2 must stay below 2^64", k);
+        b.G = G;
+        b.G2 = G * G;
+        for (uint32_t d = 0; d < ins->n_det; ++d) {
+            const mxr_tally &t = j.tallies[d];
+            if (!t.count || !t.sum_w || !t.sum_w2) return fail(MXR_E_INVALID, "job %u: tally %u has a null array", k, d);
+            if (t.n_bins != ins->det_bins[d])
+                return fail(MXR_E_INVALID, "job %u: tally %u has %llu bins, monitor needs %llu", k, d,
+                            (unsigned long long)t.n_bins, (unsigned long long)ins->det_bins[d]);
+            b.tally.count[d] = (unsigned long long *)t.count;
+            b.tally.sum_w[d] = t.sum_w;
+            b.tally.sum_w2[d] = t.sum_w2;
+        }
+        // work estimate per ray: a walk through the phantom visits ~ (nx + ny + nz) voxels
+        uint64_t per_ray = 1;
+        if (ins->host.phantom >= 0) {
+            const DevComp &c = ins->host.c[ins->host.phantom];
+            per_ray += (uint64_t)c.dims[0] + c.dims[1] + c.dims[2];
+        }
+        const uint64_t cost = j.n_rays * per_ray;
+        order.push_back({cost, k});
+        total_rays += j.n_rays;
+        total_cost += cost;
+    }
+    std::stable_sort(order.begin(), order.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+    mxr_batch *b = new (std::nothrow) mxr_batch();
+    if (!b) return fail(MXR_E_NOMEM, "host allocation failed");
+    b->device = cur;
+    b->recipe = i0->recipe;
+    b->exact = true;
+    size_t mu_bytes = 0;
+    for (uint32_t k = 0; k < n_jobs; ++k) {
+        const mxr_instrument *ins = jobs[k].instrument;
+        if (ins->host.phantom >= 0) {
+            b->exact = b->exact && ins->host.c[ins->host.phantom].aux[4] != 0.0;
+            mu_bytes = std::max(mu_bytes, (size_t)ins->host.n_mat * ins->host.n_ebin * sizeof(double));
+        }
+    }
+    b->shmem = mu_bytes;
+    b->n_jobs = n_jobs;
+    b->total_rays = total_rays;
+    b->total_cost = total_cost;
+    for (const auto &o : order) b->host_jobs.push_back(hj[o.second]);
+    e = hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, cur);
+    if (e != hipSuccess || b->n_cu < 1) b->n_cu = 256;
+    b->groups_per_cu = 0;  // grid form until tuned
+    b->tile_rays = kBlock;
+    if (schedule) {
+        uint32_t g = schedule->groups_per_cu;
+        uint32_t t = schedule->tile_rays ? schedule->tile_rays : (g == 0 ? (uint32_t)kBlock : 65536u);
+        if (!schedule_ok(g, t)) {
+            delete b;
+            return fail(MXR_E_INVALID, "schedule: groups_per_cu 0 (grid form, tile_rays 256) or 1..8 with tile_rays a multiple of 256 in [256, 2^24]");
+        }
+        b->groups_per_cu = g;
+        b->tile_rays = t;
+    }
+    char key[256];
+    std::string chain;
+    for (uint32_t c = 0; c < i0->host.ncomp; ++c) chain += std::to_string(i0->host.c[c].type) + (c + 1 < i0->host.ncomp ? "-" : "");
+    snprintf(key, sizeof key, "chain=%s jobs=%u rays=%llu cost=%llu cu=%d", chain.c_str(), n_jobs,
+             (unsigned long long)total_rays, (unsigned long long)total_cost, b->n_cu);
+    b->key = key;
+    b->graph_ready = false;
+    b->dev_jobs = nullptr;
+    b->counter = nullptr;
+    b->capture_stream = nullptr;
+    e = hipMalloc((void **)&b->dev_jobs, n_jobs * sizeof(BatchJob));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->counter, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+    mxr_status st = e == hipSuccess ? batch_layout(b) : fail(MXR_E_NOMEM, "batch allocation: %s", hipGetErrorString(e));
+    if (st != MXR_OK) {
+        if (b->dev_jobs) (void)hipFree(b->dev_jobs);
+        if (b->counter) (void)hipFree(b->counter);
+        if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return MXR_OK;
+}
+
+mxr_status mxr_batch_run(mxr_batch *b, void *hip_stream) {
+    if (!b) return fail(MXR_E_INVALID, "null batch");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != b->device) return fail(MXR_E_STATE, "batch lives on device %d, device %d is current", b->device, cur);
+    if (!b->graph_ready) {
+        mxr_status st = batch_capture(b);
+        if (st != MXR_OK) return st;
+    }
+    e = hipGraphLaunch(b->exec, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return MXR_OK;
+}
+
+mxr_status mxr_batch_get_schedule(const mxr_batch *b, mxr_batch_schedule *out) {
+    if (!b || !out) return fail(MXR_E_INVALID, "null batch or output");
+    out->groups_per_cu = b->groups_per_cu;
+    out->tile_rays = b->tile_rays;
+    return MXR_OK;
+}
+
+mxr_status mxr_batch_set_schedule(mxr_batch *b, const mxr_batch_schedule *s) {
+    if (!b || !s) return fail(MXR_E_INVALID, "null batch or schedule");
+    if (!schedule_ok(s->groups_per_cu, s->tile_rays))
+        return fail(MXR_E_INVALID, "schedule: groups_per_cu 0 (grid form, tile_rays 256) or 1..8 with tile_rays a multiple of 256 in [256, 2^24]");
+    const bool relayout = s->tile_rays != b->tile_rays;
+    b->groups_per_cu = s->groups_per_cu;
+    b->tile_rays = s->tile_rays;
+    batch_drop_graph(b);
+    return relayout ? batch_layout(b) : MXR_OK;
+}
+
+void mxr_batch_destroy(mxr_batch *b) {
+    if (!b) return;
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != b->device) (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    batch_drop_graph(b);
+    (void)hipFree(b->dev_jobs);
+    (void)hipFree(b->counter);
+    (void)hipStreamDestroy(b->capture_stream);
+    if (cur >= 0 && cur != b->device) (void)hipSetDevice(cur);
+    delete b;
+}
+
+// Tuning cache: one line per batch, "<key>\t<groups_per_cu> <tile_rays>".
+static bool cache_lookup(const char *path, const std::string &key, uint32_t &g, uint32_t &t) {
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char *tab = std::strchr(line, '\t');
+        if (!tab) continue;
+        *tab = 0;
+        unsigned gg = 0, tt = 0;
+        if (key == line && std::sscanf(tab + 1, "%u %u", &gg, &tt) == 2 && schedule_ok(gg, tt)) {
+            g = gg;
+            t = tt;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void cache_store(const char *path, const std::string &key, uint32_t g, uint32_t t) {
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s\t%u %u\n", key.c_str(), g, t);
+    std::fclose(f);
+}
+
+mxr_status mxr_batch_autotune(mxr_batch *b, double rays_fraction, const char *cache_path, mxr_batch_schedule *out) {
+    if (!b) return fail(MXR_E_INVALID, "null batch");
+    if (!(rays_fraction > 0.0 && rays_fraction <= 1.0)) return fail(MXR_E_INVALID, "rays_fraction must be in (0, 1]");
+    uint32_t g = 0, t = 0;
+    if (cache_lookup(cache_path, b->key, g, t)) {
+        mxr_batch_schedule s{g, t};
+        mxr_status st = mxr_batch_set_schedule(b, &s);
+        if (st == MXR_OK && out) *out = s;
+        return st;
+    }
+    // timing copy of the job table with every job's rays scaled down (the
+    // random streams and tallies are the real ones)
+    std::vector<BatchJob> saved = b->host_jobs;
+    for (BatchJob &j : b->host_jobs) {
+        j.args.n = std::max<uint64_t>(1, (uint64_t)(j.args.n * rays_fraction));
+        j.args.n_total = j.args.n;
+        uint64_t G = j.args.G;
+        while (G > 1 && G * G > j.args.n_total) G -= 1;
+        j.args.G = G;
+        j.args.G2 = G * G;
+    }
+    mxr_status lay = batch_layout(b);
+    if (lay != MXR_OK) {
+        b->host_jobs = saved;
+        (void)batch_layout(b);
+        return lay;
+    }
+    const uint32_t gpc[] = {2, 4, 6, 8};
+    const uint32_t tiles[] = {16384, 65536, 262144};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best_ms = 0.f;
+    uint32_t best_g = b->groups_per_cu, best_t = b->tile_rays;
+    mxr_status st = e == hipSuccess ? MXR_OK : hip_fail(e, "hipEventCreate");
+    for (uint32_t ti = 0; st == MXR_OK && ti < 4; ++ti) {
+        for (uint32_t gi = 0; st == MXR_OK && gi < 4; ++gi) {
+            if (ti == 3 && gi > 0) break;
+            // the last candidate is the grid form
+            mxr_batch_schedule s = ti < 3 ? mxr_batch_schedule{gpc[gi], tiles[ti]} : mxr_batch_schedule{0u, (uint32_t)kBlock};
+            st = mxr_batch_set_schedule(b, &s);
+            for (int rep = 0; st == MXR_OK && rep < 2; ++rep) {  // first replay warms up
+                e = hipEventRecord(e0, b->capture_stream);
+                if (e == hipSuccess) st = mxr_batch_run(b, b->capture_stream);
+                if (st == MXR_OK) e = hipEventRecord(e1, b->capture_stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e != hipSuccess) st = hip_fail(e, "autotune timing");
+            }
+            float ms = 0.f;
+            if (st == MXR_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && (best_ms == 0.f || ms < best_ms)) {
+                best_ms = ms;
+                best_g = s.groups_per_cu;
+                best_t = s.tile_rays;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    // back to the real ray counts, with the fastest shape
+    b->host_jobs = saved;
+    b->groups_per_cu = best_g;
+    b->tile_rays = best_t;
+    mxr_batch_schedule s{best_g, best_t};
+    mxr_status st2 = batch_layout(b);
+    if (st != MXR_OK) return st;
+    if (st2 != MXR_OK) return st2;
+    cache_store(cache_path, b->key, best_g, best_t);
+    if (out) *out = s;
+    return MXR_OK;
 }
 
 }  // extern "C"

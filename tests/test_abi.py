@@ -52,6 +52,10 @@ def test_calls_that_need_no_device(lib):
     assert b"null" in lib.mxr_last_error()
     assert lib.mxr_run(None, 0, 0, 1, 0, 0, 0, None, 0, None, None) == -1
     lib.mxr_instrument_destroy(None)
+    bout = ctypes.c_void_p()
+    assert lib.mxr_batch_create(None, 1, None, ctypes.byref(bout)) == -1
+    assert lib.mxr_batch_run(None, None) == -1
+    lib.mxr_batch_destroy(None)
 
 
 def test_binding_struct_layout(lib):
@@ -65,7 +69,7 @@ def test_binding_struct_layout(lib):
 #include <stdio.h>
 #include <stddef.h>
 #include "mxr.h"
-int main(void){printf("%zu %zu %zu %zu\n", sizeof(mxr_component_desc), sizeof(mxr_tally), sizeof(mxr_ray_soa), offsetof(mxr_component_desc, data));return 0;}
+int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(mxr_component_desc), sizeof(mxr_tally), sizeof(mxr_ray_soa), offsetof(mxr_component_desc, data), sizeof(mxr_batch_job), offsetof(mxr_batch_job, tallies), sizeof(mxr_batch_schedule));return 0;}
 '''
     import tempfile
     with tempfile.TemporaryDirectory() as d:
@@ -76,3 +80,6 @@ int main(void){printf("%zu %zu %zu %zu\n", sizeof(mxr_component_desc), sizeof(mx
         sizes = [int(x) for x in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     assert sizes[:3] == [280, 32, 88]
     assert sizes[3] == desc.data.offset
+    assert sizes[4] == ctypes.sizeof(m.mxr_batch_job) == 160
+    assert sizes[5] == m.mxr_batch_job.tallies.offset
+    assert sizes[6] == ctypes.sizeof(m.mxr_batch_schedule) == 8
