@@ -117,11 +117,12 @@ def _load():
         lib.mxo_spectrum.restype = ctypes.c_double
         lib.mxo_run.argtypes = [
             ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
-            ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+            ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_double,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
         ]
         lib.mxo_trace_rays.argtypes = [
             ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
-            ctypes.c_void_p, ctypes.c_int64,
+            ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
         ]
@@ -130,6 +131,13 @@ def _load():
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
         ]
         lib.mxo_siddon_debug.restype = ctypes.c_double
+        lib.mxo_ppnd16.argtypes = [ctypes.c_double]
+        lib.mxo_ppnd16.restype = ctypes.c_double
+        lib.mxo_truncnorm.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        lib.mxo_truncnorm.restype = ctypes.c_double
+        lib.mxo_proposal_density.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
+        lib.mxo_proposal_density.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -215,9 +223,19 @@ class Instrument:
             raise ValueError(f"unknown component type {t}")
 
 
+def _gmm(gmm):
+    if gmm is None:
+        return None, None
+    g = np.ascontiguousarray(np.asarray(gmm, dtype=np.float64).reshape(56))
+    return g, _ptr(g)
+
+
 def run(instr: Dict, n: int, seed: int, first: int = 0, n_total: Optional[int] = None,
-        purpose: int = 0, job: int = 0, threads: Optional[int] = None, ledger: bool = False):
-    """Trace rays [first, first + n) of an n_total-ray run.
+        purpose: int = 0, job: int = 0, threads: Optional[int] = None, ledger: bool = False,
+        gmm=None, alpha: float = 0.1):
+    """Trace rays [first, first + n) of an n_total-ray run (the cone-beam
+    source drawing from the proposal mixture ``gmm``, 8 x (pi, mu_u, mu_v,
+    mu_E, sigma_u, sigma_v, sigma_E), with plain weight ``alpha``, when given).
 
     Returns a list (one per detector) of dicts with ``count`` (uint64),
     ``sum_w`` and ``sum_w2`` (float64) arrays in the flat bin order
@@ -236,12 +254,14 @@ def run(instr: Dict, n: int, seed: int, first: int = 0, n_total: Optional[int] =
         tal[i].count, tal[i].sum_w, tal[i].sum_w2 = _ptr(o["count"]), _ptr(o["sum_w"]), _ptr(o["sum_w2"])
         tal[i].n_bins = nb
     led = np.zeros(4 * ins.n + 1) if ledger else None
-    lib.mxo_run(ctypes.addressof(ins.arr), ins.n, seed, first, n, n_total, purpose, job,
+    g, gp = _gmm(gmm)
+    lib.mxo_run(ctypes.addressof(ins.arr), ins.n, seed, first, n, n_total, purpose, job, gp, alpha,
                 ctypes.addressof(tal), _ptr(led) if led is not None else None, threads)
     return (outs, led) if ledger else outs
 
 
-def trace_rays(instr: Dict, ids: Sequence[int], seed: int, n_total: int, purpose: int = 0, job: int = 0):
+def trace_rays(instr: Dict, ids: Sequence[int], seed: int, n_total: int, purpose: int = 0, job: int = 0,
+               gmm=None, alpha: float = 0.1):
     """Final state of each listed ray: r, d (n,3), E, w, status, dead_at, bin."""
     lib = _load()
     ins = Instrument(instr)
@@ -251,7 +271,8 @@ def trace_rays(instr: Dict, ids: Sequence[int], seed: int, n_total: int, purpose
         "r": np.zeros((n, 3)), "d": np.zeros((n, 3)), "E": np.zeros(n), "w": np.zeros(n),
         "status": np.zeros(n, np.int32), "dead_at": np.zeros(n, np.int32), "bin": np.zeros(n, np.int64),
     }
-    lib.mxo_trace_rays(ctypes.addressof(ins.arr), ins.n, seed, n_total, purpose, job, _ptr(ids), n,
+    g, gp = _gmm(gmm)
+    lib.mxo_trace_rays(ctypes.addressof(ins.arr), ins.n, seed, n_total, purpose, job, gp, alpha, _ptr(ids), n,
                        _ptr(out["r"]), _ptr(out["d"]), _ptr(out["E"]), _ptr(out["w"]),
                        _ptr(out["status"]), _ptr(out["dead_at"]), _ptr(out["bin"]))
     return out
@@ -294,3 +315,24 @@ def siddon_segments(phantom: Dict, q, dl, E: float, max_seg: int = 100000):
                                _ptr(vox), _ptr(ln), max_seg, _ptr(ns))
     k = int(min(ns[0], max_seg))
     return tau, vox[:k].copy(), ln[:k].copy()
+
+
+def ppnd16(p: float) -> float:
+    """Standard normal quantile (Wichura's AS 241)."""
+    return _load().mxo_ppnd16(float(p))
+
+
+def truncnorm(za: float, zb: float, U: float) -> float:
+    """Standard normal truncated to [za, zb] by inversion at U."""
+    return _load().mxo_truncnorm(float(za), float(zb), float(U))
+
+
+def proposal_density(source: Dict, gmm, alpha: float, u: float, v: float, E: float):
+    """(q, p): the proposal mixture density and the physical source density
+    at y = (u, v, E) for a cone-beam source."""
+    ins = Instrument({"components": [source]})
+    g, gp = _gmm(gmm)
+    pp = np.zeros(1)
+    q = _load().mxo_proposal_density(ctypes.addressof(ins.arr[0].par), gp, float(alpha), float(u), float(v),
+                                     float(E), _ptr(pp))
+    return q, float(pp[0])

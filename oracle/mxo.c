@@ -299,6 +299,179 @@ static void src_cone_beam(const mxo_comp *c, mxo_stream *s, mxo_ray *ray, uint64
     to_lab(c, q, dl, ray->r, ray->d);
 }
 
+/* ------------------------------------------------ learned proposal ---- */
+/* Inverse of the standard normal distribution function: Wichura's
+ * algorithm AS 241 (PPND16, Applied Statistics 37 (1988) 477), rational
+ * approximations on a central region and two tail regions, accurate to about
+ * 1e-16. */
+double mxo_ppnd16(double p)
+{
+    double q = p - 0.5, r;
+    if (fabs(q) <= 0.425) {
+        r = 0.180625 - q * q;
+        return q * (((((((2.5090809287301226727e+3 * r + 3.3430575583588128105e+4) * r +
+                          6.7265770927008700853e+4) * r + 4.5921953931549871457e+4) * r +
+                        1.3731693765509461125e+4) * r + 1.9715909503065514427e+3) * r +
+                      1.3314166789178437745e+2) * r + 3.3871328727963666080e+0) /
+               (((((((5.2264952788528545610e+3 * r + 2.8729085735721942674e+4) * r +
+                     3.9307895800092710610e+4) * r + 2.1213794301586595867e+4) * r +
+                   5.3941960214247511077e+3) * r + 6.8718700749205790830e+2) * r +
+                 4.2313330701600911252e+1) * r + 1.0);
+    }
+    r = q < 0.0 ? p : 1.0 - p;
+    r = sqrt(-log(r));
+    double x;
+    if (r <= 5.0) {
+        r -= 1.6;
+        x = (((((((7.74545014278341407640e-4 * r + 2.27238449892691845833e-2) * r +
+                  2.41780725177450611770e-1) * r + 1.27045825245236838258e+0) * r +
+                3.64784832476320460504e+0) * r + 5.76949722146069140550e+0) * r +
+              4.63033784615654529590e+0) * r + 1.42343711074968357734e+0) /
+            (((((((1.05075007164441684324e-9 * r + 5.47593808499534494600e-4) * r +
+                  1.51986665636164571966e-2) * r + 1.48103976427480074590e-1) * r +
+                6.89767334985100004550e-1) * r + 1.67638483018380384940e+0) * r +
+              2.05319162663775882187e+0) * r + 1.0);
+    } else {
+        r -= 5.0;
+        x = (((((((2.01033439929228813265e-7 * r + 2.71155556874348757815e-5) * r +
+                  1.24266094738807843860e-3) * r + 2.65321895265761230930e-2) * r +
+                2.96560571828504891230e-1) * r + 1.78482653991729133580e+0) * r +
+              5.46378491116411436990e+0) * r + 6.65790464350110377720e+0) /
+            (((((((2.04426310338993978564e-15 * r + 1.42151175831644588870e-7) * r +
+                  1.84631831751005468180e-5) * r + 7.86869131145613259100e-4) * r +
+                1.48753612908506148525e-2) * r + 1.36929880922735805310e-1) * r +
+              5.99832206555887937690e-1) * r + 1.0);
+    }
+    return q < 0.0 ? -x : x;
+}
+
+/* Standard normal distribution function and its upper tail. */
+static double norm_cdf(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
+static double norm_sf(double z) { return 0.5 * erfc(z / sqrt(2.0)); }
+
+/* A standard normal truncated to [za, zb], by inversion of the distribution
+ * function at the point that leaves mass U of the interval below it.  The
+ * target is written as a lower-tail probability Pa + U (Pb - Pa) when that
+ * is at most 1/2, else as the upper-tail probability Qb + (1 - U)(Qa - Qb)
+ * (P lower tails, Q upper tails of za and zb), so no probability near 1 is
+ * inverted and neither form cancels in the tail it serves. */
+double mxo_truncnorm(double za, double zb, double U)
+{
+    double Pa = norm_cdf(za), Pb = norm_cdf(zb);
+    double pl = Pa + U * (Pb - Pa);
+    if (pl <= 0.5)
+        return mxo_ppnd16(pl);
+    double Qa = norm_sf(za), Qb = norm_sf(zb);
+    return -mxo_ppnd16(Qb + (1.0 - U) * (Qa - Qb));
+}
+
+/* Density of the proposal mixture q = alpha q_plain + (1 - alpha) q_gmm at
+ * y = (u, v, E), u = dx/dz, v = dy/dz, and the physical density p of the
+ * plain source at y.  The plain source is uniform in solid angle inside the
+ * cone (solid angle Omega; in (u, v) its density is
+ * (1 + u^2 + v^2)^(-3/2) / Omega) and uniform in energy; the physical
+ * source has the spectrum S(E) instead.  q_gmm is the 8-component diagonal
+ * Gaussian mixture truncated to the box [-t, t]^2 x [emin, emax], t = tan
+ * alpha: sum_k pi_k prod_d phi(z_kd)/sigma_kd divided by sum_k pi_k Z_k, Z_k
+ * the box mass of component k.  gmm holds per component (pi, mu_u, mu_v,
+ * mu_E, sigma_u, sigma_v, sigma_E). */
+double mxo_proposal_density(const double *par, const double *gmm, double alpha_def, double u, double v, double E,
+                            double *p_phys)
+{
+    double alpha = par[0], emin = par[1], emax = par[2];
+    double t = tan(alpha);
+    double lo[3] = {-t, -t, emin}, hi[3] = {t, t, emax}, y[3] = {u, v, E};
+    double omega = 2.0 * M_PI * (1.0 - cos(alpha));
+    double J = pow(1.0 + u * u + v * v, -1.5);
+    int in_cone = u * u + v * v <= t * t && E >= emin && E <= emax;
+    double q_plain = in_cone ? J / omega / (emax - emin) : 0.0;
+    *p_phys = in_cone ? mxo_spectrum(par, E) * J / omega : 0.0;
+    double num = 0.0, norm = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        const double *g = gmm + 7 * k;
+        double dens = g[0], Z = g[0];
+        for (int d = 0; d < 3; ++d) {
+            double mu = g[1 + d], sg = g[4 + d];
+            double z = (y[d] - mu) / sg;
+            dens *= exp(-0.5 * z * z) / (sg * sqrt(2.0 * M_PI));
+            Z *= norm_cdf((hi[d] - mu) / sg) - norm_cdf((lo[d] - mu) / sg);
+        }
+        num += dens;
+        norm += Z;
+    }
+    int in_box = u >= lo[0] && u <= hi[0] && v >= lo[1] && v <= hi[1] && E >= emin && E <= emax;
+    double q_gmm = in_box ? num / norm : 0.0;
+    return alpha_def * q_plain + (1.0 - alpha_def) * q_gmm;
+}
+
+/* Cone-beam point source drawing from the proposal mixture (unstratified).
+ * Uniforms: U0 picks the branch (plain when U0 < alpha_def), U1 the mixture
+ * component (probability proportional to pi_k Z_k), U2..U4 the coordinates
+ * (u, v, E): the plain branch maps (U2, U3) to the cone like the plain
+ * source with one stratum and takes E = emin + (emax - emin) U4; the mixture
+ * branch inverts a truncated normal per coordinate.  w0 = p(y) / q(y) with q
+ * the full mixture density whichever branch drew the ray; a draw outside the
+ * cone has w0 = 0 and is absorbed at the source. */
+static int src_cone_proposal(const mxo_comp *c, mxo_stream *s, mxo_ray *ray, const double *gmm, double alpha_def)
+{
+    double alpha = c->par[0], emin = c->par[1], emax = c->par[2];
+    double t = tan(alpha);
+    double lo[3] = {-t, -t, emin}, hi[3] = {t, t, emax};
+    double y[3];
+    if (stream_uniform(s, 0) < alpha_def) {
+        double a = 2.0 * stream_uniform(s, 2) - 1.0, b = 2.0 * stream_uniform(s, 3) - 1.0;
+        double rad, ang;
+        if (a == 0.0 && b == 0.0) {
+            rad = 0.0;
+            ang = 0.0;
+        } else if (fabs(a) > fabs(b)) {
+            rad = a;
+            ang = (M_PI / 4.0) * (b / a);
+        } else {
+            rad = b;
+            ang = (M_PI / 2.0) - (M_PI / 4.0) * (a / b);
+        }
+        double theta = 2.0 * asin(fabs(rad) * sin(0.5 * alpha));
+        double psi = atan2(rad * sin(ang), rad * cos(ang));
+        double dz = cos(theta);
+        y[0] = sin(theta) * cos(psi) / dz;
+        y[1] = sin(theta) * sin(psi) / dz;
+        y[2] = emin + (emax - emin) * stream_uniform(s, 4);
+    } else {
+        double mass[8], total = 0.0;
+        for (int k = 0; k < 8; ++k) {
+            const double *g = gmm + 7 * k;
+            double Z = g[0];
+            for (int d = 0; d < 3; ++d)
+                Z *= norm_cdf((hi[d] - g[1 + d]) / g[4 + d]) - norm_cdf((lo[d] - g[1 + d]) / g[4 + d]);
+            mass[k] = Z;
+            total += Z;
+        }
+        double target = stream_uniform(s, 1) * total, run = 0.0;
+        int pick = 7;
+        for (int k = 0; k < 8; ++k) {
+            run += mass[k];
+            if (target < run && mass[k] > 0.0) {
+                pick = k;
+                break;
+            }
+        }
+        const double *g = gmm + 7 * pick;
+        for (int d = 0; d < 3; ++d) {
+            double mu = g[1 + d], sg = g[4 + d];
+            y[d] = mu + sg * mxo_truncnorm((lo[d] - mu) / sg, (hi[d] - mu) / sg, stream_uniform(s, 2 + d));
+        }
+    }
+    double p_phys;
+    double q = mxo_proposal_density(c->par, gmm, alpha_def, y[0], y[1], y[2], &p_phys);
+    double n = sqrt(1.0 + y[0] * y[0] + y[1] * y[1]);
+    double qz[3] = {0.0, 0.0, 0.0}, dl[3] = {y[0] / n, y[1] / n, 1.0 / n};
+    ray->E = y[2];
+    ray->w = p_phys > 0.0 ? p_phys / q : 0.0;
+    to_lab(c, qz, dl, ray->r, ray->d);
+    return p_phys > 0.0;
+}
+
 /* Gaussian (undulator-like) source: position and angle normal in both
  * planes (Box-Muller on consecutive uniform pairs), energy flat within a
  * relative half-width. */
@@ -753,6 +926,8 @@ typedef struct {
     int ncomp;
     uint64_t seed, n_total;
     uint32_t purpose, job;
+    const double *gmm; /* proposal mixture of the cone-beam source, or NULL */
+    double alpha_def;  /* weight of the plain source in the proposal mixture */
 } mxo_instr;
 
 static void trace_one(const mxo_instr *I, uint64_t ray_id, mxo_ray *ray, mxo_tally *tallies, ksum *ledger)
@@ -771,7 +946,13 @@ static void trace_one(const mxo_instr *I, uint64_t ray_id, mxo_ray *ray, mxo_tal
         int64_t bin = -1;
         switch (c->type) {
         case MXO_SRC_RECT_CONE: src_rect_cone(c, &s, ray); w_in = ray->w; break;
-        case MXO_SRC_CONE_BEAM: src_cone_beam(c, &s, ray, ray_id, I->n_total); w_in = ray->w; break;
+        case MXO_SRC_CONE_BEAM:
+            if (I->gmm)
+                ok = src_cone_proposal(c, &s, ray, I->gmm, I->alpha_def);
+            else
+                src_cone_beam(c, &s, ray, ray_id, I->n_total);
+            w_in = ray->w;
+            break;
         case MXO_SRC_GAUSSIAN: src_gaussian(c, &s, ray); w_in = ray->w; break;
         case MXO_SLIT: ok = comp_slit(c, ray); break;
         case MXO_BOX: comp_box(c, ray); break;
@@ -782,9 +963,17 @@ static void trace_one(const mxo_instr *I, uint64_t ray_id, mxo_ray *ray, mxo_tal
         case MXO_DETECTOR: ok = comp_detector(c, ray, &bin); break;
         default: ok = 0; break;
         }
-        draw += draws_of(c->type);
+        draw += (c->type == MXO_SRC_CONE_BEAM && I->gmm) ? 5 : draws_of(c->type);
         if (ledger)
             kadd(&ledger[4 * k + 0], w_in);
+        if (!ok && k == 0) {
+            /* a proposal draw outside the cone: emitted with weight 0 */
+            ray->status = MXO_ABSORBED;
+            ray->dead_at = 0;
+            if (ledger)
+                kadd(&ledger[1], ray->w);
+            return;
+        }
         if (!ok) {
             *ray = before;
             ray->status = MXO_ABSORBED;
@@ -844,18 +1033,19 @@ static int count_detectors(const mxo_comp *comps, int ncomp)
     return n;
 }
 
-/* Trace rays [first, first + n) of an n_total-ray run, adding their
+/* Trace rays [first, first + n) of an n_total-ray run (with the cone-beam
+ * source drawing from the proposal mixture gmm when it is non-null), adding their
  * histograms into the caller's tallies (one per detector, in order) and,
  * when ledger is non-null, their weight ledger (4 * ncomp + 1 doubles).
  * The work is split over n_threads threads by contiguous ray ranges, each
  * with private histograms that are summed at the end. */
 int mxo_run(const mxo_comp *comps, int ncomp, uint64_t seed, uint64_t first, uint64_t n,
-            uint64_t n_total, uint32_t purpose, uint32_t job, mxo_tally *tallies, double *ledger,
-            int n_threads)
+            uint64_t n_total, uint32_t purpose, uint32_t job, const double *gmm, double alpha_def,
+            mxo_tally *tallies, double *ledger, int n_threads)
 {
     if (n_threads < 1)
         n_threads = 1;
-    mxo_instr I = {comps, ncomp, seed, n_total, purpose, job};
+    mxo_instr I = {comps, ncomp, seed, n_total, purpose, job, gmm, alpha_def};
     int n_det = count_detectors(comps, ncomp);
     int n_slots = 4 * ncomp + 1;
     worker_arg *args = (worker_arg *)calloc((size_t)n_threads, sizeof(worker_arg));
@@ -907,10 +1097,11 @@ int mxo_run(const mxo_comp *comps, int ncomp, uint64_t seed, uint64_t first, uin
 
 /* Trace the listed rays one by one and report their final states. */
 int mxo_trace_rays(const mxo_comp *comps, int ncomp, uint64_t seed, uint64_t n_total, uint32_t purpose,
-                   uint32_t job, const uint64_t *ids, int64_t n, double *r_out, double *d_out,
-                   double *E_out, double *w_out, int32_t *status_out, int32_t *dead_out, int64_t *bin_out)
+                   uint32_t job, const double *gmm, double alpha_def, const uint64_t *ids, int64_t n,
+                   double *r_out, double *d_out, double *E_out, double *w_out, int32_t *status_out,
+                   int32_t *dead_out, int64_t *bin_out)
 {
-    mxo_instr I = {comps, ncomp, seed, n_total, purpose, job};
+    mxo_instr I = {comps, ncomp, seed, n_total, purpose, job, gmm, alpha_def};
     for (int64_t i = 0; i < n; ++i) {
         mxo_ray ray;
         memset(&ray, 0, sizeof ray);
