@@ -182,7 +182,8 @@ def batch_bench(args):
                    "rays_per_job": args.batch_rays, "strata": STRATA, "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
-        "schedule": {"groups_per_cu": sched[0], "tile_rays": sched[1], "autotune_s": t_tune},
+        "schedule": {"form": ["grid", "persistent", "launches"][sched[0]], "groups_per_cu": sched[1],
+                     "tile_rays": sched[2], "branches": sched[3], "autotune_s": t_tune},
         "separate_launches": {"value": n_rays / wall_s, "unit": "rays/s", "ms_per_step": wall_s * 1e3},
         "batch_over_separate": wall_s / wall_b,
     }

@@ -207,17 +207,185 @@ mxr_status mxr_trace_rays(mxr_instrument *ins, const uint64_t *ray_ids, uint64_t
                           void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Importance sampling of the cone-beam source by a learned proposal.
+ *
+ * The Monte Carlo weight a ray carries (paper, section 2.2.2: the particle
+ * state includes a statistical weight) lets rays be drawn from any density
+ * q that covers the physical one p, each weighted by p/q, without bias.  The
+ * proposal is a defensive mixture q = alpha q_plain + (1 - alpha) q_gmm over
+ * y = (u, v, E), u = dx/dz and v = dy/dz in the source frame:
+ *   q_plain  the plain source (uniform in solid angle inside the cone,
+ *            uniform energy);
+ *   q_gmm    8 diagonal Gaussians truncated to the box
+ *            [-tan a, tan a]^2 x [emin, emax] (a the cone half-angle), with
+ *            density sum_k pi_k prod_d N(y_d; mu_kd, sigma_kd) / sum_k pi_k Z_k,
+ *            Z_k the box mass of component k.
+ * Draw order per ray: U0 picks the branch (plain when U0 < alpha), U1 the
+ * component (probability pi_k Z_k / sum), U2..U4 the coordinates (plain
+ * branch: concentric map of (U2, U3) with one stratum, E from U4; mixture
+ * branch: truncated-normal inversion).  The ray's weight is p(y)/q(y), q the
+ * full mixture density whichever branch drew it; a draw outside the cone is
+ * absorbed at the source with weight 0.
+ */
+
+/* Makes later mxr_run / mxr_trace_rays / mxr_collect calls on this
+ * instrument draw its cone-beam source from the proposal (runs are then
+ * unstratified).  gmm: DEVICE array of 56 doubles, per component
+ * (pi, mu_u, mu_v, mu_E, sigma_u, sigma_v, sigma_E); pi >= 0 (need not sum
+ * to 1), sigma > 0; it is copied (synchronously, after the device is idle),
+ * so it may be freed afterwards.  alpha in [0, 1].  gmm NULL switches the
+ * proposal off.  Errors: MXR_E_INVALID (values), MXR_E_UNSUPPORTED (the
+ * first component is not a cone-beam source, or a later component draws
+ * uniforms), MXR_E_STATE, MXR_E_NOMEM, MXR_E_HIP. */
+mxr_status mxr_proposal_set(mxr_instrument *ins, const double *gmm, double alpha);
+
+/* Rows of training data: one per ray that reaches the monitor.  All arrays
+ * are DEVICE arrays of `capacity` rows; *count (device) is advanced by the
+ * rows found (rows past capacity are dropped, so count > capacity means
+ * truncation: zero *count before the first run).  Row order is not
+ * specified. */
+typedef struct {
+    float *ctx;        /* capacity x 6: `context` of the run, copied per row */
+    double *y;         /* capacity x 3: u, v (source frame), E of the ray */
+    double *w;         /* capacity: weight at the monitor */
+    int64_t *bin;      /* capacity: monitor bin */
+    uint64_t capacity;
+    uint64_t *count;
+    float context[6];  /* the run's context (e.g. focal spot, angle, size) */
+} mxr_hits;
+
+/* mxr_run that also appends every ray reaching the monitor to hits.  The
+ * instrument must be a cone-beam source, then slits / boxes / phantoms
+ * (which keep direction and energy), then one monitor.  Errors as mxr_run,
+ * plus MXR_E_UNSUPPORTED for other instruments. */
+mxr_status mxr_collect(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays, uint64_t n_total, uint64_t seed,
+                       uint32_t purpose, uint32_t job, const mxr_tally *tallies, uint32_t n_tallies,
+                       const mxr_hits *hits, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * The proposal network.
+ *
+ * An MLP maps a 6-number context c (e.g. focal-spot position, projection
+ * angle as cos / sin, phantom size) to the mixture above:
+ *   z1 = c W1 + b1, h1 = silu(z1), z2 = h1 W2 + b2, h2 = silu(z2),
+ *   o = h2 W3 + b3 (56 numbers), silu(z) = z / (1 + exp(-z)).
+ * Head, component k reading o[7k .. 7k+6]: pi = softmax of the logits
+ * o[7k], mu_d = centre_d + half_d tanh(o[7k+1+d]), sigma_d = half_d
+ * (1e-3 + softplus(o[7k+4+d])), with the box of the source (centre, half
+ * width).  Parameters are packed W1 (6 x 128, row-major), b1, W2 (128 x
+ * 128), b2, W3 (128 x 56), b3: MXR_MLP_PARAMS numbers, held as float32
+ * master weights and a bfloat16 working copy (uint16_t bit patterns).
+ * Products run in bfloat16 with float32 accumulation; the head and its loss
+ * in float32.
+ *
+ * Training loss over a batch: L = -sum_i omega_i log q_gmm(y_i | c_i) /
+ * sum_i omega_i.  All arrays below are DEVICE arrays owned by the caller;
+ * every call is asynchronous on hip_stream.
+ */
+#define MXR_MLP_IN 6
+#define MXR_MLP_HIDDEN 128
+#define MXR_MLP_OUT 56
+#define MXR_MLP_PARAMS 24632
+
+/* Regions of the workspace of a batch of n rows (offsets in bytes from
+ * mxr_mlp_workspace_layout; row-major, row stride = the row width):
+ * X context (n x 6 bf16), Z1 / H1 (n x 128 f32 / bf16), Z2 / H2, O (n x 56
+ * f32), DO / DOH gradient of O (f32 / bf16), DZ2 / DZ2H, DZ1 / DZ1H
+ * gradients of the pre-activations, PARTIAL per-split gradient partials,
+ * Y (n x 3 f64) and W (n f64) gathered targets and weights, ROWLOSS (n f64),
+ * SCALARS (reduction scratch). */
+#define MXR_MLP_WS_X 0
+#define MXR_MLP_WS_Z1 1
+#define MXR_MLP_WS_H1 2
+#define MXR_MLP_WS_Z2 3
+#define MXR_MLP_WS_H2 4
+#define MXR_MLP_WS_O 5
+#define MXR_MLP_WS_DO 6
+#define MXR_MLP_WS_DOH 7
+#define MXR_MLP_WS_DZ2 8
+#define MXR_MLP_WS_DZ2H 9
+#define MXR_MLP_WS_DZ1 10
+#define MXR_MLP_WS_DZ1H 11
+#define MXR_MLP_WS_PARTIAL 12
+#define MXR_MLP_WS_Y 13
+#define MXR_MLP_WS_W 14
+#define MXR_MLP_WS_ROWLOSS 15
+#define MXR_MLP_WS_SCALARS 16
+#define MXR_MLP_WS_REGIONS 17
+
+typedef struct {
+    float lr, beta1, beta2, eps; /* Adam (Kingma and Ba 2015) */
+    uint32_t batch;              /* rows per step */
+    uint32_t epochs;
+    uint64_t seed;               /* per-epoch row shuffles */
+    uint32_t first_step;         /* Adam steps already taken (0 for a fresh start) */
+} mxr_train_cfg;
+
+/* Bytes of workspace for batches of up to `batch` rows. */
+uint64_t mxr_mlp_workspace_bytes(uint64_t batch);
+
+/* Byte offsets of the MXR_MLP_WS_REGIONS workspace regions for a batch of
+ * n rows (offsets[MXR_MLP_WS_REGIONS], host).  Errors: MXR_E_INVALID. */
+mxr_status mxr_mlp_workspace_layout(uint64_t batch, uint64_t *offsets);
+
+/* y[i] = bfloat16(x[i]), round to nearest even. */
+mxr_status mxr_mlp_to_bf16(const float *x, uint64_t n, uint16_t *y, void *hip_stream);
+
+/* Network outputs o (n x 56 f32) of contexts ctx (n x 6 f32) under the
+ * bfloat16 parameters w; the layer values stay in ws (ws_bytes >=
+ * mxr_mlp_workspace_bytes(n)).  Errors: MXR_E_INVALID, MXR_E_HIP. */
+mxr_status mxr_mlp_forward(const uint16_t *w, const float *ctx, uint64_t n, float *out, void *ws, uint64_t ws_bytes,
+                           void *hip_stream);
+
+/* Mixture tables for mxr_proposal_set from outputs: gmm (n x 56 f64, per
+ * row 8 x (pi, mu[3], sigma[3])), with the source's box lo / hi (host, 3
+ * doubles each: -tan a, -tan a, emin / tan a, tan a, emax). */
+mxr_status mxr_mlp_mixture(const float *out, uint64_t n, const double lo[3], const double hi[3], double *gmm,
+                           void *hip_stream);
+
+/* Loss L (loss: device double, nullable) and its gradient with respect to
+ * the parameters (grad: MXR_MLP_PARAMS f32, overwritten) over n rows
+ * (ctx n x 6 f32, y n x 3 f64, omega n f64 >= 0 with a positive sum).
+ * The weight gradients are reduced over splits of 1024 rows in a fixed
+ * order (deterministic).  Errors: MXR_E_INVALID, MXR_E_HIP. */
+mxr_status mxr_mlp_loss_grad(const uint16_t *w, const float *ctx, const double *y, const double *omega, uint64_t n,
+                             const double lo[3], const double hi[3], float *grad, double *loss, void *ws,
+                             uint64_t ws_bytes, void *hip_stream);
+
+/* One Adam step on master (f32) with moments m, v (f32), writing the
+ * bfloat16 copy w; step counts from 1 (bias correction). */
+mxr_status mxr_adam_step(float *master, uint16_t *w, const float *grad, float *m, float *v, uint64_t n_params,
+                         uint32_t step, float lr, float beta1, float beta2, float eps, void *hip_stream);
+
+/* Training weights of collected rows: omega_i = w_i / max(I_b, floor_frac
+ * * mean of I over bins with hits), I = sum_w of the collecting run's
+ * monitor (n_bins), so every live bin carries equal total weight.
+ * scratch: 2 * 256 + 1 doubles. */
+mxr_status mxr_train_weights(const double *w, const int64_t *bin, uint64_t n, const double *sum_w, uint64_t n_bins,
+                             double floor_frac, double *omega, double *scratch, void *hip_stream);
+
+/* Adam training over n_rows rows (< 2^32) for cfg->epochs epochs of
+ * batches of cfg->batch rows, each epoch in its own shuffled order.  grad
+ * (MXR_MLP_PARAMS f32) is scratch; loss_log (nullable, epochs *
+ * ceil(n_rows / batch) doubles) receives each step's loss.  Errors:
+ * MXR_E_INVALID, MXR_E_UNSUPPORTED, MXR_E_HIP. */
+mxr_status mxr_mlp_train(const float *ctx, const double *y, const double *omega, uint64_t n_rows,
+                         const mxr_train_cfg *cfg, const double lo[3], const double hi[3], float *master, uint16_t *w,
+                         float *m, float *v, float *grad, void *ws, uint64_t ws_bytes, double *loss_log,
+                         void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Batched runs: many projections (angles) of many phantoms in one launch.
  *
  * A CT acquisition repeats one instrument for every projection angle of
  * every sample (paper, section 3.3: a simulation per imaged line and
  * rotational position; section 5.1: hundreds of projections per data set).
- * A batch traces all jobs in one launch over a table of (job, ray range)
- * tiles, longest jobs first, so phantoms of very different size share the
- * GPU without one launch per job: either one work-group per tile (grid
- * form) or persistent work-groups that pop tiles from a device counter.  The
- * launch is captured once into a HIP graph and replayed by every
- * mxr_batch_run.
+ * A batch traces all jobs, longest first, from one HIP graph that is
+ * captured once and replayed by every mxr_batch_run: either one kernel over
+ * a table of (job, ray range) tiles (one work-group per tile, or persistent
+ * work-groups that pop tiles from a device counter), or the jobs' own
+ * kernels on parallel graph branches so that one job's tail overlaps the
+ * next job.
  */
 typedef struct mxr_batch mxr_batch;
 
@@ -234,22 +402,22 @@ typedef struct {
     mxr_tally tallies[MXR_MAX_DETECTORS];
 } mxr_batch_job;
 
-/* Launch shape of a batch.  It changes the order in which tiles are traced,
+/* Launch shape of a batch.  It changes the order in which rays are traced,
  * never the set of rays or their results. */
+#define MXR_BATCH_GRID 0u       /* one work-group per tile of 256 rays over one 2-D grid */
+#define MXR_BATCH_PERSISTENT 1u /* groups_per_cu work-groups per CU pop tiles from a counter */
+#define MXR_BATCH_LAUNCHES 2u   /* one mxr_run-shaped launch per job, on `branches` graph branches */
 typedef struct {
-    /* 0: grid form -- one work-group per tile of 256 rays over a 2-D grid of
-     *    the whole batch, no loops, balanced by the hardware dispatcher;
-     * 1..8: persistent form -- that many work-groups per compute unit pop
-     *    tiles from a device counter until it passes the last tile. */
-    uint32_t groups_per_cu;
-    uint32_t tile_rays; /* persistent form: rays per tile, a multiple of 256 in
-                           [256, 2^24] (0 = 65536); grid form: 256 (0 = 256) */
+    uint32_t form;
+    uint32_t groups_per_cu; /* persistent: 1..8 */
+    uint32_t tile_rays;     /* persistent: a multiple of 256 in [256, 2^24] (0 = 65536) */
+    uint32_t branches;      /* launches: 1..4 (0 = 1); jobs dealt longest-first round-robin */
 } mxr_batch_schedule;
 
 /* Validates the jobs (all instruments on the current device with the same
  * component types in the same order; tally sizes; n_rays >= 1) and builds
  * the job and tile tables on the device (owned by the handle).  schedule is
- * nullable (grid form until tuned).  The
+ * nullable (one launch per job on one branch until tuned).  The
  * instruments and tallies must outlive the handle.  Errors: MXR_E_INVALID,
  * MXR_E_UNSUPPORTED (more than 2^31 tiles), MXR_E_NOMEM, MXR_E_HIP,
  * MXR_E_STATE. */
@@ -273,8 +441,8 @@ mxr_status mxr_batch_set_schedule(mxr_batch *batch, const mxr_batch_schedule *sc
  * accepted. */
 void mxr_batch_destroy(mxr_batch *batch);
 
-/* Autotuner: times candidate launch shapes (the grid form, and persistent
- * forms of 2/4/6/8 groups per CU x 16K/64K/256K-ray tiles) on
+/* Autotuner: times candidate launch shapes (the grid form; persistent forms
+ * of 2/4/8 groups per CU x 16K/64K-ray tiles; launches on 1/2/4 branches) on
  * the batch with every job's ray count scaled by rays_fraction (0 < f <= 1),
  * keeps the fastest and records it under a key describing the batch (its
  * component chain, job count, total rays and work estimate) in the text

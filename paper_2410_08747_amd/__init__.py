@@ -90,8 +90,35 @@ class mxr_batch_job(ctypes.Structure):
     ]
 
 
+BATCH_GRID, BATCH_PERSISTENT, BATCH_LAUNCHES = 0, 1, 2
+
+
 class mxr_batch_schedule(ctypes.Structure):
-    _fields_ = [("groups_per_cu", ctypes.c_uint32), ("tile_rays", ctypes.c_uint32)]
+    _fields_ = [("form", ctypes.c_uint32), ("groups_per_cu", ctypes.c_uint32), ("tile_rays", ctypes.c_uint32),
+                ("branches", ctypes.c_uint32)]
+
+
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 6, 128, 56, 24632
+WS_REGIONS = ("X", "Z1", "H1", "Z2", "H2", "O", "DO", "DOH", "DZ2", "DZ2H", "DZ1", "DZ1H", "PARTIAL", "Y", "W",
+              "ROWLOSS", "SCALARS")
+
+
+class mxr_train_cfg(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("batch", ctypes.c_uint32), ("epochs", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("first_step", ctypes.c_uint32)]
+
+
+class mxr_hits(ctypes.Structure):
+    _fields_ = [
+        ("ctx", ctypes.c_void_p),
+        ("y", ctypes.c_void_p),
+        ("w", ctypes.c_void_p),
+        ("bin", ctypes.c_void_p),
+        ("capacity", ctypes.c_uint64),
+        ("count", ctypes.c_void_p),
+        ("context", ctypes.c_float * 6),
+    ]
 
 
 def _load() -> ctypes.CDLL:
@@ -115,6 +142,34 @@ def _load() -> ctypes.CDLL:
         ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(mxr_ray_soa), ctypes.c_void_p,
     ]
     lib.mxr_trace_rays.restype = ctypes.c_int
+    lib.mxr_proposal_set.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double]
+    lib.mxr_proposal_set.restype = ctypes.c_int
+    lib.mxr_collect.argtypes = [
+        ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+        ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(mxr_tally), ctypes.c_uint32, ctypes.POINTER(mxr_hits),
+        ctypes.c_void_p,
+    ]
+    lib.mxr_collect.restype = ctypes.c_int
+    P, U64, D3 = ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)
+    lib.mxr_mlp_workspace_bytes.argtypes = [U64]
+    lib.mxr_mlp_workspace_bytes.restype = U64
+    lib.mxr_mlp_workspace_layout.argtypes = [U64, P]
+    lib.mxr_mlp_workspace_layout.restype = ctypes.c_int
+    lib.mxr_mlp_to_bf16.argtypes = [P, U64, P, P]
+    lib.mxr_mlp_to_bf16.restype = ctypes.c_int
+    lib.mxr_mlp_forward.argtypes = [P, P, U64, P, P, U64, P]
+    lib.mxr_mlp_forward.restype = ctypes.c_int
+    lib.mxr_mlp_mixture.argtypes = [P, U64, D3, D3, P, P]
+    lib.mxr_mlp_mixture.restype = ctypes.c_int
+    lib.mxr_mlp_loss_grad.argtypes = [P, P, P, P, U64, D3, D3, P, P, P, U64, P]
+    lib.mxr_mlp_loss_grad.restype = ctypes.c_int
+    lib.mxr_adam_step.argtypes = [P, P, P, P, P, U64, ctypes.c_uint32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, P]
+    lib.mxr_adam_step.restype = ctypes.c_int
+    lib.mxr_train_weights.argtypes = [P, P, U64, P, U64, ctypes.c_double, P, P, P]
+    lib.mxr_train_weights.restype = ctypes.c_int
+    lib.mxr_mlp_train.argtypes = [P, P, P, U64, ctypes.POINTER(mxr_train_cfg), D3, D3, P, P, P, P, P, P, U64, P, P]
+    lib.mxr_mlp_train.restype = ctypes.c_int
     lib.mxr_batch_create.argtypes = [ctypes.POINTER(mxr_batch_job), ctypes.c_uint32,
                                      ctypes.POINTER(mxr_batch_schedule), ctypes.POINTER(ctypes.c_void_p)]
     lib.mxr_batch_create.restype = ctypes.c_int
@@ -179,6 +234,63 @@ def mxr_trace_rays(handle: int, ids_ptr: int, n: int, n_total: int, seed: int, p
                    out: mxr_ray_soa, stream=None) -> None:
     _check(lib.mxr_trace_rays(handle, ids_ptr, n, n_total, seed, purpose, job, ctypes.byref(out),
                               _stream_handle(stream)))
+
+
+def mxr_proposal_set(handle: int, gmm_ptr: Optional[int], alpha: float) -> None:
+    _check(lib.mxr_proposal_set(handle, gmm_ptr, alpha))
+
+
+def mxr_collect(handle: int, first_ray: int, n_rays: int, n_total: int, seed: int, purpose: int, job: int,
+                tallies: Sequence[mxr_tally], hits: mxr_hits, stream=None) -> None:
+    arr = (mxr_tally * max(1, len(tallies)))(*tallies)
+    _check(lib.mxr_collect(handle, first_ray, n_rays, n_total, seed, purpose, job, arr, len(tallies),
+                           ctypes.byref(hits), _stream_handle(stream)))
+
+
+def _d3(v):
+    return (ctypes.c_double * 3)(*[float(x) for x in v])
+
+
+def mxr_mlp_workspace_bytes(batch: int) -> int:
+    return int(lib.mxr_mlp_workspace_bytes(batch))
+
+
+def mxr_mlp_workspace_layout(batch: int) -> List[int]:
+    off = (ctypes.c_uint64 * len(WS_REGIONS))()
+    _check(lib.mxr_mlp_workspace_layout(batch, off))
+    return [int(x) for x in off]
+
+
+def mxr_mlp_to_bf16(x_ptr: int, n: int, y_ptr: int, stream=None) -> None:
+    _check(lib.mxr_mlp_to_bf16(x_ptr, n, y_ptr, _stream_handle(stream)))
+
+
+def mxr_mlp_forward(w_ptr, ctx_ptr, n, out_ptr, ws_ptr, ws_bytes, stream=None) -> None:
+    _check(lib.mxr_mlp_forward(w_ptr, ctx_ptr, n, out_ptr, ws_ptr, ws_bytes, _stream_handle(stream)))
+
+
+def mxr_mlp_mixture(out_ptr, n, lo, hi, gmm_ptr, stream=None) -> None:
+    _check(lib.mxr_mlp_mixture(out_ptr, n, _d3(lo), _d3(hi), gmm_ptr, _stream_handle(stream)))
+
+
+def mxr_mlp_loss_grad(w_ptr, ctx_ptr, y_ptr, omega_ptr, n, lo, hi, grad_ptr, loss_ptr, ws_ptr, ws_bytes,
+                      stream=None) -> None:
+    _check(lib.mxr_mlp_loss_grad(w_ptr, ctx_ptr, y_ptr, omega_ptr, n, _d3(lo), _d3(hi), grad_ptr, loss_ptr, ws_ptr,
+                                 ws_bytes, _stream_handle(stream)))
+
+
+def mxr_adam_step(master, w, grad, m, v, n_params, step, lr, beta1, beta2, eps, stream=None) -> None:
+    _check(lib.mxr_adam_step(master, w, grad, m, v, n_params, step, lr, beta1, beta2, eps, _stream_handle(stream)))
+
+
+def mxr_train_weights(w, bin_, n, sum_w, n_bins, floor_frac, omega, scratch, stream=None) -> None:
+    _check(lib.mxr_train_weights(w, bin_, n, sum_w, n_bins, floor_frac, omega, scratch, _stream_handle(stream)))
+
+
+def mxr_mlp_train(ctx, y, omega, n_rows, cfg: mxr_train_cfg, lo, hi, master, w, m, v, grad, ws, ws_bytes, loss_log,
+                  stream=None) -> None:
+    _check(lib.mxr_mlp_train(ctx, y, omega, n_rows, ctypes.byref(cfg), _d3(lo), _d3(hi), master, w, m, v, grad, ws,
+                             ws_bytes, loss_log, _stream_handle(stream)))
 
 
 def mxr_batch_create(jobs: Sequence[mxr_batch_job], schedule: Optional[mxr_batch_schedule] = None) -> int:
@@ -348,6 +460,42 @@ class Instrument:
                 ledger.data_ptr() if ledger is not None else None, stream)
         return tallies
 
+    def set_proposal(self, gmm=None, alpha: float = 0.1) -> None:
+        """Draw the cone-beam source from the proposal mixture ``gmm`` (a
+        device tensor of 56 float64: 8 x (pi, mu_u, mu_v, mu_E, sigma_u,
+        sigma_v, sigma_E)), or switch it off with None."""
+        if gmm is None:
+            mxr_proposal_set(self.handle, None, alpha)
+            return
+        assert gmm.dtype.is_floating_point and gmm.numel() == 56 and gmm.is_cuda
+        g = gmm.reshape(56).to(dtype=__import__("torch").float64).contiguous()
+        mxr_proposal_set(self.handle, g.data_ptr(), alpha)
+
+    def new_hits(self, capacity: int):
+        """Device buffers for ``capacity`` collected rows and a zeroed counter."""
+        import torch
+        dev = self.device
+        return {"ctx": torch.empty(capacity, 6, dtype=torch.float32, device=dev),
+                "y": torch.empty(capacity, 3, dtype=torch.float64, device=dev),
+                "w": torch.empty(capacity, dtype=torch.float64, device=dev),
+                "bin": torch.empty(capacity, dtype=torch.int64, device=dev),
+                "count": torch.zeros(1, dtype=torch.int64, device=dev),
+                "capacity": capacity}
+
+    def collect(self, n_rays: int, seed: int, context, hits, first_ray: int = 0, n_total: Optional[int] = None,
+                purpose: int = 0, job: int = 0, tallies=None, stream=None):
+        """mxr_run that appends every detected ray to ``hits`` (see new_hits)."""
+        n_total = n_rays if n_total is None else n_total
+        if tallies is None:
+            tallies = self.new_tallies()
+        h = mxr_hits(hits["ctx"].data_ptr(), hits["y"].data_ptr(), hits["w"].data_ptr(), hits["bin"].data_ptr(),
+                     hits["capacity"], hits["count"].data_ptr())
+        for i in range(6):
+            h.context[i] = float(context[i])
+        mxr_collect(self.handle, first_ray, n_rays, n_total, seed, purpose, job, self.tally_structs(tallies), h,
+                    stream)
+        return tallies
+
     def new_ledger(self):
         import torch
         return torch.zeros(4 * self.n_components + 1, dtype=torch.float64, device=self.device)
@@ -373,7 +521,8 @@ class Batch:
     of every phantom of a CT acquisition) traced by one captured launch.
 
     ``jobs`` is a list of (Instrument, n_rays, seed, job, tallies); the
-    instruments and tallies must stay alive as long as the batch."""
+    instruments and tallies must stay alive as long as the batch.  A
+    schedule is (form, groups_per_cu, tile_rays, branches)."""
 
     def __init__(self, jobs, schedule=None):
         self._keep = [(j[0], j[4]) for j in jobs]
@@ -394,7 +543,7 @@ class Batch:
     @property
     def schedule(self):
         s = mxr_batch_get_schedule(self.handle)
-        return (s.groups_per_cu, s.tile_rays)
+        return (s.form, s.groups_per_cu, s.tile_rays, s.branches)
 
     @schedule.setter
     def schedule(self, value) -> None:
@@ -403,7 +552,7 @@ class Batch:
     def autotune(self, rays_fraction: float, cache_path: Optional[str] = None):
         """Pick the fastest launch shape (timing runs add into the tallies)."""
         s = mxr_batch_autotune(self.handle, rays_fraction, cache_path)
-        return (s.groups_per_cu, s.tile_rays)
+        return (s.form, s.groups_per_cu, s.tile_rays, s.branches)
 
     def close(self) -> None:
         h = getattr(self, "handle", None)
@@ -416,3 +565,91 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def source_box(source: Dict):
+    """(lo, hi) of the proposal box of a cone-beam source dict."""
+    import math
+    t = math.tan(source["half_angle"])
+    return (-t, -t, float(source["emin"])), (t, t, float(source["emax"]))
+
+
+class ProposalNet:
+    """The proposal network's device state: float32 master parameters, their
+    bfloat16 working copy, Adam moments, a gradient buffer and a workspace
+    for batches of up to ``batch`` rows (torch tensors own the memory; every
+    computation is a library call)."""
+
+    def __init__(self, params, batch: int, device=None):
+        import torch
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        p = torch.as_tensor(np.asarray(params, dtype=np.float32)).to(self.device)
+        assert p.numel() == MLP_PARAMS
+        self.master = p.contiguous()
+        self.w = torch.empty(MLP_PARAMS, dtype=torch.bfloat16, device=self.device)
+        self.m = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        self.v = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        self.grad = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self.batch = batch
+        self.ws_bytes = mxr_mlp_workspace_bytes(batch)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.step = 0
+        mxr_mlp_to_bf16(self.master.data_ptr(), MLP_PARAMS, self.w.data_ptr())
+
+    def region(self, name: str, n: int, dtype, width: int):
+        """View of workspace region ``name`` as an (n, width) tensor, laid out
+        for a batch of n rows."""
+        import torch
+        off = mxr_mlp_workspace_layout(n)[WS_REGIONS.index(name)]
+        item = torch.empty(0, dtype=dtype).element_size()
+        return self.ws[off:off + n * width * item].view(dtype).view(n, width)
+
+    def forward(self, ctx, stream=None):
+        import torch
+        n = ctx.shape[0]
+        assert n <= self.batch
+        out = torch.empty(n, MLP_OUT, dtype=torch.float32, device=self.device)
+        mxr_mlp_forward(self.w.data_ptr(), ctx.contiguous().data_ptr(), n, out.data_ptr(), self.ws.data_ptr(),
+                        self.ws_bytes, stream)
+        return out
+
+    def mixture(self, out, lo, hi, stream=None):
+        import torch
+        g = torch.empty(out.shape[0], MLP_OUT, dtype=torch.float64, device=self.device)
+        mxr_mlp_mixture(out.contiguous().data_ptr(), out.shape[0], lo, hi, g.data_ptr(), stream)
+        return g
+
+    def loss_grad(self, ctx, y, omega, lo, hi, stream=None):
+        n = ctx.shape[0]
+        assert n <= self.batch
+        mxr_mlp_loss_grad(self.w.data_ptr(), ctx.contiguous().data_ptr(), y.contiguous().data_ptr(),
+                          omega.contiguous().data_ptr(), n, lo, hi, self.grad.data_ptr(), self.loss.data_ptr(),
+                          self.ws.data_ptr(), self.ws_bytes, stream)
+        return self.loss, self.grad
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self.step += 1
+        mxr_adam_step(self.master.data_ptr(), self.w.data_ptr(), self.grad.data_ptr(), self.m.data_ptr(),
+                      self.v.data_ptr(), MLP_PARAMS, self.step, lr, beta1, beta2, eps, stream)
+
+    def train(self, ctx, y, omega, lo, hi, epochs: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed: int = 1,
+              loss_log=None, stream=None):
+        n = ctx.shape[0]
+        cfg = mxr_train_cfg(lr, beta1, beta2, eps, self.batch, epochs, seed, self.step)
+        mxr_mlp_train(ctx.contiguous().data_ptr(), y.contiguous().data_ptr(), omega.contiguous().data_ptr(), n, cfg,
+                      lo, hi, self.master.data_ptr(), self.w.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                      self.grad.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
+                      loss_log.data_ptr() if loss_log is not None else None, stream)
+        self.step += epochs * ((n + min(self.batch, n) - 1) // min(self.batch, n))
+
+
+def train_weights(hits, count: int, sum_w, floor_frac: float = 1e-3, stream=None):
+    """omega of the first ``count`` collected rows (see mxr_train_weights)."""
+    import torch
+    dev = sum_w.device
+    omega = torch.empty(count, dtype=torch.float64, device=dev)
+    scratch = torch.empty(2 * 256 + 1, dtype=torch.float64, device=dev)
+    mxr_train_weights(hits["w"].data_ptr(), hits["bin"].data_ptr(), count, sum_w.data_ptr(), sum_w.numel(),
+                      floor_frac, omega.data_ptr(), scratch.data_ptr(), stream)
+    return omega

@@ -1,0 +1,726 @@
+// mlp.hip -- the learned proposal's network on the matrix cores: a
+// 6 -> 128 -> 128 -> 56 MLP (SiLU) in bfloat16 with float32 accumulation,
+// the mixture head and its weighted negative log-likelihood in float32,
+// split-K weight gradients, Adam with float32 master weights, training-data
+// weights and the training loop.
+//
+// Every product of the network is a dense contraction, so it runs on MFMA:
+// v_mfma_f32_16x16x16_bf16 with one wave per 16 x 16 output tile.  Operands
+// are read from HBM / L2 through strides, so one kernel serves the forward
+// products (activations x W), the input gradients (dZ x W^T) and the weight
+// gradients (X^T x dZ, split over row chunks and reduced in a fixed order,
+// so a gradient is deterministic).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "mxr.h"
+
+namespace mxr_host {
+mxr_status set_error(mxr_status st, const char *msg);
+}
+
+namespace {
+
+constexpr int kIn = MXR_MLP_IN, kHid = MXR_MLP_HIDDEN, kOut = MXR_MLP_OUT;
+constexpr uint64_t kW1 = 0, kB1 = kW1 + kIn * kHid, kW2 = kB1 + kHid, kB2 = kW2 + kHid * kHid;
+constexpr uint64_t kW3 = kB2 + kHid, kB3 = kW3 + kHid * kOut, kParams = kB3 + kOut;
+static_assert(kParams == MXR_MLP_PARAMS, "parameter layout");
+constexpr uint64_t kSplitRows = 1024;  // rows per split of a weight-gradient product
+constexpr int kThreads = 256;
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+mxr_status fail(mxr_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+mxr_status fail(mxr_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return mxr_host::set_error(st, buf);
+}
+
+mxr_status launch_check(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MXR_E_HIP, "%s: %s", what, hipGetErrorString(e));
+    return MXR_OK;
+}
+
+// ------------------------------------------------------------ bfloat16 --
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t b = __float_as_uint(f);
+    if ((b & 0x7F800000u) == 0x7F800000u) return (uint16_t)((b >> 16) | ((b & 0xFFFFu) ? 0x40u : 0u));  // inf/nan
+    b += 0x7FFFu + ((b >> 16) & 1u);  // round to nearest, ties to even
+    return (uint16_t)(b >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
+
+__device__ __forceinline__ float silu_grad(float z) {
+    const float s = 1.0f / (1.0f + expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// ---------------------------------------------------------------- GEMM --
+
+enum Epi { kEpiHidden = 0, kEpiOut, kEpiBackward, kEpiPartial };
+
+struct GemmArgs {
+    const uint16_t *A;  // A(m, k) = A[m * sam + k * sak]
+    const uint16_t *B;  // B(k, n) = B[k * sbk + n * sbn]
+    int64_t sam, sak, sbk, sbn;
+    int64_t M, N, K;
+    int64_t kchunk;        // contraction range per split (blockIdx.z)
+    const uint16_t *bias;  // kEpiHidden / kEpiOut: bias[n] (bfloat16)
+    float *Z;              // kEpiHidden: pre-activation out; kEpiBackward: pre-activation in
+    uint16_t *H;           // kEpiHidden: silu(Z) out; kEpiBackward: dZ (bfloat16) out
+    float *C;              // kEpiOut: output; kEpiBackward: dZ (float32) out; kEpiPartial: partial base
+    int64_t ldc;           // row stride of C / Z / H
+    int64_t split_stride;  // kEpiPartial: floats between the partials of consecutive splits
+};
+
+// One wave per 16 x 16 tile of C, four waves per work-group along M.  The
+// 16x16x16 bf16 MFMA takes from lane l the row (A) or column (B) l mod 16
+// and the four consecutive k = 4 (l / 16) .. 4 (l / 16) + 3, and leaves in
+// lane l the four outputs of rows 4 (l / 16) .. +3 in column l mod 16.
+template <int EPI>
+__global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t tm = (int64_t)blockIdx.y * 4 + wave, tn = blockIdx.x;
+    if (tm * 16 >= g.M) return;  // whole wave: no barrier in this kernel
+    const int64_t k0 = (int64_t)blockIdx.z * g.kchunk;
+    const int64_t k1 = std::min<int64_t>(k0 + g.kchunk, g.K);
+    const int r = lane & 15, q = lane >> 4;
+    const int64_t m = tm * 16 + r, n = tn * 16 + r;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t kb = k0; kb < k1; kb += 16) {
+        v4s a, b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t k = kb + 4 * q + j;
+            a[j] = (m < g.M && k < k1) ? (short)g.A[m * g.sam + k * g.sak] : (short)0;
+            b[j] = (n < g.N && k < k1) ? (short)g.B[k * g.sbk + n * g.sbn] : (short)0;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t mm = tm * 16 + 4 * q + j, nn = tn * 16 + r;
+        if (mm >= g.M || nn >= g.N) continue;
+        const float v = acc[j];
+        if constexpr (EPI == kEpiHidden) {
+            const float z = v + bf16_to_f32(g.bias[nn]);
+            g.Z[mm * g.ldc + nn] = z;
+            g.H[mm * g.ldc + nn] = f32_to_bf16(silu(z));
+        } else if constexpr (EPI == kEpiOut) {
+            g.C[mm * g.ldc + nn] = v + bf16_to_f32(g.bias[nn]);
+        } else if constexpr (EPI == kEpiBackward) {
+            const float dz = v * silu_grad(g.Z[mm * g.ldc + nn]);
+            g.C[mm * g.ldc + nn] = dz;
+            g.H[mm * g.ldc + nn] = f32_to_bf16(dz);
+        } else {
+            g.C[(int64_t)blockIdx.z * g.split_stride + mm * g.ldc + nn] = v;
+        }
+    }
+}
+
+mxr_status gemm(int epi, const GemmArgs &g, int64_t splits, hipStream_t st) {
+    if (g.M == 0 || g.N == 0) return MXR_OK;
+    const dim3 grid((unsigned)((g.N + 15) / 16), (unsigned)((g.M + 63) / 64), (unsigned)splits);
+    switch (epi) {
+        case kEpiHidden: hipLaunchKernelGGL(k_gemm<kEpiHidden>, grid, dim3(kThreads), 0, st, g); break;
+        case kEpiOut: hipLaunchKernelGGL(k_gemm<kEpiOut>, grid, dim3(kThreads), 0, st, g); break;
+        case kEpiBackward: hipLaunchKernelGGL(k_gemm<kEpiBackward>, grid, dim3(kThreads), 0, st, g); break;
+        default: hipLaunchKernelGGL(k_gemm<kEpiPartial>, grid, dim3(kThreads), 0, st, g); break;
+    }
+    return launch_check("MLP product");
+}
+
+// ------------------------------------------------------ small kernels --
+
+// Rows of a batch: row i of the batch is dataset row (a i + b) mod n_data
+// (a coprime to n_data: a bijection, a cheap shuffle per epoch; a, b and
+// the row index below n_data < 2^32); the identity is a = 1, b = 0.  Contexts go to bfloat16, targets and weights
+// are copied.
+__global__ void k_gather(const float *ctx, const double *y, const double *omega, uint64_t n_data, uint64_t a,
+                         uint64_t b, uint64_t first, uint64_t n, uint16_t *X, double *Yb, double *Wb) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t src = ((a * (first + i)) % n_data + b) % n_data;  // n_data < 2^32: no overflow
+    for (int j = 0; j < kIn; ++j) X[i * kIn + j] = f32_to_bf16(ctx[src * kIn + j]);
+    if (Yb) {
+        for (int j = 0; j < 3; ++j) Yb[i * 3 + j] = y[src * 3 + j];
+        Wb[i] = omega[src];
+    }
+}
+
+// Deterministic sums: each work-group sums its stride of the input into one
+// partial; a second launch with one work-group sums the partials in order.
+__global__ void k_sum_f64(const double *x, uint64_t n, double *partial) {
+    __shared__ double red[kThreads];
+    double s = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kThreads)
+        s += x[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+constexpr unsigned kSumBlocks = 256;
+
+mxr_status sum_f64(const double *x, uint64_t n, double *scratch, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_f64, dim3(kSumBlocks), dim3(kThreads), 0, st, x, n, scratch);
+    hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(kThreads), 0, st, (const double *)scratch, (uint64_t)kSumBlocks, out);
+    return launch_check("sum");
+}
+
+// The mixture head and the weighted negative log-likelihood of one row per
+// thread, in float32.  Head: pi = softmax(logits), mu = centre + half tanh,
+// sigma = half (1e-3 + softplus).  -log q = -logsumexp_k(log pi_k +
+// sum_d log N(y_d; mu, sigma)) + log sum_k pi_k Z_k.  Writes dL/do scaled by
+// a_i = omega_i / sum omega (float32 and bfloat16) and a_i (-log q_i).
+struct HeadArgs {
+    const float *O;  // n x 56
+    const double *Y;
+    const double *W;
+    const double *wsum;
+    uint64_t n;
+    float lo[3], hi[3];
+    float *dO;
+    uint16_t *dOh;
+    double *row_loss;
+};
+
+__device__ __forceinline__ float phi_pdf(float z) { return 0.3989422804014327f * expf(-0.5f * z * z); }
+
+// mass of a standard normal in [za, zb], from the side that does not cancel
+__device__ __forceinline__ float box_mass(float za, float zb) {
+    if (za > 0.f) return 0.5f * (erfcf(za * 0.70710678f) - erfcf(zb * 0.70710678f));
+    if (zb < 0.f) return 0.5f * (erfcf(-zb * 0.70710678f) - erfcf(-za * 0.70710678f));
+    return 1.0f - 0.5f * (erfcf(-za * 0.70710678f) + erfcf(zb * 0.70710678f));
+}
+
+__global__ __launch_bounds__(kThreads) void k_head_loss_grad(HeadArgs h) {
+    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= h.n) return;
+    const float *o = h.O + i * kOut;
+    const float a = (float)(h.W[i] / *h.wsum);
+    float y[3];
+    for (int d = 0; d < 3; ++d) y[d] = (float)h.Y[i * 3 + d];
+    float mx = -INFINITY;
+    for (int k = 0; k < 8; ++k) mx = fmaxf(mx, o[7 * k]);
+    float se = 0.f;
+    for (int k = 0; k < 8; ++k) se += expf(o[7 * k] - mx);
+    const float lse_logit = mx + logf(se);
+    float comp[8], pi[8], Z[8];
+    float cmax = -INFINITY;
+    for (int k = 0; k < 8; ++k) {
+        pi[k] = expf(o[7 * k] - lse_logit);
+        float c = o[7 * k] - lse_logit, zk = 1.f;
+        for (int d = 0; d < 3; ++d) {
+            const float cen = 0.5f * (h.lo[d] + h.hi[d]), half = 0.5f * (h.hi[d] - h.lo[d]);
+            const float mu = cen + half * tanhf(o[7 * k + 1 + d]);
+            const float raw = o[7 * k + 4 + d];
+            const float sp = raw > 20.f ? raw : log1pf(expf(raw));
+            const float sg = half * (1e-3f + sp);
+            const float z = (y[d] - mu) / sg;
+            c += -0.5f * z * z - logf(sg) - 0.91893853f;
+            zk *= box_mass((h.lo[d] - mu) / sg, (h.hi[d] - mu) / sg);
+        }
+        comp[k] = c;
+        Z[k] = zk;
+        cmax = fmaxf(cmax, c);
+    }
+    float sr = 0.f, S = 0.f;
+    for (int k = 0; k < 8; ++k) {
+        sr += expf(comp[k] - cmax);
+        S += pi[k] * Z[k];
+    }
+    const float lse = cmax + logf(sr);
+    h.row_loss[i] = (double)(a * (logf(S) - lse));
+    for (int k = 0; k < 8; ++k) {
+        const float r = expf(comp[k] - lse);
+        const float s = pi[k] * Z[k] / S;
+        float g[7];
+        g[0] = s - r;
+        for (int d = 0; d < 3; ++d) {
+            const float half = 0.5f * (h.hi[d] - h.lo[d]), cen = 0.5f * (h.lo[d] + h.hi[d]);
+            const float t = tanhf(o[7 * k + 1 + d]);
+            const float mu = cen + half * t;
+            const float raw = o[7 * k + 4 + d];
+            const float sp = raw > 20.f ? raw : log1pf(expf(raw));
+            const float sg = half * (1e-3f + sp);
+            const float z = (y[d] - mu) / sg;
+            const float za = (h.lo[d] - mu) / sg, zb = (h.hi[d] - mu) / sg;
+            const float F = box_mass(za, zb);
+            const float pa = phi_pdf(za), pb = phi_pdf(zb);
+            const float dF_mu = -(pb - pa) / sg;
+            const float dF_sg = -(zb * pb - za * pa) / sg;
+            const float g_mu = -r * z / sg + s * dF_mu / F;
+            const float g_sg = -r * (z * z - 1.f) / sg + s * dF_sg / F;
+            g[1 + d] = g_mu * half * (1.f - t * t);
+            g[4 + d] = g_sg * half / (1.f + expf(-raw));
+        }
+        for (int j = 0; j < 7; ++j) {
+            const float v = a * g[j];
+            h.dO[i * kOut + 7 * k + j] = v;
+            h.dOh[i * kOut + 7 * k + j] = f32_to_bf16(v);
+        }
+    }
+}
+
+// Mixture tables for the tracer from head outputs: per row and component
+// (pi, mu_u, mu_v, mu_E, sigma_u, sigma_v, sigma_E), computed in float32
+// like the training head and stored as float64.
+__global__ void k_head_params(const float *O, uint64_t n, float lo0, float lo1, float lo2, float hi0, float hi1,
+                              float hi2, double *gmm) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float lo[3] = {lo0, lo1, lo2}, hi[3] = {hi0, hi1, hi2};
+    const float *o = O + i * kOut;
+    float mx = -INFINITY;
+    for (int k = 0; k < 8; ++k) mx = fmaxf(mx, o[7 * k]);
+    float se = 0.f;
+    for (int k = 0; k < 8; ++k) se += expf(o[7 * k] - mx);
+    const float lse = mx + logf(se);
+    for (int k = 0; k < 8; ++k) {
+        double *g = gmm + i * kOut + 7 * k;
+        g[0] = (double)expf(o[7 * k] - lse);
+        for (int d = 0; d < 3; ++d) {
+            const float cen = 0.5f * (lo[d] + hi[d]), half = 0.5f * (hi[d] - lo[d]);
+            const float raw = o[7 * k + 4 + d];
+            const float sp = raw > 20.f ? raw : log1pf(expf(raw));
+            g[1 + d] = (double)(cen + half * tanhf(o[7 * k + 1 + d]));
+            g[4 + d] = (double)(half * (1e-3f + sp));
+        }
+    }
+}
+
+// Bias gradients of one split: column sums of a float32 matrix over the
+// split's rows, into the split's partial.
+__global__ void k_colsum_partial(const float *X, int64_t n_rows, int64_t n_cols, int64_t ld, int64_t rows_per_split,
+                                 float *partial, int64_t split_stride) {
+    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= n_cols) return;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+    const int64_t r1 = std::min<int64_t>(r0 + rows_per_split, n_rows);
+    float s = 0.f;
+    for (int64_t r = r0; r < r1; ++r) s += X[r * ld + col];
+    partial[(int64_t)blockIdx.y * split_stride + col] = s;
+}
+
+// gradient[p] = sum over splits, in split order
+__global__ void k_reduce_partials(const float *partial, int64_t splits, float *grad) {
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kParams) return;
+    float s = 0.f;
+    for (int64_t z = 0; z < splits; ++z) s += partial[z * (int64_t)kParams + p];
+    grad[p] = s;
+}
+
+__global__ void k_adam(float *theta, uint16_t *wb, const float *g, float *m, float *v, uint64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float t = theta[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    theta[i] = t;
+    wb[i] = f32_to_bf16(t);
+}
+
+__global__ void k_to_bf16(const float *x, uint64_t n, uint16_t *y) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f32_to_bf16(x[i]);
+}
+
+// Training weights omega_i = w_i / max(I_b, floor), I_b = sum_w[b] / n_emitted
+// the bin's estimated intensity, floor = floor_frac * (mean I over bins with
+// hits): every live bin gets equal total weight, the proposal that makes the
+// per-bin relative errors equal when weights within a bin are alike.
+__global__ void k_bin_stats(const double *sum_w, uint64_t n_bins, double *partial) {
+    __shared__ double rs[kThreads], rc[kThreads];
+    double s = 0.0, c = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < n_bins; i += (uint64_t)gridDim.x * kThreads) {
+        if (sum_w[i] > 0.0) {
+            s += sum_w[i];
+            c += 1.0;
+        }
+    }
+    rs[threadIdx.x] = s;
+    rc[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            rs[threadIdx.x] += rs[threadIdx.x + w];
+            rc[threadIdx.x] += rc[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = rs[0];
+        partial[2 * blockIdx.x + 1] = rc[0];
+    }
+}
+
+__global__ void k_bin_stats_final(const double *partial, unsigned n_part, double *out) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0, c = 0.0;
+    for (unsigned i = 0; i < n_part; ++i) {
+        s += partial[2 * i];
+        c += partial[2 * i + 1];
+    }
+    out[0] = c > 0.0 ? s / c : 0.0;  // mean sum_w over bins with hits
+}
+
+__global__ void k_train_weights(const double *w, const int64_t *bin, uint64_t n, const double *sum_w, uint64_t n_bins,
+                                const double *mean_live, double floor_frac, double *omega) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t b = bin[i];
+    const double Ib = (b >= 0 && (uint64_t)b < n_bins) ? sum_w[b] : 0.0;
+    const double den = fmax(Ib, floor_frac * *mean_live);
+    omega[i] = den > 0.0 ? w[i] / den : 0.0;
+}
+
+unsigned blocks_for(uint64_t n) { return (unsigned)std::max<uint64_t>(1, (n + kThreads - 1) / kThreads); }
+
+// ------------------------------------------------------------ workspace --
+
+struct Layout {
+    uint64_t off[MXR_MLP_WS_REGIONS];
+    uint64_t bytes;
+};
+
+uint64_t splits_for(uint64_t n) { return std::max<uint64_t>(1, (n + kSplitRows - 1) / kSplitRows); }
+
+Layout layout_for(uint64_t n) {
+    const uint64_t sizes[MXR_MLP_WS_REGIONS] = {
+        n * kIn * 2,                    // X (bf16)
+        n * kHid * 4, n * kHid * 2,     // Z1, H1
+        n * kHid * 4, n * kHid * 2,     // Z2, H2
+        n * kOut * 4,                   // O
+        n * kOut * 4, n * kOut * 2,     // dO, dO (bf16)
+        n * kHid * 4, n * kHid * 2,     // dZ2, dZ2 (bf16)
+        n * kHid * 4, n * kHid * 2,     // dZ1, dZ1 (bf16)
+        splits_for(n) * kParams * 4,    // split partials of the gradient
+        n * 3 * 8, n * 8, n * 8,        // gathered targets, weights, per-row loss
+        (kSumBlocks + 2) * 8,           // reduction scratch + sum of weights + loss
+    };
+    Layout L;
+    uint64_t o = 0;
+    for (int i = 0; i < MXR_MLP_WS_REGIONS; ++i) {
+        L.off[i] = o;
+        o += (sizes[i] + 255) / 256 * 256;
+    }
+    L.bytes = o;
+    return L;
+}
+
+template <class T>
+T *at(void *ws, const Layout &L, int region) {
+    return (T *)((char *)ws + L.off[region]);
+}
+
+mxr_status check_device_ptrs(std::initializer_list<const void *> ps) {
+    for (const void *p : ps)
+        if (!p) return fail(MXR_E_INVALID, "null array");
+    return MXR_OK;
+}
+
+// forward of the n rows already gathered into the workspace (X)
+mxr_status forward_ws(const uint16_t *w, uint64_t n, void *ws, const Layout &L, hipStream_t st) {
+    GemmArgs g{};
+    g.M = (int64_t)n;
+    g.kchunk = 1 << 30;
+    // layer 1: X (n x 6) W1 (6 x 128)
+    g.A = at<uint16_t>(ws, L, MXR_MLP_WS_X), g.sam = kIn, g.sak = 1;
+    g.B = w + kW1, g.sbk = kHid, g.sbn = 1;
+    g.N = kHid, g.K = kIn, g.bias = w + kB1;
+    g.Z = at<float>(ws, L, MXR_MLP_WS_Z1), g.H = at<uint16_t>(ws, L, MXR_MLP_WS_H1), g.ldc = kHid;
+    mxr_status s = gemm(kEpiHidden, g, 1, st);
+    if (s != MXR_OK) return s;
+    // layer 2: H1 W2
+    g.A = at<uint16_t>(ws, L, MXR_MLP_WS_H1), g.sam = kHid, g.sak = 1;
+    g.B = w + kW2, g.sbk = kHid, g.sbn = 1;
+    g.N = kHid, g.K = kHid, g.bias = w + kB2;
+    g.Z = at<float>(ws, L, MXR_MLP_WS_Z2), g.H = at<uint16_t>(ws, L, MXR_MLP_WS_H2);
+    s = gemm(kEpiHidden, g, 1, st);
+    if (s != MXR_OK) return s;
+    // layer 3: H2 W3 + b3 -> O
+    g.A = at<uint16_t>(ws, L, MXR_MLP_WS_H2);
+    g.B = w + kW3, g.sbk = kOut, g.sbn = 1;
+    g.N = kOut, g.K = kHid, g.bias = w + kB3;
+    g.C = at<float>(ws, L, MXR_MLP_WS_O), g.ldc = kOut;
+    return gemm(kEpiOut, g, 1, st);
+}
+
+// loss and gradient of the n rows gathered into the workspace
+mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const float hi[3], float *grad,
+                        double *loss, void *ws, const Layout &L, hipStream_t st) {
+    mxr_status s = forward_ws(w, n, ws, L, st);
+    if (s != MXR_OK) return s;
+    double *red = at<double>(ws, L, MXR_MLP_WS_SCALARS);
+    double *wsum = red + kSumBlocks;
+    s = sum_f64(at<double>(ws, L, MXR_MLP_WS_W), n, red, wsum, st);
+    if (s != MXR_OK) return s;
+    HeadArgs h;
+    h.O = at<float>(ws, L, MXR_MLP_WS_O);
+    h.Y = at<double>(ws, L, MXR_MLP_WS_Y);
+    h.W = at<double>(ws, L, MXR_MLP_WS_W);
+    h.wsum = wsum;
+    h.n = n;
+    for (int d = 0; d < 3; ++d) {
+        h.lo[d] = lo[d];
+        h.hi[d] = hi[d];
+    }
+    h.dO = at<float>(ws, L, MXR_MLP_WS_DO);
+    h.dOh = at<uint16_t>(ws, L, MXR_MLP_WS_DOH);
+    h.row_loss = at<double>(ws, L, MXR_MLP_WS_ROWLOSS);
+    hipLaunchKernelGGL(k_head_loss_grad, dim3(blocks_for(n)), dim3(kThreads), 0, st, h);
+    if ((s = launch_check("head")) != MXR_OK) return s;
+    if (loss) {
+        s = sum_f64(h.row_loss, n, red, loss, st);
+        if (s != MXR_OK) return s;
+    }
+    const int64_t splits = (int64_t)splits_for(n);
+    float *part = at<float>(ws, L, MXR_MLP_WS_PARTIAL);
+    GemmArgs g{};
+    g.kchunk = kSplitRows;
+    g.K = (int64_t)n;
+    g.C = part;
+    g.split_stride = kParams;
+    // dW3 = H2^T dO  (128 x 56)
+    g.A = at<uint16_t>(ws, L, MXR_MLP_WS_H2), g.sam = 1, g.sak = kHid;
+    g.B = h.dOh, g.sbk = kOut, g.sbn = 1;
+    g.M = kHid, g.N = kOut, g.ldc = kOut;
+    g.C = part + kW3;
+    if ((s = gemm(kEpiPartial, g, splits, st)) != MXR_OK) return s;
+    // dZ2 = (dO W3^T) * silu'(Z2)
+    GemmArgs b{};
+    b.kchunk = 1 << 30;
+    b.M = (int64_t)n, b.N = kHid, b.K = kOut;
+    b.A = h.dOh, b.sam = kOut, b.sak = 1;
+    b.B = w + kW3, b.sbk = 1, b.sbn = kOut;
+    b.Z = at<float>(ws, L, MXR_MLP_WS_Z2);
+    b.C = at<float>(ws, L, MXR_MLP_WS_DZ2), b.H = at<uint16_t>(ws, L, MXR_MLP_WS_DZ2H), b.ldc = kHid;
+    if ((s = gemm(kEpiBackward, b, 1, st)) != MXR_OK) return s;
+    // dW2 = H1^T dZ2
+    g.A = at<uint16_t>(ws, L, MXR_MLP_WS_H1), g.sam = 1, g.sak = kHid;
+    g.B = at<uint16_t>(ws, L, MXR_MLP_WS_DZ2H), g.sbk = kHid, g.sbn = 1;
+    g.M = kHid, g.N = kHid, g.ldc = kHid;
+    g.C = part + kW2;
+    if ((s = gemm(kEpiPartial, g, splits, st)) != MXR_OK) return s;
+    // dZ1 = (dZ2 W2^T) * silu'(Z1)
+    b.K = kHid;
+    b.A = at<uint16_t>(ws, L, MXR_MLP_WS_DZ2H), b.sam = kHid, b.sak = 1;
+    b.B = w + kW2, b.sbk = 1, b.sbn = kHid;
+    b.Z = at<float>(ws, L, MXR_MLP_WS_Z1);
+    b.C = at<float>(ws, L, MXR_MLP_WS_DZ1), b.H = at<uint16_t>(ws, L, MXR_MLP_WS_DZ1H);
+    if ((s = gemm(kEpiBackward, b, 1, st)) != MXR_OK) return s;
+    // dW1 = X^T dZ1
+    g.A = at<uint16_t>(ws, L, MXR_MLP_WS_X), g.sam = 1, g.sak = kIn;
+    g.B = at<uint16_t>(ws, L, MXR_MLP_WS_DZ1H), g.sbk = kHid, g.sbn = 1;
+    g.M = kIn, g.N = kHid, g.ldc = kHid;
+    g.C = part + kW1;
+    if ((s = gemm(kEpiPartial, g, splits, st)) != MXR_OK) return s;
+    // bias gradients: column sums of dO, dZ2, dZ1 per split
+    const dim3 cg1((kOut + 63) / 64, (unsigned)splits), cg2((kHid + 63) / 64, (unsigned)splits);
+    hipLaunchKernelGGL(k_colsum_partial, cg1, dim3(64), 0, st, (const float *)h.dO, (int64_t)n, (int64_t)kOut,
+                       (int64_t)kOut, (int64_t)kSplitRows, part + kB3, (int64_t)kParams);
+    hipLaunchKernelGGL(k_colsum_partial, cg2, dim3(64), 0, st, (const float *)at<float>(ws, L, MXR_MLP_WS_DZ2),
+                       (int64_t)n, (int64_t)kHid, (int64_t)kHid, (int64_t)kSplitRows, part + kB2, (int64_t)kParams);
+    hipLaunchKernelGGL(k_colsum_partial, cg2, dim3(64), 0, st, (const float *)at<float>(ws, L, MXR_MLP_WS_DZ1),
+                       (int64_t)n, (int64_t)kHid, (int64_t)kHid, (int64_t)kSplitRows, part + kB1, (int64_t)kParams);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(kParams)), dim3(kThreads), 0, st, (const float *)part,
+                       splits, grad);
+    return launch_check("gradient reduction");
+}
+
+mxr_status box_ok(const double lo[3], const double hi[3], float flo[3], float fhi[3]) {
+    if (!lo || !hi) return fail(MXR_E_INVALID, "null box");
+    for (int d = 0; d < 3; ++d) {
+        if (!std::isfinite(lo[d]) || !std::isfinite(hi[d]) || !(hi[d] > lo[d]))
+            return fail(MXR_E_INVALID, "box edge %d: need finite lo < hi", d);
+        flo[d] = (float)lo[d];
+        fhi[d] = (float)hi[d];
+    }
+    return MXR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t mxr_mlp_workspace_bytes(uint64_t batch) { return layout_for(batch).bytes; }
+
+mxr_status mxr_mlp_workspace_layout(uint64_t batch, uint64_t *offsets) {
+    if (!offsets) return fail(MXR_E_INVALID, "null offsets");
+    const Layout L = layout_for(batch);
+    for (int i = 0; i < MXR_MLP_WS_REGIONS; ++i) offsets[i] = L.off[i];
+    return MXR_OK;
+}
+
+mxr_status mxr_mlp_to_bf16(const float *x, uint64_t n, uint16_t *y, void *hip_stream) {
+    if (n == 0) return MXR_OK;
+    if (!x || !y) return fail(MXR_E_INVALID, "null array");
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for(n)), dim3(kThreads), 0, (hipStream_t)hip_stream, x, n, y);
+    return launch_check("bfloat16 conversion");
+}
+
+mxr_status mxr_mlp_forward(const uint16_t *w, const float *ctx, uint64_t n, float *out, void *ws, uint64_t ws_bytes,
+                           void *hip_stream) {
+    if (n == 0) return MXR_OK;
+    mxr_status s = check_device_ptrs({w, ctx, out, ws});
+    if (s != MXR_OK) return s;
+    const Layout L = layout_for(n);
+    if (ws_bytes < L.bytes) return fail(MXR_E_INVALID, "workspace of %llu bytes, %llu needed", (unsigned long long)ws_bytes, (unsigned long long)L.bytes);
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(n)), dim3(kThreads), 0, st, ctx, (const double *)nullptr,
+                       (const double *)nullptr, n, (uint64_t)1, (uint64_t)0, (uint64_t)0, n,
+                       at<uint16_t>(ws, L, MXR_MLP_WS_X), (double *)nullptr, (double *)nullptr);
+    if ((s = launch_check("gather")) != MXR_OK) return s;
+    if ((s = forward_ws(w, n, ws, L, st)) != MXR_OK) return s;
+    hipError_t e = hipMemcpyAsync(out, at<float>(ws, L, MXR_MLP_WS_O), n * kOut * sizeof(float),
+                                  hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return fail(MXR_E_HIP, "copy of the outputs: %s", hipGetErrorString(e));
+    return MXR_OK;
+}
+
+mxr_status mxr_mlp_mixture(const float *out, uint64_t n, const double lo[3], const double hi[3], double *gmm,
+                           void *hip_stream) {
+    if (n == 0) return MXR_OK;
+    float flo[3], fhi[3];
+    mxr_status s = box_ok(lo, hi, flo, fhi);
+    if (s != MXR_OK) return s;
+    if ((s = check_device_ptrs({out, gmm})) != MXR_OK) return s;
+    hipLaunchKernelGGL(k_head_params, dim3(blocks_for(n)), dim3(kThreads), 0, (hipStream_t)hip_stream, out, n,
+                       flo[0], flo[1], flo[2], fhi[0], fhi[1], fhi[2], gmm);
+    return launch_check("mixture head");
+}
+
+mxr_status mxr_mlp_loss_grad(const uint16_t *w, const float *ctx, const double *y, const double *omega, uint64_t n,
+                             const double lo[3], const double hi[3], float *grad, double *loss, void *ws,
+                             uint64_t ws_bytes, void *hip_stream) {
+    if (n == 0) return fail(MXR_E_INVALID, "empty batch");
+    float flo[3], fhi[3];
+    mxr_status s = box_ok(lo, hi, flo, fhi);
+    if (s != MXR_OK) return s;
+    if ((s = check_device_ptrs({w, ctx, y, omega, grad, ws})) != MXR_OK) return s;
+    const Layout L = layout_for(n);
+    if (ws_bytes < L.bytes) return fail(MXR_E_INVALID, "workspace of %llu bytes, %llu needed", (unsigned long long)ws_bytes, (unsigned long long)L.bytes);
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(n)), dim3(kThreads), 0, st, ctx, y, omega, n, (uint64_t)1,
+                       (uint64_t)0, (uint64_t)0, n, at<uint16_t>(ws, L, MXR_MLP_WS_X), at<double>(ws, L, MXR_MLP_WS_Y),
+                       at<double>(ws, L, MXR_MLP_WS_W));
+    if ((s = launch_check("gather")) != MXR_OK) return s;
+    return loss_grad_ws(w, n, flo, fhi, grad, loss, ws, L, st);
+}
+
+mxr_status mxr_adam_step(float *master, uint16_t *w, const float *grad, float *m, float *v, uint64_t n_params,
+                         uint32_t step, float lr, float beta1, float beta2, float eps, void *hip_stream) {
+    if (n_params == 0) return MXR_OK;
+    mxr_status s = check_device_ptrs({master, w, grad, m, v});
+    if (s != MXR_OK) return s;
+    if (step < 1) return fail(MXR_E_INVALID, "Adam steps count from 1");
+    if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
+        return fail(MXR_E_INVALID, "bad Adam hyper-parameters");
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, (double)step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, (double)step)));
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n_params)), dim3(kThreads), 0, (hipStream_t)hip_stream, master, w, grad,
+                       m, v, n_params, lr, beta1, beta2, eps, c1, c2);
+    return launch_check("Adam");
+}
+
+mxr_status mxr_train_weights(const double *w, const int64_t *bin, uint64_t n, const double *sum_w, uint64_t n_bins,
+                             double floor_frac, double *omega, double *scratch, void *hip_stream) {
+    if (n == 0) return MXR_OK;
+    mxr_status s = check_device_ptrs({w, bin, sum_w, omega, scratch});
+    if (s != MXR_OK) return s;
+    if (!(floor_frac >= 0.0) || !std::isfinite(floor_frac)) return fail(MXR_E_INVALID, "bad floor fraction");
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_bin_stats, dim3(kSumBlocks), dim3(kThreads), 0, st, sum_w, n_bins, scratch);
+    hipLaunchKernelGGL(k_bin_stats_final, dim3(1), dim3(64), 0, st, (const double *)scratch, kSumBlocks,
+                       scratch + 2 * kSumBlocks);
+    hipLaunchKernelGGL(k_train_weights, dim3(blocks_for(n)), dim3(kThreads), 0, st, w, bin, n, sum_w, n_bins,
+                       (const double *)(scratch + 2 * kSumBlocks), floor_frac, omega);
+    return launch_check("training weights");
+}
+
+mxr_status mxr_mlp_train(const float *ctx, const double *y, const double *omega, uint64_t n_rows,
+                         const mxr_train_cfg *cfg, const double lo[3], const double hi[3], float *master, uint16_t *w,
+                         float *m, float *v, float *grad, void *ws, uint64_t ws_bytes, double *loss_log,
+                         void *hip_stream) {
+    if (!cfg) return fail(MXR_E_INVALID, "null configuration");
+    if (n_rows == 0) return fail(MXR_E_INVALID, "no training rows");
+    if (cfg->batch == 0 || cfg->epochs == 0) return fail(MXR_E_INVALID, "batch and epochs must be positive");
+    if (n_rows >= (1ull << 32)) return fail(MXR_E_UNSUPPORTED, "at most 2^32 - 1 training rows");
+    float flo[3], fhi[3];
+    mxr_status s = box_ok(lo, hi, flo, fhi);
+    if (s != MXR_OK) return s;
+    if ((s = check_device_ptrs({ctx, y, omega, master, w, m, v, grad, ws})) != MXR_OK) return s;
+    const uint64_t B = std::min<uint64_t>(cfg->batch, n_rows);
+    const Layout L = layout_for(B);
+    if (ws_bytes < L.bytes) return fail(MXR_E_INVALID, "workspace of %llu bytes, %llu needed", (unsigned long long)ws_bytes, (unsigned long long)L.bytes);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const uint64_t steps_per_epoch = (n_rows + B - 1) / B;
+    // per-epoch bijections i -> (a i + b) mod n_rows from a splitmix64 sequence
+    uint64_t state = cfg->seed;
+    auto next = [&state]() {
+        uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    auto gcd = [](uint64_t a, uint64_t b) {
+        while (b) {
+            const uint64_t t = a % b;
+            a = b;
+            b = t;
+        }
+        return a;
+    };
+    uint32_t step = cfg->first_step;
+    for (uint32_t e = 0; e < cfg->epochs; ++e) {
+        uint64_t a = 1, b = 0;
+        if (n_rows > 1) {
+            a = next() % n_rows;
+            while (a == 0 || gcd(a, n_rows) != 1) a = (a + 1) % n_rows;
+            b = next() % n_rows;
+        }
+        for (uint64_t k = 0; k < steps_per_epoch; ++k) {
+            const uint64_t first = k * B, cnt = std::min<uint64_t>(B, n_rows - first);
+            hipLaunchKernelGGL(k_gather, dim3(blocks_for(cnt)), dim3(kThreads), 0, st, ctx, y, omega, n_rows, a, b,
+                               first, cnt, at<uint16_t>(ws, L, MXR_MLP_WS_X), at<double>(ws, L, MXR_MLP_WS_Y),
+                               at<double>(ws, L, MXR_MLP_WS_W));
+            if ((s = launch_check("gather")) != MXR_OK) return s;
+            double *lp = loss_log ? loss_log + (uint64_t)e * steps_per_epoch + k : nullptr;
+            const Layout Lc = layout_for(B);  // the batch's layout also serves a shorter last batch
+            if ((s = loss_grad_ws(w, cnt, flo, fhi, grad, lp, ws, Lc, st)) != MXR_OK) return s;
+            ++step;
+            if ((s = mxr_adam_step(master, w, grad, m, v, kParams, step, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps,
+                                   hip_stream)) != MXR_OK)
+                return s;
+        }
+    }
+    return MXR_OK;
+}
+
+}  // extern "C"

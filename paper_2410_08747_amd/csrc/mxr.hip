@@ -33,6 +33,13 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kDynamic = -1;
+constexpr uint32_t kMaxBranches = 4;  // graph branches of a batch in the launches form
+// internal component kinds (not in the public enum): the cone-beam source
+// drawing from a proposal mixture, and a monitor that also records its hits
+constexpr int kSrcConeProposal = 100;
+constexpr int kDetectorCollect = 101;
+
+constexpr bool is_detector(int T) { return T == MXR_DETECTOR || T == kDetectorCollect; }
 
 // ---------------------------------------------------------------- state --
 
@@ -50,15 +57,55 @@ __device__ __forceinline__ void ledger_add(const LedgerLds &L, int slot, double 
     if constexpr (LEDGER) atomicAdd(L.slots + slot, v);
 }
 
+// Append (context, y, w, bin) of the lanes whose flag is set to the hit
+// sink: one atomic per wave reserves the rows, each lane writes at its rank
+// among the flagged lanes.  y is the direction in the source's frame as
+// (dx/dz, dy/dz) and the energy: the collecting chains leave both as the
+// source drew them.
+__device__ __forceinline__ void append_hit(const RunArgs &a, const DevComp &src, const Ray &ray, int64_t bin,
+                                           bool flag) {
+    const uint64_t mask = __builtin_amdgcn_ballot_w64(flag);
+    if (!flag) return;
+    const uint32_t lane = __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    const int leader = __builtin_ctzll(mask);
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    unsigned long long base = 0;
+    if ((int)lane == leader) base = atomicAdd(a.hits.count, (unsigned long long)__builtin_popcountll(mask));
+    base = __shfl(base, leader, 64);
+    const uint64_t row = base + rank;
+    if (row >= a.hits.capacity) return;
+    double q[3], dl[3];
+    to_local(src, ray, q, dl);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) a.hits.ctx[row * 6 + i] = a.hits.c[i];
+    a.hits.y[row * 3 + 0] = dl[0] / dl[2];
+    a.hits.y[row * 3 + 1] = dl[1] / dl[2];
+    a.hits.y[row * 3 + 2] = ray.E;
+    a.hits.w[row] = ray.w;
+    a.hits.bin[row] = bin;
+}
+
 // Apply component k of type T.  Returns false when the ray is absorbed.
 template <int T, bool LEDGER, bool TRACE, bool EXACT>
 __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream &s, uint64_t ray_id,
                                       const RunArgs &a, const double *mu_lds, uint32_t n_mat, uint32_t n_ebin,
                                       RayEnd &end, const LedgerLds &L) {
-    if constexpr (T == MXR_SRC_RECT_CONE || T == MXR_SRC_CONE_BEAM || T == MXR_SRC_GAUSSIAN) {
+    if constexpr (T == MXR_SRC_RECT_CONE || T == MXR_SRC_CONE_BEAM || T == MXR_SRC_GAUSSIAN ||
+                  T == kSrcConeProposal) {
         if constexpr (T == MXR_SRC_RECT_CONE) src_rect_cone(c, s, ray);
         if constexpr (T == MXR_SRC_CONE_BEAM) src_cone_beam(c, s, ray, ray_id, a);
         if constexpr (T == MXR_SRC_GAUSSIAN) src_gaussian(c, s, ray);
+        if constexpr (T == kSrcConeProposal) {
+            const bool ok = src_cone_proposal(c, a.prop, s, ray);
+            ledger_add<LEDGER>(L, 4 * k, ray.w);
+            if (!ok) {  // drawn outside the cone: emitted with weight 0
+                end.status = kAbsorbed;
+                end.dead_at = k;
+                ledger_add<LEDGER>(L, 4 * k + 1, ray.w);
+                return false;
+            }
+            return true;
+        }
         ledger_add<LEDGER>(L, 4 * k, ray.w);
         return true;
     } else {
@@ -89,7 +136,7 @@ __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream 
         if constexpr (T == MXR_MIRROR_ELLIPTIC) ok = comp_mirror(c, ray);
         if constexpr (T == MXR_DCM) ok = comp_dcm(c, ray);
         if constexpr (T == MXR_POWDER) ok = comp_powder(c, s, ray);
-        if constexpr (T == MXR_DETECTOR) ok = comp_detector(c, ray, bin);
+        if constexpr (is_detector(T)) ok = comp_detector(c, ray, bin);
         ledger_add<LEDGER>(L, 4 * k, w_in);
         if (!ok) {
             ray = before;
@@ -99,7 +146,8 @@ __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream 
             return false;
         }
         ledger_add<LEDGER>(L, 4 * k + 2, w_in - ray.w);
-        if constexpr (T == MXR_DETECTOR) {
+        if constexpr (T == kDetectorCollect) append_hit(a, a.ins->c[0], ray, bin, bin >= 0);
+        if constexpr (is_detector(T)) {
             if (bin >= 0) {
                 end.bin = bin;
                 if constexpr (!TRACE) {
@@ -123,7 +171,9 @@ __device__ __forceinline__ bool apply_dynamic(const DevComp &c, int k, Ray &ray,
     case T: return apply<T, LEDGER, TRACE, EXACT>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
     switch (c.type) {
         MXR_CASE(MXR_SRC_RECT_CONE)
-        MXR_CASE(MXR_SRC_CONE_BEAM)
+        case MXR_SRC_CONE_BEAM:
+            if (a.prop) return apply<kSrcConeProposal, LEDGER, TRACE, EXACT>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
+            return apply<MXR_SRC_CONE_BEAM, LEDGER, TRACE, EXACT>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
         MXR_CASE(MXR_SRC_GAUSSIAN)
         MXR_CASE(MXR_SLIT)
         MXR_CASE(MXR_BOX)
@@ -131,7 +181,9 @@ __device__ __forceinline__ bool apply_dynamic(const DevComp &c, int k, Ray &ray,
         MXR_CASE(MXR_MIRROR_ELLIPTIC)
         MXR_CASE(MXR_DCM)
         MXR_CASE(MXR_POWDER)
-        MXR_CASE(MXR_DETECTOR)
+        case MXR_DETECTOR:
+            if (a.hits.count) return apply<kDetectorCollect, LEDGER, TRACE, EXACT>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
+            return apply<MXR_DETECTOR, LEDGER, TRACE, EXACT>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
         default: break;
     }
 #undef MXR_CASE
@@ -154,6 +206,14 @@ struct WavesHint {
 };
 template <>
 struct WavesHint<Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR>> {
+    static constexpr int value = 8;
+};
+template <>
+struct WavesHint<Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, kDetectorCollect>> {
+    static constexpr int value = 8;
+};
+template <>
+struct WavesHint<Chain<kSrcConeProposal, MXR_PHANTOM, MXR_DETECTOR>> {
     static constexpr int value = 8;
 };
 // The batch kernels read their per-job arguments from memory rather than the
@@ -408,6 +468,8 @@ using ChainGeneric = Chain<kDynamic>;
 using ChainBasic = Chain<MXR_SRC_RECT_CONE, MXR_SLIT, MXR_BOX, MXR_DETECTOR>;
 using ChainEdct = Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR>;
 using ChainBeamline = Chain<MXR_SRC_GAUSSIAN, MXR_MIRROR_ELLIPTIC, MXR_DCM, MXR_POWDER, MXR_DETECTOR>;
+using ChainEdctProposal = Chain<kSrcConeProposal, MXR_PHANTOM, MXR_DETECTOR>;
+using ChainEdctCollect = Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, kDetectorCollect>;
 
 enum Recipe { kRecipeGeneric = 0, kRecipeBasic, kRecipeEdct, kRecipeBeamline, kNumRecipes };
 
@@ -421,9 +483,20 @@ struct KernelSet {
     }
 };
 
+enum RunMode { kModePlain = 0, kModeProposal, kModeCollect };
+
 // exact: the phantom's planes are reached exactly by adding the voxel edge
 // (chains without a phantom ignore it)
-KernelFn pick_kernel(int recipe, bool ledger, bool trace, bool exact) {
+KernelFn pick_kernel(int recipe, bool ledger, bool trace, bool exact, int mode) {
+    if (mode != kModePlain) {
+        if (recipe == kRecipeEdct && mode == kModeProposal)
+            return exact ? KernelSet<ChainEdctProposal, true>::get(ledger, trace)
+                         : KernelSet<ChainEdctProposal, false>::get(ledger, trace);
+        if (recipe == kRecipeEdct && mode == kModeCollect && !trace)
+            return exact ? KernelSet<ChainEdctCollect, true>::get(ledger, false)
+                         : KernelSet<ChainEdctCollect, false>::get(ledger, false);
+        return exact ? KernelSet<ChainGeneric, true>::get(ledger, trace) : KernelSet<ChainGeneric, false>::get(ledger, trace);
+    }
     switch (recipe) {
         case kRecipeBasic: return KernelSet<ChainBasic, true>::get(ledger, trace);
         case kRecipeEdct:
@@ -508,6 +581,14 @@ int draws_of(uint32_t t) {
 
 }  // namespace
 
+// error reporting shared with the other translation units of the library
+namespace mxr_host {
+mxr_status set_error(mxr_status st, const char *msg) {
+    g_error = msg;
+    return st;
+}
+}  // namespace mxr_host
+
 struct mxr_instrument {
     int device;
     DevInstr host;
@@ -515,7 +596,9 @@ struct mxr_instrument {
     int recipe;
     uint32_t n_det;
     uint64_t det_bins[MXR_MAX_DETECTORS];
-    uint64_t strata;  // G of the cone-beam source, 0 if none
+    uint64_t strata;      // G of the cone-beam source, 0 if none
+    PropTable *prop_dev;  // proposal mixture (device), allocated on first use
+    bool prop_on;
 };
 
 // Derive per-component constants on the host (glibc), validate ranges.
@@ -762,6 +845,7 @@ void mxr_instrument_destroy(mxr_instrument *ins) {
     if (hipGetDevice(&cur) == hipSuccess && cur != ins->device) (void)hipSetDevice(ins->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(ins->dev);
+    if (ins->prop_dev) (void)hipFree(ins->prop_dev);
     if (cur >= 0 && cur != ins->device) (void)hipSetDevice(cur);
     delete ins;
 }
@@ -769,7 +853,8 @@ void mxr_instrument_destroy(mxr_instrument *ins) {
 static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, bool ledger, bool trace,
                          hipStream_t stream) {
     const bool exact = ins->host.phantom < 0 || ins->host.c[ins->host.phantom].aux[4] != 0.0;
-    KernelFn k = pick_kernel(ins->recipe, ledger, trace, exact);
+    const int mode = base.hits.count ? kModeCollect : (base.prop ? kModeProposal : kModePlain);
+    KernelFn k = pick_kernel(ins->recipe, ledger, trace, exact, mode);
     size_t shmem = 0;
     if (ins->host.phantom >= 0) shmem += (size_t)ins->host.n_mat * ins->host.n_ebin * sizeof(double);
     if (ledger) shmem += (size_t)(4 * ins->host.ncomp + 1) * sizeof(double);
@@ -826,18 +911,11 @@ static mxr_status common_args(mxr_instrument *ins, uint64_t n_total, uint64_t se
     a.G = G;
     a.G2 = G * G;
     if (a.G2 > 1 && n_total > (~0ull) / a.G2) return fail(MXR_E_INVALID, "n_total * strata^2 must stay below 2^64");
+    a.prop = ins->prop_on ? ins->prop_dev : nullptr;
     return MXR_OK;
 }
 
-mxr_status mxr_run(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays, uint64_t n_total, uint64_t seed,
-                   uint32_t purpose, uint32_t job, const mxr_tally *tallies, uint32_t n_tallies, double *ledger,
-                   void *hip_stream) {
-    RunArgs a;
-    mxr_status st = common_args(ins, n_total, seed, purpose, job, a);
-    if (st != MXR_OK) return st;
-    if (first_ray > n_total || n_rays > n_total - first_ray)
-        return fail(MXR_E_INVALID, "rays [%llu, %llu) exceed n_total %llu", (unsigned long long)first_ray,
-                    (unsigned long long)(first_ray + n_rays), (unsigned long long)n_total);
+static mxr_status check_tallies(mxr_instrument *ins, const mxr_tally *tallies, uint32_t n_tallies, RunArgs &a) {
     if (n_tallies != ins->n_det) return fail(MXR_E_INVALID, "%u tallies given, instrument has %u monitors", n_tallies, ins->n_det);
     if (n_tallies && !tallies) return fail(MXR_E_INVALID, "null tallies");
     for (uint32_t i = 0; i < n_tallies; ++i) {
@@ -850,11 +928,134 @@ mxr_status mxr_run(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays, uin
         a.tally.sum_w[i] = tallies[i].sum_w;
         a.tally.sum_w2[i] = tallies[i].sum_w2;
     }
+    return MXR_OK;
+}
+
+mxr_status mxr_run(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays, uint64_t n_total, uint64_t seed,
+                   uint32_t purpose, uint32_t job, const mxr_tally *tallies, uint32_t n_tallies, double *ledger,
+                   void *hip_stream) {
+    RunArgs a;
+    mxr_status st = common_args(ins, n_total, seed, purpose, job, a);
+    if (st != MXR_OK) return st;
+    if (first_ray > n_total || n_rays > n_total - first_ray)
+        return fail(MXR_E_INVALID, "rays [%llu, %llu) exceed n_total %llu", (unsigned long long)first_ray,
+                    (unsigned long long)(first_ray + n_rays), (unsigned long long)n_total);
+    st = check_tallies(ins, tallies, n_tallies, a);
+    if (st != MXR_OK) return st;
     if (n_rays == 0) return MXR_OK;
     a.first = first_ray;
     a.n = n_rays;
     a.ledger = ledger;
     return launch(ins, a, n_rays, ledger != nullptr, false, (hipStream_t)hip_stream);
+}
+
+mxr_status mxr_collect(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays, uint64_t n_total, uint64_t seed,
+                       uint32_t purpose, uint32_t job, const mxr_tally *tallies, uint32_t n_tallies,
+                       const mxr_hits *hits, void *hip_stream) {
+    RunArgs a;
+    mxr_status st = common_args(ins, n_total, seed, purpose, job, a);
+    if (st != MXR_OK) return st;
+    if (first_ray > n_total || n_rays > n_total - first_ray)
+        return fail(MXR_E_INVALID, "rays [%llu, %llu) exceed n_total %llu", (unsigned long long)first_ray,
+                    (unsigned long long)(first_ray + n_rays), (unsigned long long)n_total);
+    st = check_tallies(ins, tallies, n_tallies, a);
+    if (st != MXR_OK) return st;
+    if (!hits || !hits->ctx || !hits->y || !hits->w || !hits->bin || !hits->count)
+        return fail(MXR_E_INVALID, "null hit sink array");
+    const DevInstr &d = ins->host;
+    if (d.c[0].type != MXR_SRC_CONE_BEAM) return fail(MXR_E_UNSUPPORTED, "hit collection needs a cone-beam source");
+    if (ins->n_det != 1 || d.c[d.ncomp - 1].type != MXR_DETECTOR)
+        return fail(MXR_E_UNSUPPORTED, "hit collection needs exactly one monitor, the last component");
+    for (uint32_t k = 1; k + 1 < d.ncomp; ++k) {
+        const uint32_t t = d.c[k].type;
+        if (t != MXR_SLIT && t != MXR_BOX && t != MXR_PHANTOM)
+            return fail(MXR_E_UNSUPPORTED, "hit collection: component %u changes direction or energy", k);
+    }
+    for (int i = 0; i < 6; ++i)
+        if (!std::isfinite(hits->context[i])) return fail(MXR_E_INVALID, "non-finite context");
+    if (n_rays == 0) return MXR_OK;
+    a.hits.ctx = hits->ctx;
+    a.hits.y = hits->y;
+    a.hits.w = hits->w;
+    a.hits.bin = hits->bin;
+    a.hits.count = (unsigned long long *)hits->count;
+    a.hits.capacity = hits->capacity;
+    for (int i = 0; i < 6; ++i) a.hits.c[i] = hits->context[i];
+    a.first = first_ray;
+    a.n = n_rays;
+    return launch(ins, a, n_rays, false, false, (hipStream_t)hip_stream);
+}
+
+mxr_status mxr_proposal_set(mxr_instrument *ins, const double *gmm, double alpha) {
+    if (!ins) return fail(MXR_E_INVALID, "null instrument");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != ins->device) return fail(MXR_E_STATE, "instrument lives on device %d, device %d is current", ins->device, cur);
+    if (!gmm) {
+        ins->prop_on = false;
+        return MXR_OK;
+    }
+    const DevInstr &d = ins->host;
+    if (d.c[0].type != MXR_SRC_CONE_BEAM) return fail(MXR_E_UNSUPPORTED, "a proposal needs a cone-beam source");
+    for (uint32_t k = 1; k < d.ncomp; ++k)
+        if (draws_of(d.c[k].type)) return fail(MXR_E_UNSUPPORTED, "a proposal needs components that draw no uniforms");
+    if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(MXR_E_INVALID, "alpha must be in [0, 1]");
+    double g[56];
+    e = hipMemcpy(g, gmm, sizeof g, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "copy of the mixture table");
+    const DevComp &c = d.c[0];
+    PropTable P;
+    std::memset(&P, 0, sizeof P);
+    const double t = std::tan(c.par[0]);
+    const double lo[3] = {-t, -t, c.par[1]}, hi[3] = {t, t, c.par[2]};
+    double run = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        const double *gk = g + 7 * k;
+        if (!std::isfinite(gk[0]) || gk[0] < 0.0) return fail(MXR_E_INVALID, "component %d: bad weight", k);
+        double Z = gk[0], sprod = 1.0;
+        for (int dd = 0; dd < 3; ++dd) {
+            const double mu = gk[1 + dd], sg = gk[4 + dd];
+            if (!std::isfinite(mu) || !std::isfinite(sg) || !(sg > 0.0))
+                return fail(MXR_E_INVALID, "component %d: non-finite mean or non-positive width", k);
+            const double za = (lo[dd] - mu) / sg, zb = (hi[dd] - mu) / sg;
+            P.mu[k][dd] = mu;
+            P.sigma[k][dd] = sg;
+            P.inv_sigma[k][dd] = 1.0 / sg;
+            P.Pa[k][dd] = 0.5 * std::erfc(-za / std::sqrt(2.0));
+            P.Pb[k][dd] = 0.5 * std::erfc(-zb / std::sqrt(2.0));
+            P.Qa[k][dd] = 0.5 * std::erfc(za / std::sqrt(2.0));
+            P.Qb[k][dd] = 0.5 * std::erfc(zb / std::sqrt(2.0));
+            Z *= P.Pb[k][dd] - P.Pa[k][dd];
+            sprod *= sg;
+        }
+        P.coef[k] = gk[0] / (sprod * std::pow(2.0 * M_PI, 1.5));
+        P.mass[k] = Z;
+        run += Z;
+        P.cum[k] = run;
+    }
+    P.norm = run;
+    if (!(run > 0.0) && alpha < 1.0) return fail(MXR_E_INVALID, "the mixture has no mass inside the box");
+    P.alpha = alpha;
+    P.t2 = t * t;
+    P.inv_omega = 1.0 / (2.0 * M_PI * (1.0 - std::cos(c.par[0])));
+    for (int dd = 0; dd < 3; ++dd) {
+        P.lo[dd] = lo[dd];
+        P.hi[dd] = hi[dd];
+    }
+    if (!ins->prop_dev) {
+        e = hipMalloc((void **)&ins->prop_dev, sizeof(PropTable));
+        if (e != hipSuccess) {
+            ins->prop_dev = nullptr;
+            return fail(MXR_E_NOMEM, "hipMalloc of the proposal table: %s", hipGetErrorString(e));
+        }
+    }
+    // runs still in flight read the previous table
+    e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(ins->prop_dev, &P, sizeof P, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload of the proposal table");
+    ins->prop_on = true;
+    return MXR_OK;
 }
 
 mxr_status mxr_trace_rays(mxr_instrument *ins, const uint64_t *ray_ids, uint64_t n, uint64_t n_total, uint64_t seed,
@@ -887,11 +1088,13 @@ struct mxr_batch {
     BatchJob *dev_jobs;
     unsigned long long *counter;
     size_t shmem;
-    uint32_t groups_per_cu, tile_rays;
+    mxr_batch_schedule sched;  // normalised launch shape
     uint64_t n_tiles;
     int n_cu;
     std::string key;  // describes the batch for the tuning cache
     hipStream_t capture_stream;
+    hipStream_t branch[kMaxBranches];  // graph branches of the launches form
+    hipEvent_t fork, join[kMaxBranches];
     hipGraph_t graph;
     hipGraphExec_t exec;
     bool graph_ready;
@@ -914,13 +1117,26 @@ static void batch_drop_graph(mxr_batch *b) {
     }
 }
 
+static void batch_free(mxr_batch *b) {
+    batch_drop_graph(b);
+    if (b->dev_jobs) (void)hipFree(b->dev_jobs);
+    if (b->counter) (void)hipFree(b->counter);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    for (uint32_t i = 0; i < kMaxBranches; ++i) {
+        if (b->branch[i]) (void)hipStreamDestroy(b->branch[i]);
+        if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    delete b;
+}
+
 // Lays out the tiles for the current tile size and uploads the job table.
 static mxr_status batch_layout(mxr_batch *b) {
     // a replay still in flight reads the table being replaced
     hipError_t w = hipDeviceSynchronize();
     if (w != hipSuccess) return hip_fail(w, "hipDeviceSynchronize before the job table upload");
     std::vector<uint64_t> first;
-    const uint64_t n_tiles = batch_tiles(b->host_jobs, b->tile_rays, &first);
+    const uint64_t n_tiles = batch_tiles(b->host_jobs, b->sched.tile_rays, &first);
     if (n_tiles >= (1ull << 31)) return fail(MXR_E_UNSUPPORTED, "batch needs %llu tiles (limit 2^31)", (unsigned long long)n_tiles);
     for (size_t i = 0; i < first.size(); ++i) b->host_jobs[i].tile0 = first[i];
     b->n_tiles = n_tiles;
@@ -930,17 +1146,75 @@ static mxr_status batch_layout(mxr_batch *b) {
     return MXR_OK;
 }
 
-// groups_per_cu 0 is the grid form, whose tiles are one work-group (256 rays)
-static bool schedule_ok(uint32_t g, uint32_t t) {
-    if (g == 0) return t == (uint32_t)kBlock;
-    return g >= 1 && g <= 8 && t >= (uint32_t)kBlock && t <= (1u << 24) && t % kBlock == 0;
+// Checks a launch shape and fills the fields its form ignores: the grid
+// form's tiles are one work-group (256 rays), the launches form keeps the
+// 256-ray tile table unused.
+static bool schedule_normalise(const mxr_batch_schedule &in, mxr_batch_schedule &out) {
+    out = in;
+    switch (in.form) {
+        case MXR_BATCH_GRID:
+            out.groups_per_cu = 0;
+            out.tile_rays = kBlock;
+            out.branches = 0;
+            return true;
+        case MXR_BATCH_PERSISTENT:
+            out.branches = 0;
+            if (out.tile_rays == 0) out.tile_rays = 65536;
+            return in.groups_per_cu >= 1 && in.groups_per_cu <= 8 && out.tile_rays >= (uint32_t)kBlock &&
+                   out.tile_rays <= (1u << 24) && out.tile_rays % kBlock == 0;
+        case MXR_BATCH_LAUNCHES:
+            out.groups_per_cu = 0;
+            out.tile_rays = kBlock;
+            if (out.branches == 0) out.branches = 1;
+            return out.branches <= kMaxBranches;
+        default: return false;
+    }
 }
 
-// Capture counter reset + persistent kernel into a graph (once per shape).
+static const char *kScheduleRule =
+    "schedule: form 0 (grid), 1 (persistent: groups_per_cu 1..8, tile_rays a multiple of 256 in [256, 2^24]) "
+    "or 2 (launches: branches 1..4)";
+
+// One job's rays as k_trace launches of at most 2^30 work-groups (the same
+// kernels and launch shape as mxr_run).
+static hipError_t launch_job(KernelFn k, const RunArgs &job, size_t shmem, hipStream_t st) {
+    const uint64_t max_rays = (1ull << 30) * kBlock;
+    for (uint64_t done = 0; done < job.n;) {
+        const uint64_t m = std::min(job.n - done, max_rays);
+        RunArgs a = job;
+        a.first = done;
+        a.n = m;
+        const uint64_t groups = (m + kBlock - 1) / kBlock;
+        a.blocks_per_xcd = (uint32_t)((groups + 7) / 8);
+        hipLaunchKernelGGL(k, dim3((unsigned)((uint64_t)a.blocks_per_xcd * 8)), dim3(kBlock), shmem, st, job.ins, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        done += m;
+    }
+    return hipSuccess;
+}
+
+// Capture the batch's launch into a graph (once per shape): the grid kernel,
+// or counter reset + persistent kernel, or the per-job launches.
 static mxr_status batch_capture(mxr_batch *b) {
     hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    if (b->groups_per_cu == 0) {
+    hipError_t launch_err = hipSuccess;
+    if (b->sched.form == MXR_BATCH_LAUNCHES) {
+        // jobs dealt longest-first round-robin over the branches, which fork
+        // from and join back into the capture stream
+        const uint32_t nb = b->sched.branches;
+        KernelFn k = pick_kernel(b->recipe, false, false, b->exact, kModePlain);
+        launch_err = hipEventRecord(b->fork, b->capture_stream);
+        for (uint32_t i = 0; launch_err == hipSuccess && i < nb; ++i)
+            launch_err = hipStreamWaitEvent(b->branch[i], b->fork, 0);
+        for (uint32_t j = 0; launch_err == hipSuccess && j < b->n_jobs; ++j)
+            launch_err = launch_job(k, b->host_jobs[j].args, b->shmem, b->branch[j % nb]);
+        for (uint32_t i = 0; launch_err == hipSuccess && i < nb; ++i) {
+            launch_err = hipEventRecord(b->join[i], b->branch[i]);
+            if (launch_err == hipSuccess) launch_err = hipStreamWaitEvent(b->capture_stream, b->join[i], 0);
+        }
+    } else if (b->sched.form == MXR_BATCH_GRID) {
         // grid form: one work-group per 256-ray tile, 2-D grid
         const uint64_t groups = (b->n_tiles + 511) / 512 * 512;
         const uint32_t gx = (uint32_t)std::min<uint64_t>(groups, 1u << 16);
@@ -950,11 +1224,11 @@ static mxr_status batch_capture(mxr_batch *b) {
     } else {
         hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, b->capture_stream, b->counter);
         BatchKernelFn k = pick_batch_kernel(b->recipe, b->exact);
-        const unsigned grid = (unsigned)(b->groups_per_cu * (uint32_t)b->n_cu);
+        const unsigned grid = (unsigned)(b->sched.groups_per_cu * (uint32_t)b->n_cu);
         hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), b->shmem, b->capture_stream, (const BatchJob *)b->dev_jobs,
-                           b->n_jobs, b->n_tiles, b->tile_rays, b->counter);
+                           b->n_jobs, b->n_tiles, b->sched.tile_rays, b->counter);
     }
-    hipError_t launch = hipGetLastError();
+    hipError_t launch = launch_err != hipSuccess ? launch_err : hipGetLastError();
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(b->capture_stream, &g);
     if (launch != hipSuccess) {
@@ -993,6 +1267,7 @@ mxr_status mxr_batch_create(const mxr_batch_job *jobs, uint32_t n_jobs, const mx
         const mxr_instrument *ins = j.instrument;
         if (!ins) return fail(MXR_E_INVALID, "job %u has no instrument", k);
         if (ins->device != cur) return fail(MXR_E_STATE, "job %u: instrument on device %d, device %d current", k, ins->device, cur);
+        if (ins->prop_on) return fail(MXR_E_UNSUPPORTED, "job %u: batches trace the plain source (clear the proposal)", k);
         if (ins->host.ncomp != i0->host.ncomp) return fail(MXR_E_INVALID, "job %u: component chain differs from job 0", k);
         for (uint32_t c = 0; c < ins->host.ncomp; ++c)
             if (ins->host.c[c].type != i0->host.c[c].type) return fail(MXR_E_INVALID, "job %u: component chain differs from job 0", k);
@@ -1054,17 +1329,11 @@ mxr_status mxr_batch_create(const mxr_batch_job *jobs, uint32_t n_jobs, const mx
     for (const auto &o : order) b->host_jobs.push_back(hj[o.second]);
     e = hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, cur);
     if (e != hipSuccess || b->n_cu < 1) b->n_cu = 256;
-    b->groups_per_cu = 0;  // grid form until tuned
-    b->tile_rays = kBlock;
-    if (schedule) {
-        uint32_t g = schedule->groups_per_cu;
-        uint32_t t = schedule->tile_rays ? schedule->tile_rays : (g == 0 ? (uint32_t)kBlock : 65536u);
-        if (!schedule_ok(g, t)) {
-            delete b;
-            return fail(MXR_E_INVALID, "schedule: groups_per_cu 0 (grid form, tile_rays 256) or 1..8 with tile_rays a multiple of 256 in [256, 2^24]");
-        }
-        b->groups_per_cu = g;
-        b->tile_rays = t;
+    // one launch per job, one branch, until tuned
+    const mxr_batch_schedule dflt{MXR_BATCH_LAUNCHES, 0, 0, 1};
+    if (!schedule_normalise(schedule ? *schedule : dflt, b->sched)) {
+        delete b;
+        return fail(MXR_E_INVALID, "%s", kScheduleRule);
     }
     char key[256];
     std::string chain;
@@ -1076,15 +1345,20 @@ mxr_status mxr_batch_create(const mxr_batch_job *jobs, uint32_t n_jobs, const mx
     b->dev_jobs = nullptr;
     b->counter = nullptr;
     b->capture_stream = nullptr;
+    b->fork = nullptr;
+    for (uint32_t i = 0; i < kMaxBranches; ++i) {
+        b->branch[i] = nullptr;
+        b->join[i] = nullptr;
+    }
     e = hipMalloc((void **)&b->dev_jobs, n_jobs * sizeof(BatchJob));
     if (e == hipSuccess) e = hipMalloc((void **)&b->counter, sizeof(unsigned long long));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+    for (uint32_t i = 0; e == hipSuccess && i < kMaxBranches; ++i) e = hipStreamCreateWithFlags(&b->branch[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (uint32_t i = 0; e == hipSuccess && i < kMaxBranches; ++i) e = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming);
     mxr_status st = e == hipSuccess ? batch_layout(b) : fail(MXR_E_NOMEM, "batch allocation: %s", hipGetErrorString(e));
     if (st != MXR_OK) {
-        if (b->dev_jobs) (void)hipFree(b->dev_jobs);
-        if (b->counter) (void)hipFree(b->counter);
-        if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
-        delete b;
+        batch_free(b);
         return st;
     }
     *out = b;
@@ -1108,37 +1382,32 @@ mxr_status mxr_batch_run(mxr_batch *b, void *hip_stream) {
 
 mxr_status mxr_batch_get_schedule(const mxr_batch *b, mxr_batch_schedule *out) {
     if (!b || !out) return fail(MXR_E_INVALID, "null batch or output");
-    out->groups_per_cu = b->groups_per_cu;
-    out->tile_rays = b->tile_rays;
+    *out = b->sched;
     return MXR_OK;
 }
 
 mxr_status mxr_batch_set_schedule(mxr_batch *b, const mxr_batch_schedule *s) {
     if (!b || !s) return fail(MXR_E_INVALID, "null batch or schedule");
-    if (!schedule_ok(s->groups_per_cu, s->tile_rays))
-        return fail(MXR_E_INVALID, "schedule: groups_per_cu 0 (grid form, tile_rays 256) or 1..8 with tile_rays a multiple of 256 in [256, 2^24]");
-    const bool relayout = s->tile_rays != b->tile_rays;
-    b->groups_per_cu = s->groups_per_cu;
-    b->tile_rays = s->tile_rays;
+    mxr_batch_schedule n;
+    if (!schedule_normalise(*s, n)) return fail(MXR_E_INVALID, "%s", kScheduleRule);
+    const bool relayout = n.tile_rays != b->sched.tile_rays;
+    b->sched = n;
     batch_drop_graph(b);
     return relayout ? batch_layout(b) : MXR_OK;
 }
 
 void mxr_batch_destroy(mxr_batch *b) {
     if (!b) return;
+    const int b_device = b->device;
     int cur = -1;
-    if (hipGetDevice(&cur) == hipSuccess && cur != b->device) (void)hipSetDevice(b->device);
+    if (hipGetDevice(&cur) == hipSuccess && cur != b_device) (void)hipSetDevice(b_device);
     (void)hipDeviceSynchronize();
-    batch_drop_graph(b);
-    (void)hipFree(b->dev_jobs);
-    (void)hipFree(b->counter);
-    (void)hipStreamDestroy(b->capture_stream);
-    if (cur >= 0 && cur != b->device) (void)hipSetDevice(cur);
-    delete b;
+    batch_free(b);
+    if (cur >= 0 && cur != b_device) (void)hipSetDevice(cur);
 }
 
-// Tuning cache: one line per batch, "<key>\t<groups_per_cu> <tile_rays>".
-static bool cache_lookup(const char *path, const std::string &key, uint32_t &g, uint32_t &t) {
+// Tuning cache: one line per batch, "<key>\t<form> <groups_per_cu> <tile_rays> <branches>".
+static bool cache_lookup(const char *path, const std::string &key, mxr_batch_schedule &out) {
     if (!path) return false;
     FILE *f = std::fopen(path, "r");
     if (!f) return false;
@@ -1148,10 +1417,10 @@ static bool cache_lookup(const char *path, const std::string &key, uint32_t &g, 
         char *tab = std::strchr(line, '\t');
         if (!tab) continue;
         *tab = 0;
-        unsigned gg = 0, tt = 0;
-        if (key == line && std::sscanf(tab + 1, "%u %u", &gg, &tt) == 2 && schedule_ok(gg, tt)) {
-            g = gg;
-            t = tt;
+        mxr_batch_schedule s{}, n{};
+        if (key == line && std::sscanf(tab + 1, "%u %u %u %u", &s.form, &s.groups_per_cu, &s.tile_rays, &s.branches) == 4 &&
+            schedule_normalise(s, n)) {
+            out = n;
             found = true;
         }
     }
@@ -1159,22 +1428,21 @@ static bool cache_lookup(const char *path, const std::string &key, uint32_t &g, 
     return found;
 }
 
-static void cache_store(const char *path, const std::string &key, uint32_t g, uint32_t t) {
+static void cache_store(const char *path, const std::string &key, const mxr_batch_schedule &s) {
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s\t%u %u\n", key.c_str(), g, t);
+    std::fprintf(f, "%s\t%u %u %u %u\n", key.c_str(), s.form, s.groups_per_cu, s.tile_rays, s.branches);
     std::fclose(f);
 }
 
 mxr_status mxr_batch_autotune(mxr_batch *b, double rays_fraction, const char *cache_path, mxr_batch_schedule *out) {
     if (!b) return fail(MXR_E_INVALID, "null batch");
     if (!(rays_fraction > 0.0 && rays_fraction <= 1.0)) return fail(MXR_E_INVALID, "rays_fraction must be in (0, 1]");
-    uint32_t g = 0, t = 0;
-    if (cache_lookup(cache_path, b->key, g, t)) {
-        mxr_batch_schedule s{g, t};
-        mxr_status st = mxr_batch_set_schedule(b, &s);
-        if (st == MXR_OK && out) *out = s;
+    mxr_batch_schedule cached;
+    if (cache_lookup(cache_path, b->key, cached)) {
+        mxr_status st = mxr_batch_set_schedule(b, &cached);
+        if (st == MXR_OK && out) *out = b->sched;
         return st;
     }
     // timing copy of the job table with every job's rays scaled down (the
@@ -1194,47 +1462,42 @@ mxr_status mxr_batch_autotune(mxr_batch *b, double rays_fraction, const char *ca
         (void)batch_layout(b);
         return lay;
     }
-    const uint32_t gpc[] = {2, 4, 6, 8};
-    const uint32_t tiles[] = {16384, 65536, 262144};
+    std::vector<mxr_batch_schedule> cand;
+    cand.push_back({MXR_BATCH_GRID, 0, 0, 0});
+    for (uint32_t g : {2u, 4u, 8u})
+        for (uint32_t t : {16384u, 65536u}) cand.push_back({MXR_BATCH_PERSISTENT, g, t, 0});
+    for (uint32_t br : {1u, 2u, 4u}) cand.push_back({MXR_BATCH_LAUNCHES, 0, 0, br});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     float best_ms = 0.f;
-    uint32_t best_g = b->groups_per_cu, best_t = b->tile_rays;
+    mxr_batch_schedule best = b->sched;
     mxr_status st = e == hipSuccess ? MXR_OK : hip_fail(e, "hipEventCreate");
-    for (uint32_t ti = 0; st == MXR_OK && ti < 4; ++ti) {
-        for (uint32_t gi = 0; st == MXR_OK && gi < 4; ++gi) {
-            if (ti == 3 && gi > 0) break;
-            // the last candidate is the grid form
-            mxr_batch_schedule s = ti < 3 ? mxr_batch_schedule{gpc[gi], tiles[ti]} : mxr_batch_schedule{0u, (uint32_t)kBlock};
-            st = mxr_batch_set_schedule(b, &s);
-            for (int rep = 0; st == MXR_OK && rep < 2; ++rep) {  // first replay warms up
-                e = hipEventRecord(e0, b->capture_stream);
-                if (e == hipSuccess) st = mxr_batch_run(b, b->capture_stream);
-                if (st == MXR_OK) e = hipEventRecord(e1, b->capture_stream);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                if (e != hipSuccess) st = hip_fail(e, "autotune timing");
-            }
-            float ms = 0.f;
-            if (st == MXR_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && (best_ms == 0.f || ms < best_ms)) {
-                best_ms = ms;
-                best_g = s.groups_per_cu;
-                best_t = s.tile_rays;
-            }
+    for (size_t c = 0; st == MXR_OK && c < cand.size(); ++c) {
+        st = mxr_batch_set_schedule(b, &cand[c]);
+        for (int rep = 0; st == MXR_OK && rep < 2; ++rep) {  // first replay warms up
+            e = hipEventRecord(e0, b->capture_stream);
+            if (e == hipSuccess) st = mxr_batch_run(b, b->capture_stream);
+            if (st == MXR_OK) e = hipEventRecord(e1, b->capture_stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e != hipSuccess) st = hip_fail(e, "autotune timing");
+        }
+        float ms = 0.f;
+        if (st == MXR_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && (best_ms == 0.f || ms < best_ms)) {
+            best_ms = ms;
+            best = b->sched;
         }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     // back to the real ray counts, with the fastest shape
     b->host_jobs = saved;
-    b->groups_per_cu = best_g;
-    b->tile_rays = best_t;
-    mxr_batch_schedule s{best_g, best_t};
+    b->sched = best;
     mxr_status st2 = batch_layout(b);
     if (st != MXR_OK) return st;
     if (st2 != MXR_OK) return st2;
-    cache_store(cache_path, b->key, best_g, best_t);
-    if (out) *out = s;
+    cache_store(cache_path, b->key, best);
+    if (out) *out = best;
     return MXR_OK;
 }
 

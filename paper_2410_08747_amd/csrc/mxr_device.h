@@ -56,6 +56,34 @@ struct TallyPtrs {
     double *sum_w2[MXR_MAX_DETECTORS];
 };
 
+// Proposal mixture of a cone-beam source, prepared on the host from the
+// caller's 8 x (pi, mu[3], sigma[3]) table: per component the normal
+// distribution function (P) and its upper tail (Q) at the box edges, in
+// standard units, the running sums of the box masses pi_k Z_k, and the
+// density prefactor pi_k / (sigma_u sigma_v sigma_E (2 pi)^(3/2)).
+struct PropTable {
+    double coef[8];
+    double mu[8][3], sigma[8][3], inv_sigma[8][3];
+    double Pa[8][3], Pb[8][3], Qa[8][3], Qb[8][3];
+    double mass[8], cum[8];
+    double norm;       // sum_k pi_k Z_k
+    double alpha;      // share of the plain source in the mixture
+    double t2;         // tan^2 of the cone half-angle
+    double inv_omega;  // 1 / solid angle of the cone
+    double lo[3], hi[3];
+};
+
+// Where a hit-collecting run writes the rays that reach a monitor.
+struct HitSink {
+    float *ctx;                  // n x 6
+    double *y;                   // n x 3: u = dx/dz, v = dy/dz (source frame), E
+    double *w;                   // n
+    int64_t *bin;                // n
+    unsigned long long *count;   // rows written (may exceed capacity: then truncated)
+    uint64_t capacity;
+    float c[6];                  // context of this run
+};
+
 struct RunArgs {
     const DevInstr *ins;
     uint64_t first, n, n_total, seed;
@@ -66,6 +94,8 @@ struct RunArgs {
     double *ledger;
     const uint64_t *ids;  // trace mode: ray ids
     mxr_ray_soa dump;     // trace mode: outputs
+    const PropTable *prop;  // proposal of the cone-beam source, or null
+    HitSink hits;           // hit-collecting runs
 };
 
 // ------------------------------------------------------------- Philox ----
@@ -224,6 +254,89 @@ __device__ __forceinline__ void src_cone_beam(const DevComp &c, Stream &s, Ray &
     ray.E = c.par[1] + c.aux[1] * s.u(2);
     ray.w = (c.aux[1] * spectrum(c, ray.E)) * factor;
     to_lab(c, q, dl, ray);
+}
+
+// Standard normal truncated to [za, zb] by inversion: the point leaving
+// mass U of the interval below it, written as a lower-tail probability
+// Pa + U (Pb - Pa) when that is at most 1/2 and as the upper-tail
+// probability Qb + (1 - U)(Qa - Qb) otherwise, so that no probability near 1
+// is inverted.  Phi^-1(p) = -sqrt(2) erfcinv(2p).
+__device__ __forceinline__ double trunc_normal(double Pa, double Pb, double Qa, double Qb, double U) {
+    const double pl = Pa + U * (Pb - Pa);
+    if (pl <= 0.5) return -1.4142135623730951 * erfcinv(2.0 * pl);
+    return 1.4142135623730951 * erfcinv(2.0 * (Qb + (1.0 - U) * (Qa - Qb)));
+}
+
+// Cone-beam point source drawing y = (u, v, E), u = dx/dz, v = dy/dz, from
+// the mixture alpha q_plain + (1 - alpha) q_gmm (unstratified).  U0 picks
+// the branch (plain below alpha), U1 the mixture component (by box mass),
+// U2..U4 the coordinates: the plain branch maps (U2, U3) to the cone like the
+// plain source with one stratum, E = emin + (emax - emin) U4; the mixture
+// branch inverts a truncated normal per coordinate.  The weight is the
+// physical density over the full mixture density, p(y) / q(y).  A draw
+// outside the cone gets weight 0 and the source returns false.
+__device__ __forceinline__ bool src_cone_proposal(const DevComp &c, const PropTable *__restrict__ P, Stream &s,
+                                                  Ray &ray) {
+    double y[3];
+    if (s.u(0) < P->alpha) {
+        double ca = 2.0 * s.u(2) - 1.0, cb = 2.0 * s.u(3) - 1.0;
+        double rad, ang;
+        if (ca == 0.0 && cb == 0.0) {
+            rad = 0.0;
+            ang = 0.0;
+        } else if (fabs(ca) > fabs(cb)) {
+            rad = ca;
+            ang = (kPi / 4.0) * (cb / ca);
+        } else {
+            rad = cb;
+            ang = (kPi / 2.0) - (kPi / 4.0) * (ca / cb);
+        }
+        double sa, cs;
+        sincos(ang, &sa, &cs);
+        double sh = fabs(rad) * c.aux[0];
+        double ch = sqrt(1.0 - sh * sh);
+        double k = 2.0 * c.aux[0] * ch;
+        double dz = 1.0 - 2.0 * (sh * sh);
+        y[0] = (k * (rad * cs)) / dz;
+        y[1] = (k * (rad * sa)) / dz;
+        y[2] = c.par[1] + c.aux[1] * s.u(4);
+    } else {
+        const double target = s.u(1) * P->norm;
+        int pick = 7;
+        for (int k = 0; k < 8; ++k) {
+            if (target < P->cum[k] && P->mass[k] > 0.0) {
+                pick = k;
+                break;
+            }
+        }
+        for (int d = 0; d < 3; ++d) {
+            double z = trunc_normal(P->Pa[pick][d], P->Pb[pick][d], P->Qa[pick][d], P->Qb[pick][d], s.u(2 + d));
+            y[d] = P->mu[pick][d] + P->sigma[pick][d] * z;
+        }
+    }
+    const double r2 = y[0] * y[0] + y[1] * y[1];
+    const bool in_cone = r2 <= P->t2 && y[2] >= P->lo[2] && y[2] <= P->hi[2];
+    const bool in_box = y[0] >= P->lo[0] && y[0] <= P->hi[0] && y[1] >= P->lo[1] && y[1] <= P->hi[1] &&
+                        y[2] >= P->lo[2] && y[2] <= P->hi[2];
+    double num = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        double zu = (y[0] - P->mu[k][0]) * P->inv_sigma[k][0];
+        double zv = (y[1] - P->mu[k][1]) * P->inv_sigma[k][1];
+        double ze = (y[2] - P->mu[k][2]) * P->inv_sigma[k][2];
+        num += P->coef[k] * exp(-0.5 * (zu * zu + zv * zv + ze * ze));
+    }
+    const double J = pow(1.0 + r2, -1.5);
+    const double q_plain = in_cone ? J * P->inv_omega / c.aux[1] : 0.0;
+    const double q_gmm = in_box ? num / P->norm : 0.0;
+    const double q = P->alpha * q_plain + (1.0 - P->alpha) * q_gmm;
+    const double p_phys = in_cone ? spectrum(c, y[2]) * J * P->inv_omega : 0.0;
+    const double n = sqrt(1.0 + r2);
+    double dl[3] = {y[0] / n, y[1] / n, 1.0 / n};
+    double q0[3] = {0.0, 0.0, 0.0};
+    ray.E = y[2];
+    ray.w = p_phys > 0.0 ? p_phys / q : 0.0;
+    to_lab(c, q0, dl, ray);
+    return p_phys > 0.0;
 }
 
 __device__ __forceinline__ void src_gaussian(const DevComp &c, Stream &s, Ray &ray) {

@@ -69,7 +69,7 @@ def test_binding_struct_layout(lib):
 #include <stdio.h>
 #include <stddef.h>
 #include "mxr.h"
-int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(mxr_component_desc), sizeof(mxr_tally), sizeof(mxr_ray_soa), offsetof(mxr_component_desc, data), sizeof(mxr_batch_job), offsetof(mxr_batch_job, tallies), sizeof(mxr_batch_schedule));return 0;}
+int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mxr_component_desc), sizeof(mxr_tally), sizeof(mxr_ray_soa), offsetof(mxr_component_desc, data), sizeof(mxr_batch_job), offsetof(mxr_batch_job, tallies), sizeof(mxr_batch_schedule), sizeof(mxr_hits));return 0;}
 '''
     import tempfile
     with tempfile.TemporaryDirectory() as d:
@@ -82,4 +82,5 @@ int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(mxr_component_desc
     assert sizes[3] == desc.data.offset
     assert sizes[4] == ctypes.sizeof(m.mxr_batch_job) == 160
     assert sizes[5] == m.mxr_batch_job.tallies.offset
-    assert sizes[6] == ctypes.sizeof(m.mxr_batch_schedule) == 8
+    assert sizes[6] == ctypes.sizeof(m.mxr_batch_schedule) == 16
+    assert sizes[7] == ctypes.sizeof(m.mxr_hits) == 72

@@ -88,7 +88,8 @@ def separate_runs(jobs):
     return [I.run(nr, seed=seed, job=job) for I, nr, seed, job, _ in jobs]
 
 
-@pytest.mark.parametrize("schedule", [(0, 256), (1, 256), (2, 4096), (8, 65536)])
+@pytest.mark.parametrize("schedule", [(0, 0, 256, 0), (1, 1, 256, 0), (1, 2, 4096, 0), (1, 8, 65536, 0),
+                                      (2, 0, 256, 1), (2, 0, 256, 3)])
 def test_batch_equals_separate_runs(torch_cuda, edct_jobs, schedule):
     m = mxr()
     announce("batch vs separate runs", "schedule", schedule, "jobs", len(edct_jobs))
@@ -122,13 +123,14 @@ def test_graph_replays(torch_cuda, edct_jobs):
     m = mxr()
     announce("graph replays")
     jobs = build(m, edct_jobs, {})
-    B = m.Batch(jobs, schedule=(4, 4096))
+    B = m.Batch(jobs, schedule=(1, 4, 4096, 0))
+    L = m.Batch(jobs, schedule=(2, 0, 0, 2))  # the launches form: its own graph
     first = None
-    for rep in range(3):
+    for rep in range(4):
         for j in jobs:
             for v in j[4][0].values():
                 v.zero_()
-        B.run()
+        (B if rep % 2 == 0 else L).run()
         torch_cuda.cuda.synchronize()
         snap = [{k: v.clone() for k, v in j[4][0].items()} for j in jobs]
         if first is None:
@@ -149,11 +151,12 @@ def test_schedule_change_and_autotune(torch_cuda, edct_jobs, tmp_path):
     cache = str(tmp_path / "tune.txt")
     s1 = B.autotune(0.25, cache)
     assert B.schedule == s1
-    g, t = s1
-    assert g == 0 and t == 256 or (1 <= g <= 8 and t % 256 == 0)
+    f, g, t, br = s1
+    assert (f, g, t, br) == (0, 0, 256, 0) or (f == 1 and 1 <= g <= 8 and t % 256 == 0 and br == 0) or \
+        (f == 2 and 1 <= br <= 4)
     lines = open(cache).read().strip().splitlines()
-    assert len(lines) == 1 and lines[0].endswith(f"\t{g} {t}")
-    B.schedule = (0, 256)
+    assert len(lines) == 1 and lines[0].endswith(f"\t{f} {g} {t} {br}")
+    B.schedule = (0, 0, 256, 0)
     s2 = B.autotune(0.25, cache)  # answered from the cache, nothing timed
     assert s2 == s1 and len(open(cache).read().strip().splitlines()) == 1
     # timing runs added into the tallies: zero, then one production run
@@ -205,13 +208,22 @@ def test_batch_errors(torch_cuda, edct_jobs):
     with pytest.raises(m.MxrError):
         m.Batch([(I, 10, 1, 1 << 24, I.new_tallies())])  # job field too wide
     with pytest.raises(m.MxrError):
-        m.Batch([(I, 10, 1, 0, I.new_tallies())], schedule=(9, 256))
+        m.Batch([(I, 10, 1, 0, I.new_tallies())], schedule=(1, 9, 256, 0))
     with pytest.raises(m.MxrError):
-        m.Batch([(I, 10, 1, 0, I.new_tallies())], schedule=(2, 300))
+        m.Batch([(I, 10, 1, 0, I.new_tallies())], schedule=(1, 2, 300, 0))
     with pytest.raises(m.MxrError):
-        m.Batch([(I, 10, 1, 0, I.new_tallies())], schedule=(0, 512))
+        m.Batch([(I, 10, 1, 0, I.new_tallies())], schedule=(2, 0, 0, 5))
+    with pytest.raises(m.MxrError):
+        m.Batch([(I, 10, 1, 0, I.new_tallies())], schedule=(3, 0, 0, 0))
     B = m.Batch([(I, 10, 1, 0, I.new_tallies())])
     with pytest.raises(m.MxrError):
         B.autotune(0.0)
     with pytest.raises(m.MxrError):
-        B.schedule = (3, 100)
+        B.schedule = (1, 3, 100, 0)
+    # a proposal on a job's instrument is refused (batches trace the plain source)
+    import torch
+    P = m.Instrument(ins)
+    g = np.tile([1 / 8, 0.0, 0.0, 80.0, 0.02, 0.02, 30.0], 8)
+    P.set_proposal(torch.tensor(g, device="cuda"), 0.1)
+    with pytest.raises(m.MxrError):
+        m.Batch([(P, 10, 1, 0, P.new_tallies())])
