@@ -44,9 +44,13 @@ def parse():
     p.add_argument("--rays", type=int, default=N_RAYS)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample", type=int, default=4_000_000)
-    p.add_argument("--workload", choices=("projection", "batch"), default="projection",
+    p.add_argument("--train-hits", type=int, default=10**8, help="learned: detector hits collected for training")
+    p.add_argument("--epochs", type=int, default=5, help="learned: training epochs")
+    p.add_argument("--eval-rays", type=int, default=16 * 10**8, help="learned: rays per error evaluation (16 replicas)")
+    p.add_argument("--workload", choices=("projection", "batch", "learned"), default="projection",
                    help="projection: one 1e9-ray projection of the 256^3 phantom per step; batch: every angle "
-                        "of phantoms of uneven size in one captured launch per step, beside one launch per job")
+                        "of phantoms of uneven size in one captured launch per step, beside one launch per job; "
+                        "learned: time to 1%% per-bin error of the plain and the learned-proposal source")
     p.add_argument("--batch-rays", type=int, default=10**8, help="rays per job of the batch")
     p.add_argument("--batch-angles", type=int, default=360)
     p.add_argument("--batch-sizes", default="64,128,256,512", help="phantom edges (voxels) of the batch")
@@ -54,6 +58,31 @@ def parse():
                    help="copy 1 GiB device to device before the timed region: a kernel of known traffic "
                         "for scaling the FETCH_SIZE / WRITE_SIZE counters")
     return p.parse_args()
+
+
+KERNEL_SOURCES = ["paper_2410_08747_amd/csrc/mxr.hip", "paper_2410_08747_amd/csrc/mxr_device.h", "include/mxr.h",
+                  "paper_2410_08747_amd/build.py"]
+PROFILE = "profiles/k_trace_edct_projection_256.md"
+
+
+def measured_traffic():
+    """HBM bytes per launch of the projection kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counters, scaled by the copy calibration; None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    try:
+        with open(os.path.join(ROOT, PROFILE)) as fh:
+            line = [l for l in fh if l.startswith("counters:")][-1]
+    except (OSError, IndexError):
+        return None
+    kv = dict(x.split("=") for x in line.split()[1:])
+    if kv.get("source") != h.hexdigest()[:16]:
+        return None
+    return (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) + float(kv["write_kib"]) * float(kv["write_scale"])) * 1024.0
 
 
 def cpu_baseline(instr, n_sample: int, n_total: int):
@@ -190,6 +219,134 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def learned_bench(args):
+    """Time to 1 % per-bin relative error (q95 over signal bins, batch means
+    over 16 replicas) of the plain stratified source and of the learned
+    proposal on the 256^3 projection; the learned time includes collecting
+    the training rays, the weights, training and inference."""
+    import torch
+    import paper_2410_08747_amd as mxr
+    import workloads
+    from paper_2410_08747_amd import metrics
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    vol = workloads.make_phantom(256, seed=1)
+    instr = workloads.edct_projection(vol, workloads.make_mu_tables(1), angle=0.0, strata=STRATA)
+    I = mxr.Instrument(instr, dev)
+    lo, hi = mxr.source_box(instr["components"][0])
+    nb = 256 * 64 * 128
+    R = 16
+    stream = torch.cuda.current_stream()
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+
+    def new_tally(sum_w=None):
+        return {"count": torch.zeros(nb, dtype=torch.int64, device=dev),
+                "sum_w": torch.zeros(nb, dtype=torch.float64, device=dev) if sum_w is None else sum_w,
+                "sum_w2": torch.zeros(nb, dtype=torch.float64, device=dev)}
+
+    def replicas(n_rays):
+        per = n_rays // R
+        sums = torch.zeros(R, nb, dtype=torch.float64, device=dev)
+        tallies = [[new_tally(sums[r])] for r in range(R)]
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for r in range(R):
+            I.run(per, seed=1, purpose=3 + r, tallies=tallies[r], stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        secs = e0.elapsed_time(e1) * 1e-3
+        mean, rel = mxr.batch_means(sums, per)
+        return mean.cpu().numpy(), rel.cpu().numpy(), secs, per * R
+
+    # reference image (purpose 2) and the signal bins
+    n_ref = 4 * 10**9
+    ref = [new_tally()]
+    I.run(n_ref, seed=7, purpose=2, tallies=ref)
+    torch.cuda.synchronize()
+    I_ref = ref[0]["sum_w"].cpu().numpy() / n_ref
+    var_ref = ref[0]["sum_w2"].cpu().numpy() / n_ref ** 2
+    I_flat = metrics.flat_field(instr)
+    mask = metrics.signal_bins(I_ref, I_flat)
+    log(f"reference {n_ref:.1e} rays, {mask.sum()} signal bins of {nb}")
+    del ref
+
+    # plain source
+    mp, rp, tp, n_p = replicas(args.eval_rays)
+    q_p = metrics.q95(rp, mask)
+    T_p = metrics.time_to_1pct(tp / n_p, n_p, q_p)
+    log(f"plain: {n_p:.2e} rays in {tp:.3f} s, q95 {q_p:.4f}, T_1% {T_p:.2f} s")
+
+    # learned proposal: training rays (purpose 1), weights, training, inference
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = workloads.projection_context(0.0, 256)
+    cap = int(args.train_hits)
+    hits = I.new_hits(cap)
+    coll = [new_tally()]
+    emitted = 0
+    chunk = 10**9
+    while int(hits["count"].item()) < cap:
+        I.collect(chunk, seed=1, context=ctx, hits=hits, first_ray=0, n_total=chunk, purpose=1, job=emitted // chunk,
+                  tallies=coll, stream=stream)
+        emitted += chunk
+    n_rows = min(int(hits["count"].item()), cap)
+    omega = mxr.train_weights(hits, n_rows, coll[0]["sum_w"])
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    net = mxr.ProposalNet(workloads.init_mlp_params(1), batch=65536, device=dev)
+    steps = args.epochs * ((n_rows + 65535) // 65536)
+    loss_log = torch.zeros(steps, dtype=torch.float64, device=dev)
+    net.train(hits["ctx"][:n_rows], hits["y"][:n_rows], omega, lo, hi, epochs=args.epochs, lr=1e-3, seed=1,
+              loss_log=loss_log, stream=stream)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0 - t_collect
+    out = net.forward(torch.tensor(ctx[None, :], device=dev))
+    gmm = net.mixture(out, lo, hi)
+    I.set_proposal(gmm[0], alpha=0.1)
+    torch.cuda.synchronize()
+    t_learn = time.perf_counter() - t0
+    ll = loss_log.cpu().numpy()
+    log(f"collected {n_rows:.2e} hits from {emitted:.1e} rays in {t_collect:.2f} s; trained {steps} steps in "
+        f"{t_train:.2f} s; loss {ll[:10].mean():.4f} -> {ll[-10:].mean():.4f}")
+    del hits, omega
+    ml, rl, tl, n_l = replicas(args.eval_rays)
+    q_l = metrics.q95(rl, mask)
+    T_l = metrics.time_to_1pct(tl / n_l, n_l, q_l)
+    # unbiased: the learned image agrees with the reference within errors
+    z = (ml - I_ref)[mask] / np.sqrt((rl * ml)[mask] ** 2 + var_ref[mask])
+    log(f"learned: {n_l:.2e} rays in {tl:.3f} s, q95 {q_l:.4f}, T_1% {T_l:.2f} s (+{t_learn:.2f} s to learn); "
+        f"|z| > 4 in {np.mean(np.abs(z) > 4):.2e} of signal bins, mean z^2 {np.mean(z * z):.3f}")
+    I.set_proposal(None)
+    out = {
+        "metric": METRIC,
+        "value": T_l + t_learn,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": (T_l + t_learn) * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "edct_projection_time_to_1pct", "phantom": "256^3 uint8, 1 mm voxels, seed 1",
+                   "detector": "256x64 px x 128 E-bins", "replicas": R, "eval_rays": n_p,
+                   "signal_bins": int(mask.sum()), "train_hits": n_rows, "epochs": args.epochs, "alpha": 0.1,
+                   "parallelism": "none (1 GPU)"},
+        "plain": {"rays_per_s": n_p / tp, "q95": q_p, "time_to_1pct_s": T_p},
+        "learned": {"rays_per_s": n_l / tl, "q95": q_l, "time_to_1pct_s": T_l, "learn_s": t_learn,
+                    "collect_s": t_collect, "train_s": t_train, "time_to_1pct_with_learning_s": T_l + t_learn,
+                    "loss_first": float(ll[:10].mean()), "loss_last": float(ll[-10:].mean()),
+                    "bias_mean_z2": float(np.mean(z * z))},
+        "gain_excl_learning": T_p / T_l,
+        "gain_incl_learning": T_p / (T_l + t_learn),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -198,6 +355,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         batch_bench(args)
+        return
+    if args.workload == "learned":
+        learned_bench(args)
         return
     import torch
     import paper_2410_08747_amd as mxr
@@ -261,7 +421,7 @@ def main():
         "config": {"workload": "edct_projection", "n_rays": n, "phantom": "256^3 uint8, 1 mm voxels, seed 1",
                    "detector": "256x64 px x 128 E-bins", "strata": STRATA, "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic()},
         "kernel_ms": kern_ms,
         "detected_fraction": detected / n,
     }

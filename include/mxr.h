@@ -375,6 +375,20 @@ mxr_status mxr_mlp_train(const float *ctx, const double *y, const double *omega,
                          void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Per-bin error of a detector image by batch means.
+ *
+ * sums: DEVICE array of R x n_bins doubles, row r the summed weights
+ * (mxr_tally.sum_w) of replica r, an independent run of rays_per_replica
+ * rays (e.g. purpose 3 + r).  Writes per bin the image mean_b = (1/R)
+ * sum_r sums_rb / rays_per_replica and its relative standard error rel_b =
+ * sd_r / (sqrt(R) mean_b) (sd with R - 1 degrees of freedom; +inf where
+ * mean_b = 0).  The estimate holds for stratified and importance-weighted
+ * runs alike.  Errors: MXR_E_INVALID (R < 2, no rays, null arrays),
+ * MXR_E_HIP. */
+mxr_status mxr_batch_means(const double *sums, uint32_t R, uint64_t n_bins, uint64_t rays_per_replica,
+                           double *mean, double *rel, void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Batched runs: many projections (angles) of many phantoms in one launch.
  *
  * A CT acquisition repeats one instrument for every projection angle of

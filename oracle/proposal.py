@@ -212,17 +212,9 @@ def adam(theta, m, v, g, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def init_params(seed: int) -> np.ndarray:
-    """Seeded initial weights: uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)),
-    biases zero, returned as float32 values."""
-    rng = np.random.default_rng(seed)
-    parts = {}
-    for name, shape in SHAPES:
-        if name.startswith("W"):
-            bound = 1.0 / math.sqrt(shape[0])
-            parts[name] = rng.uniform(-bound, bound, size=shape)
-        else:
-            parts[name] = np.zeros(shape)
-    return pack(parts).astype(np.float32).astype(np.float64)
+    """The seeded initial parameters (shared input generator), as float64."""
+    import workloads
+    return workloads.init_mlp_params(seed).astype(np.float64)
 
 
 def gemm_bound(A: np.ndarray, B: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:

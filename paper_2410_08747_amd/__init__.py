@@ -170,6 +170,8 @@ def _load() -> ctypes.CDLL:
     lib.mxr_train_weights.restype = ctypes.c_int
     lib.mxr_mlp_train.argtypes = [P, P, P, U64, ctypes.POINTER(mxr_train_cfg), D3, D3, P, P, P, P, P, P, U64, P, P]
     lib.mxr_mlp_train.restype = ctypes.c_int
+    lib.mxr_batch_means.argtypes = [P, ctypes.c_uint32, U64, U64, P, P, P]
+    lib.mxr_batch_means.restype = ctypes.c_int
     lib.mxr_batch_create.argtypes = [ctypes.POINTER(mxr_batch_job), ctypes.c_uint32,
                                      ctypes.POINTER(mxr_batch_schedule), ctypes.POINTER(ctypes.c_void_p)]
     lib.mxr_batch_create.restype = ctypes.c_int
@@ -291,6 +293,20 @@ def mxr_mlp_train(ctx, y, omega, n_rows, cfg: mxr_train_cfg, lo, hi, master, w, 
                   stream=None) -> None:
     _check(lib.mxr_mlp_train(ctx, y, omega, n_rows, ctypes.byref(cfg), _d3(lo), _d3(hi), master, w, m, v, grad, ws,
                              ws_bytes, loss_log, _stream_handle(stream)))
+
+
+def mxr_batch_means(sums_ptr, R, n_bins, rays_per_replica, mean_ptr, rel_ptr, stream=None) -> None:
+    _check(lib.mxr_batch_means(sums_ptr, R, n_bins, rays_per_replica, mean_ptr, rel_ptr, _stream_handle(stream)))
+
+
+def batch_means(sums, rays_per_replica: int, stream=None):
+    """(mean, rel) per bin of an (R, n_bins) float64 device tensor of replica sums."""
+    import torch
+    R, nb = sums.shape
+    mean = torch.empty(nb, dtype=torch.float64, device=sums.device)
+    rel = torch.empty(nb, dtype=torch.float64, device=sums.device)
+    mxr_batch_means(sums.contiguous().data_ptr(), R, nb, rays_per_replica, mean.data_ptr(), rel.data_ptr(), stream)
+    return mean, rel
 
 
 def mxr_batch_create(jobs: Sequence[mxr_batch_job], schedule: Optional[mxr_batch_schedule] = None) -> int:

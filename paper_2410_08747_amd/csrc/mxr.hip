@@ -483,7 +483,7 @@ struct KernelSet {
     }
 };
 
-enum RunMode { kModePlain = 0, kModeProposal, kModeCollect };
+enum RunMode { kModePlain = 0, kModeProposal, kModeCollect, kModeProposalCollect };
 
 // exact: the phantom's planes are reached exactly by adding the voxel edge
 // (chains without a phantom ignore it)
@@ -495,6 +495,8 @@ KernelFn pick_kernel(int recipe, bool ledger, bool trace, bool exact, int mode) 
         if (recipe == kRecipeEdct && mode == kModeCollect && !trace)
             return exact ? KernelSet<ChainEdctCollect, true>::get(ledger, false)
                          : KernelSet<ChainEdctCollect, false>::get(ledger, false);
+        // any other combination (e.g. a proposal while collecting) dispatches
+        // both on the run's arguments
         return exact ? KernelSet<ChainGeneric, true>::get(ledger, trace) : KernelSet<ChainGeneric, false>::get(ledger, trace);
     }
     switch (recipe) {
@@ -853,7 +855,8 @@ void mxr_instrument_destroy(mxr_instrument *ins) {
 static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, bool ledger, bool trace,
                          hipStream_t stream) {
     const bool exact = ins->host.phantom < 0 || ins->host.c[ins->host.phantom].aux[4] != 0.0;
-    const int mode = base.hits.count ? kModeCollect : (base.prop ? kModeProposal : kModePlain);
+    const int mode = base.hits.count ? (base.prop ? kModeProposalCollect : kModeCollect)
+                                     : (base.prop ? kModeProposal : kModePlain);
     KernelFn k = pick_kernel(ins->recipe, ledger, trace, exact, mode);
     size_t shmem = 0;
     if (ins->host.phantom >= 0) shmem += (size_t)ins->host.n_mat * ins->host.n_ebin * sizeof(double);

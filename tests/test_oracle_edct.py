@@ -120,3 +120,20 @@ def test_chunked_run_and_ledger():
     emitted = led[0]
     lost = sum(led[4 * k + 1] + led[4 * k + 2] for k in range(K))
     assert abs(emitted - (lost + led[4 * K])) <= 1e-12 * emitted
+
+
+def test_metrics_flat_field_matches_closed_form():
+    """The metric module's flat field equals this file's closed form (and
+    so the oracle's flat-field image, pinned above)."""
+    from paper_2410_08747_amd import metrics
+    vol = np.zeros((8, 8, 8), np.uint8)
+    ins = workloads.edct_projection(vol, np.zeros((8, 256)), nx=16, ny=4, ne=13)
+    src, det = ins["components"][0], ins["components"][2]
+    om = pixel_solid_angles(det, 1200.0)
+    cone = 4 * math.pi * math.sin(src["half_angle"] / 2) ** 2
+    edges = np.linspace(20.0, 150.0, 14)
+    want = (om[:, :, None] / cone * spectrum_bin_integral(src, edges[:-1], edges[1:])[None, None, :]).reshape(-1)
+    got = metrics.flat_field(ins)
+    assert np.allclose(got, want, rtol=1e-12, atol=0)
+    # a full detector sums to the fraction of the cone it covers times the band's mass
+    assert abs(got.sum() - om.sum() / cone * spectrum_bin_integral(src, 20.0, 150.0)) < 1e-12

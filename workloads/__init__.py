@@ -249,3 +249,28 @@ def beamline(d_spacings: np.ndarray = None, reflectivity: np.ndarray = None) -> 
 # batched CT: projection angles x phantoms of uneven size
 BATCH_SIZES = (64, 128, 256, 512)
 BATCH_ANGLES = 360
+
+
+# proposal network: 6 -> 128 -> 128 -> 56, packed W1, b1, W2, b2, W3, b3
+MLP_SHAPES = [(6, 128), (128,), (128, 128), (128,), (128, 56), (56,)]
+
+
+def init_mlp_params(seed: int) -> np.ndarray:
+    """Seeded initial parameters of the proposal network (float32 values):
+    weights uniform in +-1/sqrt(fan_in), biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            b = 1.0 / math.sqrt(shape[0])
+            parts.append(rng.uniform(-b, b, size=shape).reshape(-1))
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def projection_context(angle: float, n: int) -> np.ndarray:
+    """Context of a projection for the proposal network: focal-spot offset
+    (0, 0, 0) for a point source, (cos, sin) of the projection angle, and
+    log2(n) / 9 for an n^3 phantom."""
+    return np.array([0.0, 0.0, 0.0, math.cos(angle), math.sin(angle), math.log2(n) / 9.0], dtype=np.float32)
