@@ -220,23 +220,28 @@ mxr_status mxr_trace_rays(mxr_instrument *ins, const uint64_t *ray_ids, uint64_t
  *            [-tan a, tan a]^2 x [emin, emax] (a the cone half-angle), with
  *            density sum_k pi_k prod_d N(y_d; mu_kd, sigma_kd) / sum_k pi_k Z_k,
  *            Z_k the box mass of component k.
- * Draw order per ray: U0 picks the branch (plain when U0 < alpha), U1 the
- * component (probability pi_k Z_k / sum), U2..U4 the coordinates (plain
- * branch: concentric map of (U2, U3) with one stratum, E from U4; mixture
- * branch: truncated-normal inversion).  The ray's weight is p(y)/q(y), q the
- * full mixture density whichever branch drew it; a draw outside the cone is
- * absorbed at the source with weight 0.
- */
+ * Rays are drawn as a stratified deterministic mixture: the n_total ray ids
+ * of a run are split into contiguous ranges, [0, B0) for the plain source
+ * (B0 = round(alpha n_total)) and one per component, sized by the rounded
+ * running sums of the box masses pi_k Z_k.  Within its range a ray's first
+ * two uniforms are stratified over G x G cells (G the source's strata,
+ * reduced so G^2 <= the range size) exactly like the plain source; the plain
+ * branch maps them to the cone with the concentric map and draws E from the
+ * third uniform, a component inverts a truncated normal per coordinate (u,
+ * v from the stratified pair, E from the third uniform).  The ray's weight is
+ * p(y) / sum_b (n_b / n_total) q_b(y) times the cell factor (n_b / G^2) /
+ * n_cell: the balance heuristic of multiple importance sampling, unbiased
+ * for any split.  A draw outside the cone is absorbed at the source with
+ * weight 0.  The source still draws 3 uniforms per ray. */
 
 /* Makes later mxr_run / mxr_trace_rays / mxr_collect calls on this
- * instrument draw its cone-beam source from the proposal (runs are then
- * unstratified).  gmm: DEVICE array of 56 doubles, per component
+ * instrument draw its cone-beam source from the proposal.  gmm: DEVICE array of 56 doubles, per component
  * (pi, mu_u, mu_v, mu_E, sigma_u, sigma_v, sigma_E); pi >= 0 (need not sum
  * to 1), sigma > 0; it is copied (synchronously, after the device is idle),
  * so it may be freed afterwards.  alpha in [0, 1].  gmm NULL switches the
  * proposal off.  Errors: MXR_E_INVALID (values), MXR_E_UNSUPPORTED (the
- * first component is not a cone-beam source, or a later component draws
- * uniforms), MXR_E_STATE, MXR_E_NOMEM, MXR_E_HIP. */
+ * first component is not a cone-beam source), MXR_E_STATE, MXR_E_NOMEM,
+ * MXR_E_HIP. */
 mxr_status mxr_proposal_set(mxr_instrument *ins, const double *gmm, double alpha);
 
 /* Rows of training data: one per ray that reaches the monitor.  All arrays

@@ -138,6 +138,8 @@ def _load():
         lib.mxo_proposal_density.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
         lib.mxo_proposal_density.restype = ctypes.c_double
+        lib.mxo_proposal_bounds.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_uint64,
+                                            ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -336,3 +338,12 @@ def proposal_density(source: Dict, gmm, alpha: float, u: float, v: float, E: flo
     q = _load().mxo_proposal_density(ctypes.addressof(ins.arr[0].par), gp, float(alpha), float(u), float(v),
                                      float(E), _ptr(pp))
     return q, float(pp[0])
+
+
+def proposal_bounds(source: Dict, gmm, alpha: float, n_total: int) -> np.ndarray:
+    """The 9 branch boundaries of an n_total-ray proposal run."""
+    ins = Instrument({"components": [source]})
+    g, gp = _gmm(gmm)
+    B = np.zeros(9, np.uint64)
+    _load().mxo_proposal_bounds(ctypes.addressof(ins.arr[0].par), gp, float(alpha), int(n_total), _ptr(B))
+    return B

@@ -404,22 +404,82 @@ double mxo_proposal_density(const double *par, const double *gmm, double alpha_d
     return alpha_def * q_plain + (1.0 - alpha_def) * q_gmm;
 }
 
-/* Cone-beam point source drawing from the proposal mixture (unstratified).
- * Uniforms: U0 picks the branch (plain when U0 < alpha_def), U1 the mixture
- * component (probability proportional to pi_k Z_k), U2..U4 the coordinates
- * (u, v, E): the plain branch maps (U2, U3) to the cone like the plain
- * source with one stratum and takes E = emin + (emax - emin) U4; the mixture
- * branch inverts a truncated normal per coordinate.  w0 = p(y) / q(y) with q
- * the full mixture density whichever branch drew the ray; a draw outside the
- * cone has w0 = 0 and is absorbed at the source. */
-static int src_cone_proposal(const mxo_comp *c, mxo_stream *s, mxo_ray *ray, const double *gmm, double alpha_def)
+/* Branch boundaries of an n_total-ray proposal run: rays [0, B[0]) take
+ * the plain source, rays [B[k], B[k+1]) component k; B[0] = round(alpha
+ * n_total), B[k+1] - B[0] = round((n_total - B[0]) cum_k / total) with cum_k
+ * the running sum of the box masses pi_j Z_j, B[8] = n_total. */
+void mxo_proposal_bounds(const double *par, const double *gmm, double alpha_def, uint64_t n_total, uint64_t *B)
+{
+    double alpha = par[0], emin = par[1], emax = par[2];
+    double t = tan(alpha);
+    double lo[3] = {-t, -t, emin}, hi[3] = {t, t, emax};
+    double mass[8], total = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        const double *g = gmm + 7 * k;
+        double Z = g[0];
+        for (int d = 0; d < 3; ++d)
+            Z *= norm_cdf((hi[d] - g[1 + d]) / g[4 + d]) - norm_cdf((lo[d] - g[1 + d]) / g[4 + d]);
+        mass[k] = Z;
+        total += Z;
+    }
+    uint64_t n_plain = (uint64_t)floor(alpha_def * (double)n_total + 0.5);
+    if (n_plain > n_total)
+        n_plain = n_total;
+    B[0] = n_plain;
+    double cum = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        cum += mass[k];
+        uint64_t b = total > 0.0 ? n_plain + (uint64_t)floor((double)(n_total - n_plain) * (cum / total) + 0.5) : n_total;
+        B[k + 1] = b > n_total ? n_total : b;
+    }
+    B[8] = n_total;
+}
+
+/* Cone-beam point source drawing from the proposal as a stratified
+ * deterministic mixture.  The n_total rays are split into contiguous id
+ * ranges, one per branch (plain source, then components 0..7, sizes from
+ * mxo_proposal_bounds); within its branch a ray's first two uniforms are
+ * stratified over G x G cells of the unit square exactly like the plain
+ * stratified source (cell of local index i among n: floor(i G^2 / n), cell
+ * factor (n / G^2) / n_cell), so neighbouring ids leave in neighbouring
+ * directions.  The plain branch maps the stratified pair to the cone with the
+ * concentric map; a component inverts a truncated normal per coordinate (u
+ * from the first, v from the second, E from the third uniform).  The weight
+ * is the physical density over the realised mixture density,
+ * p(y) / (sum_b (n_b / n_total) q_b(y)), times the cell factor: the balance
+ * heuristic of multiple importance sampling, unbiased for any split.  A draw
+ * outside the cone has weight 0 and is absorbed at the source. */
+static int src_cone_proposal(const mxo_comp *c, mxo_stream *s, mxo_ray *ray, uint64_t ray_id, uint64_t n_total,
+                             const double *gmm, double alpha_def)
 {
     double alpha = c->par[0], emin = c->par[1], emax = c->par[2];
     double t = tan(alpha);
     double lo[3] = {-t, -t, emin}, hi[3] = {t, t, emax};
+    uint64_t B[9];
+    mxo_proposal_bounds(c->par, gmm, alpha_def, n_total, B);
+    int branch = -1; /* -1 plain, else the component */
+    uint64_t start = 0, count = B[0];
+    if (ray_id >= B[0]) {
+        for (int k = 0; k < 8; ++k) {
+            if (ray_id >= B[k] && ray_id < B[k + 1]) {
+                branch = k;
+                start = B[k];
+                count = B[k + 1] - B[k];
+                break;
+            }
+        }
+    }
+    uint64_t G = mxo_strata_side((uint64_t)c->dims[0], count);
+    uint64_t G2 = G * G, i = ray_id - start;
+    uint64_t cell = (i * G2) / count;
+    uint64_t first = (cell * count + G2 - 1) / G2;
+    uint64_t next = ((cell + 1) * count + G2 - 1) / G2;
+    double cell_factor = ((double)count / (double)G2) / (double)(next - first);
+    double su = ((double)(cell % G) + stream_uniform(s, 0)) / (double)G;
+    double sv = ((double)(cell / G) + stream_uniform(s, 1)) / (double)G;
     double y[3];
-    if (stream_uniform(s, 0) < alpha_def) {
-        double a = 2.0 * stream_uniform(s, 2) - 1.0, b = 2.0 * stream_uniform(s, 3) - 1.0;
+    if (branch < 0) {
+        double a = 2.0 * su - 1.0, b = 2.0 * sv - 1.0;
         double rad, ang;
         if (a == 0.0 && b == 0.0) {
             rad = 0.0;
@@ -436,38 +496,40 @@ static int src_cone_proposal(const mxo_comp *c, mxo_stream *s, mxo_ray *ray, con
         double dz = cos(theta);
         y[0] = sin(theta) * cos(psi) / dz;
         y[1] = sin(theta) * sin(psi) / dz;
-        y[2] = emin + (emax - emin) * stream_uniform(s, 4);
+        y[2] = emin + (emax - emin) * stream_uniform(s, 2);
     } else {
-        double mass[8], total = 0.0;
-        for (int k = 0; k < 8; ++k) {
-            const double *g = gmm + 7 * k;
-            double Z = g[0];
-            for (int d = 0; d < 3; ++d)
-                Z *= norm_cdf((hi[d] - g[1 + d]) / g[4 + d]) - norm_cdf((lo[d] - g[1 + d]) / g[4 + d]);
-            mass[k] = Z;
-            total += Z;
-        }
-        double target = stream_uniform(s, 1) * total, run = 0.0;
-        int pick = 7;
-        for (int k = 0; k < 8; ++k) {
-            run += mass[k];
-            if (target < run && mass[k] > 0.0) {
-                pick = k;
-                break;
-            }
-        }
-        const double *g = gmm + 7 * pick;
+        const double *g = gmm + 7 * branch;
+        double U[3] = {su, sv, stream_uniform(s, 2)};
         for (int d = 0; d < 3; ++d) {
             double mu = g[1 + d], sg = g[4 + d];
-            y[d] = mu + sg * mxo_truncnorm((lo[d] - mu) / sg, (hi[d] - mu) / sg, stream_uniform(s, 2 + d));
+            y[d] = mu + sg * mxo_truncnorm((lo[d] - mu) / sg, (hi[d] - mu) / sg, U[d]);
         }
     }
-    double p_phys;
-    double q = mxo_proposal_density(c->par, gmm, alpha_def, y[0], y[1], y[2], &p_phys);
+    /* realised mixture density at y */
+    double omega = 2.0 * M_PI * (1.0 - cos(alpha));
+    double J = pow(1.0 + y[0] * y[0] + y[1] * y[1], -1.5);
+    int in_cone = y[0] * y[0] + y[1] * y[1] <= t * t && y[2] >= emin && y[2] <= emax;
+    int in_box = y[0] >= lo[0] && y[0] <= hi[0] && y[1] >= lo[1] && y[1] <= hi[1] && y[2] >= emin && y[2] <= emax;
+    double q = in_cone ? ((double)B[0] / (double)n_total) * (J / omega / (emax - emin)) : 0.0;
+    for (int k = 0; k < 8; ++k) {
+        uint64_t nk = B[k + 1] - B[k];
+        if (nk == 0 || !in_box)
+            continue;
+        const double *g = gmm + 7 * k;
+        double dens = 1.0, Fk = 1.0;
+        for (int d = 0; d < 3; ++d) {
+            double mu = g[1 + d], sg = g[4 + d];
+            double z = (y[d] - mu) / sg;
+            dens *= exp(-0.5 * z * z) / (sg * sqrt(2.0 * M_PI));
+            Fk *= norm_cdf((hi[d] - mu) / sg) - norm_cdf((lo[d] - mu) / sg);
+        }
+        q += ((double)nk / (double)n_total) * (dens / Fk);
+    }
+    double p_phys = in_cone ? mxo_spectrum(c->par, y[2]) * J / omega : 0.0;
     double n = sqrt(1.0 + y[0] * y[0] + y[1] * y[1]);
     double qz[3] = {0.0, 0.0, 0.0}, dl[3] = {y[0] / n, y[1] / n, 1.0 / n};
     ray->E = y[2];
-    ray->w = p_phys > 0.0 ? p_phys / q : 0.0;
+    ray->w = p_phys > 0.0 ? (p_phys / q) * cell_factor : 0.0;
     to_lab(c, qz, dl, ray->r, ray->d);
     return p_phys > 0.0;
 }
@@ -948,7 +1010,7 @@ static void trace_one(const mxo_instr *I, uint64_t ray_id, mxo_ray *ray, mxo_tal
         case MXO_SRC_RECT_CONE: src_rect_cone(c, &s, ray); w_in = ray->w; break;
         case MXO_SRC_CONE_BEAM:
             if (I->gmm)
-                ok = src_cone_proposal(c, &s, ray, I->gmm, I->alpha_def);
+                ok = src_cone_proposal(c, &s, ray, ray_id, I->n_total, I->gmm, I->alpha_def);
             else
                 src_cone_beam(c, &s, ray, ray_id, I->n_total);
             w_in = ray->w;
@@ -963,7 +1025,7 @@ static void trace_one(const mxo_instr *I, uint64_t ray_id, mxo_ray *ray, mxo_tal
         case MXO_DETECTOR: ok = comp_detector(c, ray, &bin); break;
         default: ok = 0; break;
         }
-        draw += (c->type == MXO_SRC_CONE_BEAM && I->gmm) ? 5 : draws_of(c->type);
+        draw += draws_of(c->type);
         if (ledger)
             kadd(&ledger[4 * k + 0], w_in);
         if (!ok && k == 0) {

@@ -96,7 +96,7 @@ __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream 
         if constexpr (T == MXR_SRC_CONE_BEAM) src_cone_beam(c, s, ray, ray_id, a);
         if constexpr (T == MXR_SRC_GAUSSIAN) src_gaussian(c, s, ray);
         if constexpr (T == kSrcConeProposal) {
-            const bool ok = src_cone_proposal(c, a.prop, s, ray);
+            const bool ok = src_cone_proposal(c, a.prop, s, ray, ray_id, a);
             ledger_add<LEDGER>(L, 4 * k, ray.w);
             if (!ok) {  // drawn outside the cone: emitted with weight 0
                 end.status = kAbsorbed;
@@ -600,6 +600,7 @@ struct mxr_instrument {
     uint64_t det_bins[MXR_MAX_DETECTORS];
     uint64_t strata;      // G of the cone-beam source, 0 if none
     PropTable *prop_dev;  // proposal mixture (device), allocated on first use
+    PropTable prop_host;  // its host copy (branch sizes are set per run)
     bool prop_on;
 };
 
@@ -915,6 +916,30 @@ static mxr_status common_args(mxr_instrument *ins, uint64_t n_total, uint64_t se
     a.G2 = G * G;
     if (a.G2 > 1 && n_total > (~0ull) / a.G2) return fail(MXR_E_INVALID, "n_total * strata^2 must stay below 2^64");
     a.prop = ins->prop_on ? ins->prop_dev : nullptr;
+    if (ins->prop_on) {
+        // branch ranges of this run: plain share round(alpha n), then the
+        // components by their box masses (rounded running sums)
+        const PropTable &P = ins->prop_host;
+        uint64_t n_plain = (uint64_t)std::floor(P.alpha * (double)n_total + 0.5);
+        if (n_plain > n_total) n_plain = n_total;
+        a.pb[0] = n_plain;
+        double cum = 0.0;
+        for (int k = 0; k < 8; ++k) {
+            cum += P.mass[k];
+            uint64_t b = P.norm > 0.0 ? n_plain + (uint64_t)std::floor((double)(n_total - n_plain) * (cum / P.norm) + 0.5)
+                                      : n_total;
+            a.pb[k + 1] = b > n_total ? n_total : b;
+        }
+        a.pb[8] = n_total;
+        const uint64_t gmax = ins->strata ? ins->strata : 1;
+        for (int b = 0; b < 9; ++b) {
+            const uint64_t cnt = a.pb[b] - (b ? a.pb[b - 1] : 0);
+            uint64_t g = gmax;
+            while (g > 1 && g * g > cnt) g -= 1;
+            a.pG[b] = (uint32_t)g;
+            a.pc[b] = (double)cnt / (double)n_total;
+        }
+    }
     return MXR_OK;
 }
 
@@ -1001,8 +1026,6 @@ mxr_status mxr_proposal_set(mxr_instrument *ins, const double *gmm, double alpha
     }
     const DevInstr &d = ins->host;
     if (d.c[0].type != MXR_SRC_CONE_BEAM) return fail(MXR_E_UNSUPPORTED, "a proposal needs a cone-beam source");
-    for (uint32_t k = 1; k < d.ncomp; ++k)
-        if (draws_of(d.c[k].type)) return fail(MXR_E_UNSUPPORTED, "a proposal needs components that draw no uniforms");
     if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(MXR_E_INVALID, "alpha must be in [0, 1]");
     double g[56];
     e = hipMemcpy(g, gmm, sizeof g, hipMemcpyDeviceToHost);
@@ -1016,7 +1039,7 @@ mxr_status mxr_proposal_set(mxr_instrument *ins, const double *gmm, double alpha
     for (int k = 0; k < 8; ++k) {
         const double *gk = g + 7 * k;
         if (!std::isfinite(gk[0]) || gk[0] < 0.0) return fail(MXR_E_INVALID, "component %d: bad weight", k);
-        double Z = gk[0], sprod = 1.0;
+        double Z = gk[0], F = 1.0, sprod = 1.0;
         for (int dd = 0; dd < 3; ++dd) {
             const double mu = gk[1 + dd], sg = gk[4 + dd];
             if (!std::isfinite(mu) || !std::isfinite(sg) || !(sg > 0.0))
@@ -1030,12 +1053,12 @@ mxr_status mxr_proposal_set(mxr_instrument *ins, const double *gmm, double alpha
             P.Qa[k][dd] = 0.5 * std::erfc(za / std::sqrt(2.0));
             P.Qb[k][dd] = 0.5 * std::erfc(zb / std::sqrt(2.0));
             Z *= P.Pb[k][dd] - P.Pa[k][dd];
+            F *= P.Pb[k][dd] - P.Pa[k][dd];
             sprod *= sg;
         }
-        P.coef[k] = gk[0] / (sprod * std::pow(2.0 * M_PI, 1.5));
+        P.kcoef[k] = F > 0.0 ? 1.0 / (sprod * std::pow(2.0 * M_PI, 1.5) * F) : 0.0;
         P.mass[k] = Z;
         run += Z;
-        P.cum[k] = run;
     }
     P.norm = run;
     if (!(run > 0.0) && alpha < 1.0) return fail(MXR_E_INVALID, "the mixture has no mass inside the box");
@@ -1057,6 +1080,7 @@ mxr_status mxr_proposal_set(mxr_instrument *ins, const double *gmm, double alpha
     e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipMemcpy(ins->prop_dev, &P, sizeof P, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "upload of the proposal table");
+    ins->prop_host = P;
     ins->prop_on = true;
     return MXR_OK;
 }

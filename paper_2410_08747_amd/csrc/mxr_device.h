@@ -59,13 +59,15 @@ struct TallyPtrs {
 // Proposal mixture of a cone-beam source, prepared on the host from the
 // caller's 8 x (pi, mu[3], sigma[3]) table: per component the normal
 // distribution function (P) and its upper tail (Q) at the box edges, in
-// standard units, the running sums of the box masses pi_k Z_k, and the
-// density prefactor pi_k / (sigma_u sigma_v sigma_E (2 pi)^(3/2)).
+// standard units, the box masses pi_k Z_k, and the prefactor of the
+// component's own truncated density, 1 / (sigma_u sigma_v sigma_E
+// (2 pi)^(3/2) F_k) with F_k its box mass without pi_k (0 for an empty
+// component).
 struct PropTable {
-    double coef[8];
+    double kcoef[8];
     double mu[8][3], sigma[8][3], inv_sigma[8][3];
     double Pa[8][3], Pb[8][3], Qa[8][3], Qb[8][3];
-    double mass[8], cum[8];
+    double mass[8];
     double norm;       // sum_k pi_k Z_k
     double alpha;      // share of the plain source in the mixture
     double t2;         // tan^2 of the cone half-angle
@@ -95,7 +97,13 @@ struct RunArgs {
     const uint64_t *ids;  // trace mode: ray ids
     mxr_ray_soa dump;     // trace mode: outputs
     const PropTable *prop;  // proposal of the cone-beam source, or null
-    HitSink hits;           // hit-collecting runs
+    // proposal runs: branch b (plain, then components 0..7) takes ray ids
+    // [pb[b], pb[b+1]) (pb[0] = 0 is implicit: pb here holds the 9 upper
+    // bounds), stratified over pG[b]^2 cells; pc[b] = its share of the rays
+    uint64_t pb[9];
+    uint32_t pG[9];
+    double pc[9];
+    HitSink hits;  // hit-collecting runs
 };
 
 // ------------------------------------------------------------- Philox ----
@@ -268,18 +276,42 @@ __device__ __forceinline__ double trunc_normal(double Pa, double Pb, double Qa, 
 }
 
 // Cone-beam point source drawing y = (u, v, E), u = dx/dz, v = dy/dz, from
-// the mixture alpha q_plain + (1 - alpha) q_gmm (unstratified).  U0 picks
-// the branch (plain below alpha), U1 the mixture component (by box mass),
-// U2..U4 the coordinates: the plain branch maps (U2, U3) to the cone like the
-// plain source with one stratum, E = emin + (emax - emin) U4; the mixture
-// branch inverts a truncated normal per coordinate.  The weight is the
-// physical density over the full mixture density, p(y) / q(y).  A draw
+// the proposal as a stratified deterministic mixture: the run's ray ids are
+// split into contiguous ranges, one per branch (the plain source, then the 8
+// truncated-normal components, sized by alpha and the box masses); within its
+// range a ray's first two uniforms are stratified over G x G cells like the
+// plain source, so the rays of a wave leave in neighbouring directions.  The
+// plain branch maps the pair to the cone (concentric map), a component
+// inverts a truncated normal per coordinate (E from the third uniform).  The
+// weight is p(y) over the realised mixture density sum_b (n_b / n) q_b(y)
+// (balance heuristic: unbiased for any split) times the cell factor.  A draw
 // outside the cone gets weight 0 and the source returns false.
 __device__ __forceinline__ bool src_cone_proposal(const DevComp &c, const PropTable *__restrict__ P, Stream &s,
-                                                  Ray &ray) {
+                                                  Ray &ray, uint64_t ray_id, const RunArgs &a) {
+    int branch = -1;
+    uint64_t start = 0, count = a.pb[0];
+    uint32_t G = a.pG[0];
+    if (ray_id >= a.pb[0]) {
+        for (int k = 0; k < 8; ++k) {
+            if (ray_id < a.pb[k + 1]) {
+                branch = k;
+                start = a.pb[k];
+                count = a.pb[k + 1] - a.pb[k];
+                G = a.pG[k + 1];
+                break;
+            }
+        }
+    }
+    const uint64_t G2 = (uint64_t)G * G, i = ray_id - start;
+    const uint64_t cell = (i * G2) / count;
+    const uint64_t first = (cell * count + G2 - 1) / G2;
+    const uint64_t next = ((cell + 1) * count + G2 - 1) / G2;
+    const double factor = ((double)count / (double)G2) / (double)(next - first);
+    const double su = ((double)(cell % G) + s.u(0)) / (double)G;
+    const double sv = ((double)(cell / G) + s.u(1)) / (double)G;
     double y[3];
-    if (s.u(0) < P->alpha) {
-        double ca = 2.0 * s.u(2) - 1.0, cb = 2.0 * s.u(3) - 1.0;
+    if (branch < 0) {
+        double ca = 2.0 * su - 1.0, cb = 2.0 * sv - 1.0;
         double rad, ang;
         if (ca == 0.0 && cb == 0.0) {
             rad = 0.0;
@@ -299,42 +331,35 @@ __device__ __forceinline__ bool src_cone_proposal(const DevComp &c, const PropTa
         double dz = 1.0 - 2.0 * (sh * sh);
         y[0] = (k * (rad * cs)) / dz;
         y[1] = (k * (rad * sa)) / dz;
-        y[2] = c.par[1] + c.aux[1] * s.u(4);
+        y[2] = c.par[1] + c.aux[1] * s.u(2);
     } else {
-        const double target = s.u(1) * P->norm;
-        int pick = 7;
-        for (int k = 0; k < 8; ++k) {
-            if (target < P->cum[k] && P->mass[k] > 0.0) {
-                pick = k;
-                break;
-            }
-        }
+        const double U[3] = {su, sv, s.u(2)};
         for (int d = 0; d < 3; ++d) {
-            double z = trunc_normal(P->Pa[pick][d], P->Pb[pick][d], P->Qa[pick][d], P->Qb[pick][d], s.u(2 + d));
-            y[d] = P->mu[pick][d] + P->sigma[pick][d] * z;
+            double z = trunc_normal(P->Pa[branch][d], P->Pb[branch][d], P->Qa[branch][d], P->Qb[branch][d], U[d]);
+            y[d] = P->mu[branch][d] + P->sigma[branch][d] * z;
         }
     }
     const double r2 = y[0] * y[0] + y[1] * y[1];
     const bool in_cone = r2 <= P->t2 && y[2] >= P->lo[2] && y[2] <= P->hi[2];
     const bool in_box = y[0] >= P->lo[0] && y[0] <= P->hi[0] && y[1] >= P->lo[1] && y[1] <= P->hi[1] &&
                         y[2] >= P->lo[2] && y[2] <= P->hi[2];
-    double num = 0.0;
-    for (int k = 0; k < 8; ++k) {
-        double zu = (y[0] - P->mu[k][0]) * P->inv_sigma[k][0];
-        double zv = (y[1] - P->mu[k][1]) * P->inv_sigma[k][1];
-        double ze = (y[2] - P->mu[k][2]) * P->inv_sigma[k][2];
-        num += P->coef[k] * exp(-0.5 * (zu * zu + zv * zv + ze * ze));
-    }
     const double J = pow(1.0 + r2, -1.5);
-    const double q_plain = in_cone ? J * P->inv_omega / c.aux[1] : 0.0;
-    const double q_gmm = in_box ? num / P->norm : 0.0;
-    const double q = P->alpha * q_plain + (1.0 - P->alpha) * q_gmm;
+    double q = in_cone ? a.pc[0] * (J * P->inv_omega / c.aux[1]) : 0.0;
+    if (in_box) {
+        for (int k = 0; k < 8; ++k) {
+            if (a.pc[k + 1] == 0.0) continue;
+            double zu = (y[0] - P->mu[k][0]) * P->inv_sigma[k][0];
+            double zv = (y[1] - P->mu[k][1]) * P->inv_sigma[k][1];
+            double ze = (y[2] - P->mu[k][2]) * P->inv_sigma[k][2];
+            q += a.pc[k + 1] * (P->kcoef[k] * exp(-0.5 * (zu * zu + zv * zv + ze * ze)));
+        }
+    }
     const double p_phys = in_cone ? spectrum(c, y[2]) * J * P->inv_omega : 0.0;
     const double n = sqrt(1.0 + r2);
     double dl[3] = {y[0] / n, y[1] / n, 1.0 / n};
     double q0[3] = {0.0, 0.0, 0.0};
     ray.E = y[2];
-    ray.w = p_phys > 0.0 ? p_phys / q : 0.0;
+    ray.w = p_phys > 0.0 ? (p_phys / q) * factor : 0.0;
     to_lab(c, q0, dl, ray);
     return p_phys > 0.0;
 }

@@ -277,3 +277,33 @@ def test_gemm_bound_holds_for_float32_accumulation():
     for k in range(128):
         acc = (acc + (A[:, k:k + 1] * B[k:k + 1, :]).astype(np.float32)).astype(np.float32)
     assert np.all(np.abs(acc - exact) <= bound)
+
+
+def test_branch_sizes_follow_the_masses():
+    src = cone_source()
+    gmm = synthetic_gmm(11, src)
+    lo, hi = P.box_of(src)
+    g = gmm.reshape(8, 7)
+    Z = g[:, 0] * np.prod([stats.norm.cdf(hi[d], g[:, 1 + d], g[:, 4 + d]) - stats.norm.cdf(lo[d], g[:, 1 + d], g[:, 4 + d])
+                           for d in range(3)], axis=0)
+    for N, alpha in ((10**9, 0.1), (12345, 0.3), (7, 0.5), (1000, 0.0), (1000, 1.0)):
+        B = oracle.proposal_bounds(src, gmm, alpha, N).astype(np.int64)
+        assert B[0] == int(np.floor(alpha * N + 0.5)) and B[8] == N
+        assert np.all(np.diff(B) >= 0)
+        want = (N - B[0]) * Z / Z.sum()
+        assert np.all(np.abs(np.diff(B) - want) <= 1.0 + 1e-9 * N)
+
+
+def test_all_plain_split_is_the_plain_source():
+    """alpha = 1: every ray takes the plain branch with the plain source's
+    strata, uniforms and weight 130 S(E) x cell factor, so the rays equal
+    the plain stratified source's, ray by ray."""
+    ins = workloads.edct_projection(workloads.make_phantom(64, 1), workloads.make_mu_tables(1), strata=64)
+    gmm = synthetic_gmm(12, ins["components"][0])
+    n = 20011
+    ids = np.arange(n)
+    a = oracle.trace_rays(ins, ids, seed=3, n_total=n, gmm=gmm, alpha=1.0)
+    b = oracle.trace_rays(ins, ids, seed=3, n_total=n)
+    assert np.array_equal(a["status"], b["status"]) and np.array_equal(a["bin"], b["bin"])
+    for k in ("d", "E", "w", "r"):
+        assert np.allclose(a[k], b[k], rtol=1e-12, atol=1e-12), k
