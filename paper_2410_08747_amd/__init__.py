@@ -124,6 +124,12 @@ class mxr_hits(ctypes.Structure):
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run paper_2410_08747_amd/build.py (or __graft_entry__.build())")
+    # torch ships its own HIP and HSA runtimes under the same sonames as the
+    # system ROCm libraries this library links.  Loading torch first makes
+    # libmxr.so bind to the runtime torch already uses; loading libmxr.so
+    # first would put two HIP runtimes on one HSA runtime in the process, and
+    # one of them then finds no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     lib.mxr_abi_version.restype = ctypes.c_uint32
     lib.mxr_last_error.restype = ctypes.c_char_p

@@ -103,15 +103,21 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
     const int r = lane & 15, q = lane >> 4;
     const int64_t m = tm * 16 + r, n = tn * 16 + r;
     v4f acc = {0.f, 0.f, 0.f, 0.f};
-    for (int64_t kb = k0; kb < k1; kb += 16) {
-        v4s a, b;
+    // four k-steps per iteration: their loads are in flight together (steps
+    // past the end load zeros and add nothing)
+    for (int64_t kb = k0; kb < k1; kb += 64) {
+        v4s a[4], b[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t k = kb + 4 * q + j;
-            a[j] = (m < g.M && k < k1) ? (short)g.A[m * g.sam + k * g.sak] : (short)0;
-            b[j] = (n < g.N && k < k1) ? (short)g.B[k * g.sbk + n * g.sbn] : (short)0;
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t k = kb + 16 * u + 4 * q + j;
+                a[u][j] = (m < g.M && k < k1) ? (short)g.A[m * g.sam + k * g.sak] : (short)0;
+                b[u][j] = (n < g.N && k < k1) ? (short)g.B[k * g.sbk + n * g.sbn] : (short)0;
+            }
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[u], b[u], acc, 0, 0, 0);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
