@@ -138,6 +138,9 @@ def _load():
         lib.mxo_proposal_density.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
         lib.mxo_proposal_density.restype = ctypes.c_double
+        lib.mxo_proposal_weight.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_uint64,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        lib.mxo_proposal_weight.restype = ctypes.c_double
         lib.mxo_proposal_bounds.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_uint64,
                                             ctypes.c_void_p]
         _lib = lib
@@ -347,3 +350,14 @@ def proposal_bounds(source: Dict, gmm, alpha: float, n_total: int) -> np.ndarray
     B = np.zeros(9, np.uint64)
     _load().mxo_proposal_bounds(ctypes.addressof(ins.arr[0].par), gp, float(alpha), int(n_total), _ptr(B))
     return B
+
+
+def proposal_weight(source: Dict, gmm, alpha: float, n_total: int, y: np.ndarray) -> np.ndarray:
+    """p(y) / q(y) of proposal draws y (m x 3: u, v, E) in an n_total-ray run
+    (without the stratification cell factor)."""
+    lib = _load()
+    ins = Instrument({"components": [source]})
+    g, gp = _gmm(gmm)
+    par = ctypes.addressof(ins.arr[0].par)
+    y = np.asarray(y, dtype=np.float64).reshape(-1, 3)
+    return np.array([lib.mxo_proposal_weight(par, gp, float(alpha), int(n_total), *row) for row in y])

@@ -435,6 +435,41 @@ void mxo_proposal_bounds(const double *par, const double *gmm, double alpha_def,
     B[8] = n_total;
 }
 
+/* Importance weight p(y) / q(y) of a proposal draw at y = (u, v, E) in an
+ * n_total-ray run, q the realised mixture density sum_b (n_b / n_total)
+ * q_b(y) (q_b the plain density or component b's truncated density); 0
+ * outside the cone. */
+double mxo_proposal_weight(const double *par, const double *gmm, double alpha_def, uint64_t n_total, double u,
+                           double v, double E)
+{
+    double alpha = par[0], emin = par[1], emax = par[2];
+    double t = tan(alpha);
+    double lo[3] = {-t, -t, emin}, hi[3] = {t, t, emax}, y[3] = {u, v, E};
+    uint64_t B[9];
+    mxo_proposal_bounds(par, gmm, alpha_def, n_total, B);
+    double omega = 2.0 * M_PI * (1.0 - cos(alpha));
+    double J = pow(1.0 + u * u + v * v, -1.5);
+    int in_cone = u * u + v * v <= t * t && E >= emin && E <= emax;
+    int in_box = u >= lo[0] && u <= hi[0] && v >= lo[1] && v <= hi[1] && E >= emin && E <= emax;
+    double q = in_cone ? ((double)B[0] / (double)n_total) * (J / omega / (emax - emin)) : 0.0;
+    for (int k = 0; k < 8; ++k) {
+        uint64_t nk = B[k + 1] - B[k];
+        if (nk == 0 || !in_box)
+            continue;
+        const double *g = gmm + 7 * k;
+        double dens = 1.0, Fk = 1.0;
+        for (int d = 0; d < 3; ++d) {
+            double mu = g[1 + d], sg = g[4 + d];
+            double z = (y[d] - mu) / sg;
+            dens *= exp(-0.5 * z * z) / (sg * sqrt(2.0 * M_PI));
+            Fk *= norm_cdf((hi[d] - mu) / sg) - norm_cdf((lo[d] - mu) / sg);
+        }
+        q += ((double)nk / (double)n_total) * (dens / Fk);
+    }
+    double p_phys = in_cone ? mxo_spectrum(par, E) * J / omega : 0.0;
+    return p_phys > 0.0 ? p_phys / q : 0.0;
+}
+
 /* Cone-beam point source drawing from the proposal as a stratified
  * deterministic mixture.  The n_total rays are split into contiguous id
  * ranges, one per branch (plain source, then components 0..7, sizes from
@@ -505,33 +540,13 @@ static int src_cone_proposal(const mxo_comp *c, mxo_stream *s, mxo_ray *ray, uin
             y[d] = mu + sg * mxo_truncnorm((lo[d] - mu) / sg, (hi[d] - mu) / sg, U[d]);
         }
     }
-    /* realised mixture density at y */
-    double omega = 2.0 * M_PI * (1.0 - cos(alpha));
-    double J = pow(1.0 + y[0] * y[0] + y[1] * y[1], -1.5);
-    int in_cone = y[0] * y[0] + y[1] * y[1] <= t * t && y[2] >= emin && y[2] <= emax;
-    int in_box = y[0] >= lo[0] && y[0] <= hi[0] && y[1] >= lo[1] && y[1] <= hi[1] && y[2] >= emin && y[2] <= emax;
-    double q = in_cone ? ((double)B[0] / (double)n_total) * (J / omega / (emax - emin)) : 0.0;
-    for (int k = 0; k < 8; ++k) {
-        uint64_t nk = B[k + 1] - B[k];
-        if (nk == 0 || !in_box)
-            continue;
-        const double *g = gmm + 7 * k;
-        double dens = 1.0, Fk = 1.0;
-        for (int d = 0; d < 3; ++d) {
-            double mu = g[1 + d], sg = g[4 + d];
-            double z = (y[d] - mu) / sg;
-            dens *= exp(-0.5 * z * z) / (sg * sqrt(2.0 * M_PI));
-            Fk *= norm_cdf((hi[d] - mu) / sg) - norm_cdf((lo[d] - mu) / sg);
-        }
-        q += ((double)nk / (double)n_total) * (dens / Fk);
-    }
-    double p_phys = in_cone ? mxo_spectrum(c->par, y[2]) * J / omega : 0.0;
+    double wgt = mxo_proposal_weight(c->par, gmm, alpha_def, n_total, y[0], y[1], y[2]);
     double n = sqrt(1.0 + y[0] * y[0] + y[1] * y[1]);
     double qz[3] = {0.0, 0.0, 0.0}, dl[3] = {y[0] / n, y[1] / n, 1.0 / n};
     ray->E = y[2];
-    ray->w = p_phys > 0.0 ? (p_phys / q) * cell_factor : 0.0;
+    ray->w = wgt > 0.0 ? wgt * cell_factor : 0.0;
     to_lab(c, qz, dl, ray->r, ray->d);
-    return p_phys > 0.0;
+    return wgt > 0.0;
 }
 
 /* Gaussian (undulator-like) source: position and angle normal in both

@@ -59,6 +59,32 @@ def mixtures(src):
     return out
 
 
+def sample_points(d, E):
+    """y = (dx/dz, dy/dz, E) of final rays (source at the origin, identity
+    frame; the projection chain keeps direction and energy)."""
+    return np.stack([d[:, 0] / d[:, 2], d[:, 1] / d[:, 2], E], 1)
+
+
+def weight_tolerance(ins, gmm, alpha, n_total, g, o):
+    """Per-ray weight tolerance: 1e-12 plus the weight change that the
+    difference between the two sides' sample points explains.  Both sides
+    draw a truncated-normal coordinate by inverting the normal distribution
+    function (the ROCm device erfcinv, Wichura's AS 241), which agree to a
+    few ulp; the weight p/q is steep in E on the flanks of the 0.3 keV
+    emission lines (|d ln S / dE| up to ~10 per keV), so a few ulp of E can
+    move it by ~1e-12.  The oracle evaluates its own weight function at both
+    sample points to measure that conditioning."""
+    src = ins["components"][0]
+    yg = sample_points(np.stack([cpu(g["dx"]), cpu(g["dy"]), cpu(g["dz"])], 1), cpu(g["E"]))
+    yo = sample_points(o["d"], o["E"])
+    tol = np.full(o["w"].size, 1e-12)
+    live = o["w"] > 0
+    Wg = oracle.proposal_weight(src, gmm, alpha, n_total, yg[live])
+    Wo = oracle.proposal_weight(src, gmm, alpha, n_total, yo[live])
+    tol[live] += 1.01 * np.abs(Wg / Wo - 1.0)
+    return tol
+
+
 @pytest.mark.parametrize("name", ["broad", "aimed", "tails"])
 @pytest.mark.parametrize("alpha", [0.1, 1.0, 0.0])
 def test_proposal_per_ray(torch_cuda, name, alpha):
@@ -72,7 +98,9 @@ def test_proposal_per_ray(torch_cuda, name, alpha):
     g = I.trace_rays(ids, seed=5, n_total=n, purpose=0, job=3)
     torch_cuda.cuda.synchronize()
     o = oracle.trace_rays(ins, ids, seed=5, n_total=n, job=3, gmm=gmm, alpha=alpha)
-    compare_rays(g, o, f"proposal {name} alpha {alpha}")
+    tol = weight_tolerance(ins, gmm, alpha, n, g, o)
+    assert np.mean(tol > 2e-12) < 1e-3  # the conditioned allowance is rare
+    compare_rays(g, o, f"proposal {name} alpha {alpha}", w_rel=tol)
 
 
 def test_proposal_per_bin_and_ledger(torch_cuda):
@@ -112,7 +140,8 @@ def test_proposal_generic_chain(torch_cuda):
     ids = np.arange(n, dtype=np.uint64)
     g = I.trace_rays(ids, seed=7, n_total=n)
     torch_cuda.cuda.synchronize()
-    compare_rays(g, oracle.trace_rays(ins, ids, seed=7, n_total=n, gmm=gmm, alpha=0.3), "generic proposal")
+    o = oracle.trace_rays(ins, ids, seed=7, n_total=n, gmm=gmm, alpha=0.3)
+    compare_rays(g, o, "generic proposal", w_rel=weight_tolerance(ins, gmm, 0.3, n, g, o))
 
 
 def detected_rows(o, src_rot=None):
