@@ -138,6 +138,12 @@ def _load():
         lib.mxo_proposal_density.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
         lib.mxo_proposal_density.restype = ctypes.c_double
+        lib.mxo_trace_after_source.argtypes = [
+            ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.c_void_p,
+        ]
         lib.mxo_proposal_weight.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_uint64,
                                             ctypes.c_double, ctypes.c_double, ctypes.c_double]
         lib.mxo_proposal_weight.restype = ctypes.c_double
@@ -361,3 +367,23 @@ def proposal_weight(source: Dict, gmm, alpha: float, n_total: int, y: np.ndarray
     par = ctypes.addressof(ins.arr[0].par)
     y = np.asarray(y, dtype=np.float64).reshape(-1, 3)
     return np.array([lib.mxo_proposal_weight(par, gp, float(alpha), int(n_total), *row) for row in y])
+
+
+def trace_after_source(instr: Dict, ids, seed: int, n_total: int, r, d, E, w, purpose: int = 0, job: int = 0):
+    """Final states of rays continued from the given states after the source
+    (r, d: m x 3; E, w: m) through the rest of the instrument."""
+    lib = _load()
+    ins = Instrument(instr)
+    ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint64))
+    n = ids.size
+    c = lambda a, shape: np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shape))
+    r_in, d_in, E_in, w_in = c(r, (n, 3)), c(d, (n, 3)), c(E, (n,)), c(w, (n,))
+    out = {
+        "r": np.zeros((n, 3)), "d": np.zeros((n, 3)), "E": np.zeros(n), "w": np.zeros(n),
+        "status": np.zeros(n, np.int32), "dead_at": np.zeros(n, np.int32), "bin": np.zeros(n, np.int64),
+    }
+    lib.mxo_trace_after_source(ctypes.addressof(ins.arr), ins.n, seed, n_total, purpose, job, _ptr(ids), n,
+                               _ptr(r_in), _ptr(d_in), _ptr(E_in), _ptr(w_in), _ptr(out["r"]), _ptr(out["d"]),
+                               _ptr(out["E"]), _ptr(out["w"]), _ptr(out["status"]), _ptr(out["dead_at"]),
+                               _ptr(out["bin"]))
+    return out

@@ -1007,7 +1007,9 @@ typedef struct {
     double alpha_def;  /* weight of the plain source in the proposal mixture */
 } mxo_instr;
 
-static void trace_one(const mxo_instr *I, uint64_t ray_id, mxo_ray *ray, mxo_tally *tallies, ksum *ledger)
+/* Carry one ray through components [k0, ncomp): k0 = 0 draws it at the
+ * source, k0 = 1 continues a ray whose source state the caller set. */
+static void trace_from(const mxo_instr *I, uint64_t ray_id, int k0, mxo_ray *ray, mxo_tally *tallies, ksum *ledger)
 {
     mxo_stream s;
     stream_init(&s, I->seed, ray_id, I->purpose, I->job);
@@ -1015,7 +1017,9 @@ static void trace_one(const mxo_instr *I, uint64_t ray_id, mxo_ray *ray, mxo_tal
     ray->dead_at = -1;
     ray->bin = -1;
     int draw = 0, det = 0;
-    for (int k = 0; k < I->ncomp; ++k) {
+    for (int k = 0; k < k0; ++k)
+        draw += draws_of(I->comps[k].type);
+    for (int k = k0; k < I->ncomp; ++k) {
         const mxo_comp *c = &I->comps[k];
         double w_in = ray->w;
         mxo_ray before = *ray;
@@ -1079,6 +1083,11 @@ static void trace_one(const mxo_instr *I, uint64_t ray_id, mxo_ray *ray, mxo_tal
     ray->status = MXO_EXITED;
     if (ledger)
         kadd(&ledger[4 * I->ncomp], ray->w);
+}
+
+static void trace_one(const mxo_instr *I, uint64_t ray_id, mxo_ray *ray, mxo_tally *tallies, ksum *ledger)
+{
+    trace_from(I, ray_id, 0, ray, tallies, ledger);
 }
 
 /* ----------------------------------------------------- exported runs ---- */
@@ -1183,6 +1192,38 @@ int mxo_trace_rays(const mxo_comp *comps, int ncomp, uint64_t seed, uint64_t n_t
         mxo_ray ray;
         memset(&ray, 0, sizeof ray);
         trace_one(&I, ids[i], &ray, NULL, NULL);
+        for (int k = 0; k < 3; ++k) {
+            r_out[3 * i + k] = ray.r[k];
+            d_out[3 * i + k] = ray.d[k];
+        }
+        E_out[i] = ray.E;
+        w_out[i] = ray.w;
+        status_out[i] = ray.status;
+        dead_out[i] = ray.dead_at;
+        bin_out[i] = ray.bin;
+    }
+    return 0;
+}
+
+/* Continue the listed rays from a given state after the source (position
+ * r, direction d, energy E, weight w per ray; the random streams of later
+ * components are the rays' own) and report their final states. */
+int mxo_trace_after_source(const mxo_comp *comps, int ncomp, uint64_t seed, uint64_t n_total, uint32_t purpose,
+                           uint32_t job, const uint64_t *ids, int64_t n, const double *r_in, const double *d_in,
+                           const double *E_in, const double *w_in, double *r_out, double *d_out, double *E_out,
+                           double *w_out, int32_t *status_out, int32_t *dead_out, int64_t *bin_out)
+{
+    mxo_instr I = {comps, ncomp, seed, n_total, purpose, job, NULL, 0.0};
+    for (int64_t i = 0; i < n; ++i) {
+        mxo_ray ray;
+        memset(&ray, 0, sizeof ray);
+        for (int k = 0; k < 3; ++k) {
+            ray.r[k] = r_in[3 * i + k];
+            ray.d[k] = d_in[3 * i + k];
+        }
+        ray.E = E_in[i];
+        ray.w = w_in[i];
+        trace_from(&I, ids[i], 1, &ray, NULL, NULL);
         for (int k = 0; k < 3; ++k) {
             r_out[3 * i + k] = ray.r[k];
             d_out[3 * i + k] = ray.d[k];

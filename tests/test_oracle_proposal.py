@@ -307,3 +307,24 @@ def test_all_plain_split_is_the_plain_source():
     assert np.array_equal(a["status"], b["status"]) and np.array_equal(a["bin"], b["bin"])
     for k in ("d", "E", "w", "r"):
         assert np.allclose(a[k], b[k], rtol=1e-12, atol=1e-12), k
+
+
+def test_continuing_after_the_source_reproduces_the_trace():
+    """The oracle's continuation from a given post-source state, fed its own
+    source states, reproduces its full traces bit for bit."""
+    ins = workloads.edct_projection(workloads.make_phantom(64, 1), workloads.make_mu_tables(1), strata=16)
+    src = ins["components"][0]
+    gmm = synthetic_gmm(13, src)
+    ids = np.arange(3000)
+    full = oracle.trace_rays(ins, ids, seed=5, n_total=3000, job=3, gmm=gmm, alpha=0.1)
+    s0 = oracle.trace_rays({"components": [src]}, ids, seed=5, n_total=3000, job=3, gmm=gmm, alpha=0.1)
+    live = s0["status"] != oracle.STATUS_ABSORBED
+    c = oracle.trace_after_source(ins, ids[live], 5, 3000, s0["r"][live], s0["d"][live], s0["E"][live],
+                                  s0["w"][live], job=3)
+    for k in ("r", "d", "E", "w", "status", "dead_at", "bin"):
+        assert np.array_equal(c[k], full[k][live]), k
+    # and the weight function times the stratum factor is the source weight
+    y = np.stack([s0["d"][:, 0] / s0["d"][:, 2], s0["d"][:, 1] / s0["d"][:, 2], s0["E"]], 1)[live]
+    W = oracle.proposal_weight(src, gmm, 0.1, 3000, y)
+    f = s0["w"][live] / W
+    assert np.all(f > 0.2) and np.all(f < 5.0)
