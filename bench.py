@@ -285,13 +285,17 @@ def learned_bench(args):
     cap = int(args.train_hits)
     hits = I.new_hits(cap)
     coll = [new_tally()]
-    emitted = 0
-    chunk = 10**9
-    while int(hits["count"].item()) < cap:
-        I.collect(chunk, seed=1, context=ctx, hits=hits, first_ray=0, n_total=chunk, purpose=1, job=emitted // chunk,
-                  tallies=coll, stream=stream)
-        emitted += chunk
-    n_rows = min(int(hits["count"].item()), cap)
+    # every run covers the whole cone (stratified over its own n_total), and
+    # every hit of a run must fit: a short pilot run measures the detected
+    # fraction, the main run is sized to fill the rest of the buffer
+    pilot = max(10**6, cap // 100)
+    I.collect(pilot, seed=1, context=ctx, hits=hits, purpose=1, job=0, tallies=coll, stream=stream)
+    got = int(hits["count"].item())
+    main = int((cap - got) / (got / pilot) * 0.97)
+    I.collect(main, seed=1, context=ctx, hits=hits, purpose=1, job=1, tallies=coll, stream=stream)
+    emitted = pilot + main
+    n_rows = int(hits["count"].item())
+    assert n_rows <= cap, "training rows overflowed the buffer"
     omega = mxr.train_weights(hits, n_rows, coll[0]["sum_w"])
     torch.cuda.synchronize()
     t_collect = time.perf_counter() - t0

@@ -140,6 +140,105 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
     }
 }
 
+// Row-heavy products (n rows x at most 128 columns): one wave per 16-row
+// strip and all NT column tiles, so a k-step's A fragment is loaded once for
+// NT MFMAs.  AVEC / BVEC: the operand's four consecutive k of a lane are
+// contiguous and 8-byte aligned (unit k stride, row stride a multiple of 4),
+// read as one 8-byte load; otherwise element loads.
+template <int EPI, int NT, bool AVEC, bool BVEC>
+__global__ __launch_bounds__(kThreads) void k_gemm_strip(GemmArgs g) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t tm = (int64_t)blockIdx.x * 4 + wave;
+    if (tm * 16 >= g.M) return;  // whole wave: no barrier in this kernel
+    const int r = lane & 15, q = lane >> 4;
+    const int64_t m = tm * 16 + r;
+    v4f acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int64_t kb = 0; kb < g.K; kb += 16) {
+        const int64_t k = kb + 4 * q;
+        v4s a;
+        if (AVEC && m < g.M && k + 3 < g.K) {
+            a = *(const v4s *)(g.A + m * g.sam + k);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                a[j] = (m < g.M && k + j < g.K) ? (short)g.A[m * g.sam + (k + j) * g.sak] : (short)0;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int64_t n = (int64_t)t * 16 + r;
+            v4s b;
+            if (BVEC && n < g.N && k + 3 < g.K) {
+                b = *(const v4s *)(g.B + n * g.sbn + k);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    b[j] = (n < g.N && k + j < g.K) ? (short)g.B[(k + j) * g.sbk + n * g.sbn] : (short)0;
+            }
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t mm = tm * 16 + 4 * q + j, nn = (int64_t)t * 16 + r;
+            if (mm >= g.M || nn >= g.N) continue;
+            const float v = acc[t][j];
+            if constexpr (EPI == kEpiHidden) {
+                const float z = v + bf16_to_f32(g.bias[nn]);
+                g.Z[mm * g.ldc + nn] = z;
+                g.H[mm * g.ldc + nn] = f32_to_bf16(silu(z));
+            } else if constexpr (EPI == kEpiOut) {
+                g.C[mm * g.ldc + nn] = v + bf16_to_f32(g.bias[nn]);
+            } else {
+                const float dz = v * silu_grad(g.Z[mm * g.ldc + nn]);
+                g.C[mm * g.ldc + nn] = dz;
+                g.H[mm * g.ldc + nn] = f32_to_bf16(dz);
+            }
+        }
+    }
+}
+
+bool vec_ok(const uint16_t *p, int64_t s_k, int64_t s_row) {
+    return s_k == 1 && s_row % 4 == 0 && ((uintptr_t)p & 7) == 0;
+}
+
+// strip product with N <= 128 (8 tiles) or N <= 64 (4 tiles)
+template <int EPI>
+mxr_status gemm_strip(const GemmArgs &g, hipStream_t st) {
+    if (g.M == 0 || g.N == 0) return MXR_OK;
+    const bool av = vec_ok(g.A, g.sak, g.sam), bv = vec_ok(g.B, g.sbk, g.sbn);
+    const dim3 grid((unsigned)((g.M + 63) / 64));
+    if (g.N <= 64) {
+        if (av && bv) hipLaunchKernelGGL((k_gemm_strip<EPI, 4, true, true>), grid, dim3(kThreads), 0, st, g);
+        else hipLaunchKernelGGL((k_gemm_strip<EPI, 4, false, false>), grid, dim3(kThreads), 0, st, g);
+    } else {
+        if (av && bv) hipLaunchKernelGGL((k_gemm_strip<EPI, 8, true, true>), grid, dim3(kThreads), 0, st, g);
+        else hipLaunchKernelGGL((k_gemm_strip<EPI, 8, false, false>), grid, dim3(kThreads), 0, st, g);
+    }
+    return launch_check("MLP strip product");
+}
+
+// W^T copies of the three weight matrices (out x in, row-major), for the
+// forward products' unit-stride B operand.
+__global__ void k_transpose_weights(const uint16_t *w, uint16_t *wt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kIn * kHid) {  // W1: in 6 x out 128
+        const int a = i / kHid, b = i % kHid;
+        wt[kW1 + b * kIn + a] = w[kW1 + i];
+    }
+    if (i < kHid * kHid) {
+        const int a = i / kHid, b = i % kHid;
+        wt[kW2 + b * kHid + a] = w[kW2 + i];
+    }
+    if (i < kHid * kOut) {
+        const int a = i / kOut, b = i % kOut;
+        wt[kW3 + b * kHid + a] = w[kW3 + i];
+    }
+}
+
 mxr_status gemm(int epi, const GemmArgs &g, int64_t splits, hipStream_t st) {
     if (g.M == 0 || g.N == 0) return MXR_OK;
     const dim3 grid((unsigned)((g.N + 15) / 16), (unsigned)((g.M + 63) / 64), (unsigned)splits);
@@ -317,16 +416,34 @@ __global__ void k_head_params(const float *O, uint64_t n, float lo0, float lo1, 
 }
 
 // Bias gradients of one split: column sums of a float32 matrix over the
-// split's rows, into the split's partial.
-__global__ void k_colsum_partial(const float *X, int64_t n_rows, int64_t n_cols, int64_t ld, int64_t rows_per_split,
-                                 float *partial, int64_t split_stride) {
-    const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= n_cols) return;
+// split's rows, into the split's partial.  A work-group of 4 waves takes 64
+// columns; wave v sums rows v, v + 4, ... of the split with 8 independent
+// accumulators (their loads in flight together), and the 32 partial sums of
+// a column are added in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_colsum_partial(const float *X, int64_t n_rows, int64_t n_cols, int64_t ld,
+                                                        int64_t rows_per_split, float *partial, int64_t split_stride) {
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t col = (int64_t)blockIdx.x * 64 + lane;
     const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
     const int64_t r1 = std::min<int64_t>(r0 + rows_per_split, n_rows);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (col < n_cols) {
+        for (int64_t r = r0 + wave; r < r1; r += 32) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t rr = r + 4 * u;
+                if (rr < r1) acc[u] += X[rr * ld + col];
+            }
+        }
+    }
     float s = 0.f;
-    for (int64_t r = r0; r < r1; ++r) s += X[r * ld + col];
-    partial[(int64_t)blockIdx.y * split_stride + col] = s;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += acc[u];
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave == 0 && col < n_cols)
+        partial[(int64_t)blockIdx.y * split_stride + col] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // gradient[p] = sum over splits, in split order
@@ -429,6 +546,7 @@ Layout layout_for(uint64_t n) {
         splits_for(n) * kParams * 4,    // split partials of the gradient
         n * 3 * 8, n * 8, n * 8,        // gathered targets, weights, per-row loss
         (kSumBlocks + 2) * 8,           // reduction scratch + sum of weights + loss
+        kParams * 2,                    // W^T copies (bf16), same offsets as W
     };
     Layout L;
     uint64_t o = 0;
@@ -453,29 +571,30 @@ mxr_status check_device_ptrs(std::initializer_list<const void *> ps) {
 
 // forward of the n rows already gathered into the workspace (X)
 mxr_status forward_ws(const uint16_t *w, uint64_t n, void *ws, const Layout &L, hipStream_t st) {
+    uint16_t *wt = at<uint16_t>(ws, L, MXR_MLP_WS_WT);
+    hipLaunchKernelGGL(k_transpose_weights, dim3((kHid * kHid + kThreads - 1) / kThreads), dim3(kThreads), 0, st, w, wt);
+    mxr_status s = launch_check("weight transpose");
+    if (s != MXR_OK) return s;
     GemmArgs g{};
     g.M = (int64_t)n;
-    g.kchunk = 1 << 30;
-    // layer 1: X (n x 6) W1 (6 x 128)
+    // layer 1: X (n x 6) W1; B(k, n) = W1^T[n][k]
     g.A = at<uint16_t>(ws, L, MXR_MLP_WS_X), g.sam = kIn, g.sak = 1;
-    g.B = w + kW1, g.sbk = kHid, g.sbn = 1;
+    g.B = wt + kW1, g.sbk = 1, g.sbn = kIn;
     g.N = kHid, g.K = kIn, g.bias = w + kB1;
     g.Z = at<float>(ws, L, MXR_MLP_WS_Z1), g.H = at<uint16_t>(ws, L, MXR_MLP_WS_H1), g.ldc = kHid;
-    mxr_status s = gemm(kEpiHidden, g, 1, st);
-    if (s != MXR_OK) return s;
+    if ((s = gemm_strip<kEpiHidden>(g, st)) != MXR_OK) return s;
     // layer 2: H1 W2
     g.A = at<uint16_t>(ws, L, MXR_MLP_WS_H1), g.sam = kHid, g.sak = 1;
-    g.B = w + kW2, g.sbk = kHid, g.sbn = 1;
+    g.B = wt + kW2, g.sbk = 1, g.sbn = kHid;
     g.N = kHid, g.K = kHid, g.bias = w + kB2;
     g.Z = at<float>(ws, L, MXR_MLP_WS_Z2), g.H = at<uint16_t>(ws, L, MXR_MLP_WS_H2);
-    s = gemm(kEpiHidden, g, 1, st);
-    if (s != MXR_OK) return s;
+    if ((s = gemm_strip<kEpiHidden>(g, st)) != MXR_OK) return s;
     // layer 3: H2 W3 + b3 -> O
     g.A = at<uint16_t>(ws, L, MXR_MLP_WS_H2);
-    g.B = w + kW3, g.sbk = kOut, g.sbn = 1;
+    g.B = wt + kW3, g.sbk = 1, g.sbn = kHid;
     g.N = kOut, g.K = kHid, g.bias = w + kB3;
     g.C = at<float>(ws, L, MXR_MLP_WS_O), g.ldc = kOut;
-    return gemm(kEpiOut, g, 1, st);
+    return gemm_strip<kEpiOut>(g, st);
 }
 
 // loss and gradient of the n rows gathered into the workspace
@@ -519,15 +638,14 @@ mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const 
     g.M = kHid, g.N = kOut, g.ldc = kOut;
     g.C = part + kW3;
     if ((s = gemm(kEpiPartial, g, splits, st)) != MXR_OK) return s;
-    // dZ2 = (dO W3^T) * silu'(Z2)
+    // dZ2 = (dO W3^T) * silu'(Z2); B(k = out, n = in) = W3[in][out]
     GemmArgs b{};
-    b.kchunk = 1 << 30;
     b.M = (int64_t)n, b.N = kHid, b.K = kOut;
     b.A = h.dOh, b.sam = kOut, b.sak = 1;
     b.B = w + kW3, b.sbk = 1, b.sbn = kOut;
     b.Z = at<float>(ws, L, MXR_MLP_WS_Z2);
     b.C = at<float>(ws, L, MXR_MLP_WS_DZ2), b.H = at<uint16_t>(ws, L, MXR_MLP_WS_DZ2H), b.ldc = kHid;
-    if ((s = gemm(kEpiBackward, b, 1, st)) != MXR_OK) return s;
+    if ((s = gemm_strip<kEpiBackward>(b, st)) != MXR_OK) return s;
     // dW2 = H1^T dZ2
     g.A = at<uint16_t>(ws, L, MXR_MLP_WS_H1), g.sam = 1, g.sak = kHid;
     g.B = at<uint16_t>(ws, L, MXR_MLP_WS_DZ2H), g.sbk = kHid, g.sbn = 1;
@@ -540,7 +658,7 @@ mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const 
     b.B = w + kW2, b.sbk = 1, b.sbn = kHid;
     b.Z = at<float>(ws, L, MXR_MLP_WS_Z1);
     b.C = at<float>(ws, L, MXR_MLP_WS_DZ1), b.H = at<uint16_t>(ws, L, MXR_MLP_WS_DZ1H);
-    if ((s = gemm(kEpiBackward, b, 1, st)) != MXR_OK) return s;
+    if ((s = gemm_strip<kEpiBackward>(b, st)) != MXR_OK) return s;
     // dW1 = X^T dZ1
     g.A = at<uint16_t>(ws, L, MXR_MLP_WS_X), g.sam = 1, g.sak = kIn;
     g.B = at<uint16_t>(ws, L, MXR_MLP_WS_DZ1H), g.sbk = kHid, g.sbn = 1;
@@ -549,11 +667,11 @@ mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const 
     if ((s = gemm(kEpiPartial, g, splits, st)) != MXR_OK) return s;
     // bias gradients: column sums of dO, dZ2, dZ1 per split
     const dim3 cg1((kOut + 63) / 64, (unsigned)splits), cg2((kHid + 63) / 64, (unsigned)splits);
-    hipLaunchKernelGGL(k_colsum_partial, cg1, dim3(64), 0, st, (const float *)h.dO, (int64_t)n, (int64_t)kOut,
+    hipLaunchKernelGGL(k_colsum_partial, cg1, dim3(256), 0, st, (const float *)h.dO, (int64_t)n, (int64_t)kOut,
                        (int64_t)kOut, (int64_t)kSplitRows, part + kB3, (int64_t)kParams);
-    hipLaunchKernelGGL(k_colsum_partial, cg2, dim3(64), 0, st, (const float *)at<float>(ws, L, MXR_MLP_WS_DZ2),
+    hipLaunchKernelGGL(k_colsum_partial, cg2, dim3(256), 0, st, (const float *)at<float>(ws, L, MXR_MLP_WS_DZ2),
                        (int64_t)n, (int64_t)kHid, (int64_t)kHid, (int64_t)kSplitRows, part + kB2, (int64_t)kParams);
-    hipLaunchKernelGGL(k_colsum_partial, cg2, dim3(64), 0, st, (const float *)at<float>(ws, L, MXR_MLP_WS_DZ1),
+    hipLaunchKernelGGL(k_colsum_partial, cg2, dim3(256), 0, st, (const float *)at<float>(ws, L, MXR_MLP_WS_DZ1),
                        (int64_t)n, (int64_t)kHid, (int64_t)kHid, (int64_t)kSplitRows, part + kB1, (int64_t)kParams);
     hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(kParams)), dim3(kThreads), 0, st, (const float *)part,
                        splits, grad);
