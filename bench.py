@@ -7,8 +7,9 @@ throughout.  One step = one mxr_run of all 1e9 rays into freshly zeroed
 histograms; inputs are resident in HBM before the timed region.
 
 Prints one JSON line: throughput, the roofline of the tracing kernel (HIP
-events on the launch stream), and the CPU oracle timed on a bounded sample
-of the same run on the host cores.
+events on the launch stream), the time to 1 % per-bin error of the plain and
+the learned-proposal source (time_to_1pct), and the CPU oracle timed on a
+bounded sample of the same run on the host cores.
 """
 from __future__ import annotations
 
@@ -43,6 +44,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--rays", type=int, default=N_RAYS)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-learned", action="store_true", help="skip the time-to-1%% measurement (plain vs learned)")
     p.add_argument("--cpu-sample", type=int, default=4_000_000)
     p.add_argument("--train-hits", type=int, default=10**8, help="learned: detector hits collected for training")
     p.add_argument("--epochs", type=int, default=5, help="learned: training epochs")
@@ -219,7 +221,7 @@ def batch_bench(args):
     print(json.dumps(out), flush=True)
 
 
-def learned_bench(args):
+def time_to_1pct(args):
     """Time to 1 % per-bin relative error (q95 over signal bins, batch means
     over 16 replicas) of the plain stratified source and of the learned
     proposal on the 256^3 projection; the learned time includes collecting
@@ -323,30 +325,37 @@ def learned_bench(args):
     log(f"learned: {n_l:.2e} rays in {tl:.3f} s, q95 {q_l:.4f}, T_1% {T_l:.2f} s (+{t_learn:.2f} s to learn); "
         f"|z| > 4 in {np.mean(np.abs(z) > 4):.2e} of signal bins, mean z^2 {np.mean(z * z):.3f}")
     I.set_proposal(None)
+    return {
+        "replicas": R, "eval_rays": n_p, "signal_bins": int(mask.sum()), "train_hits": n_rows,
+        "train_rays": emitted, "epochs": args.epochs, "alpha": 0.1,
+        "plain": {"rays_per_s": n_p / tp, "q95": q_p, "time_to_1pct_s": T_p},
+        "learned": {"rays_per_s": n_l / tl, "q95": q_l, "time_to_1pct_s": T_l, "learn_s": t_learn,
+                    "collect_s": t_collect, "train_s": t_train, "time_to_1pct_with_learning_s": T_l + t_learn,
+                    "loss_first": float(ll[:10].mean()), "loss_last": float(ll[-10:].mean()),
+                    "bias_mean_z2": float(np.mean(z * z)), "bias_frac_abs_z_gt_4": float(np.mean(np.abs(z) > 4))},
+        "gain_excl_learning": T_p / T_l,
+        "gain_incl_learning": T_p / (T_l + t_learn),
+    }
+
+
+def learned_bench(args):
+    r = time_to_1pct(args)
     out = {
         "metric": METRIC,
-        "value": T_l + t_learn,
+        "value": r["learned"]["time_to_1pct_with_learning_s"],
         "unit": "s",
         "n_gpus": 1,
         "steps": 1,
         "warmup": 0,
-        "ms_per_step": (T_l + t_learn) * 1e3,
+        "ms_per_step": r["learned"]["time_to_1pct_with_learning_s"] * 1e3,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "edct_projection_time_to_1pct", "phantom": "256^3 uint8, 1 mm voxels, seed 1",
-                   "detector": "256x64 px x 128 E-bins", "replicas": R, "eval_rays": n_p,
-                   "signal_bins": int(mask.sum()), "train_hits": n_rows, "epochs": args.epochs, "alpha": 0.1,
-                   "parallelism": "none (1 GPU)"},
-        "plain": {"rays_per_s": n_p / tp, "q95": q_p, "time_to_1pct_s": T_p},
-        "learned": {"rays_per_s": n_l / tl, "q95": q_l, "time_to_1pct_s": T_l, "learn_s": t_learn,
-                    "collect_s": t_collect, "train_s": t_train, "time_to_1pct_with_learning_s": T_l + t_learn,
-                    "loss_first": float(ll[:10].mean()), "loss_last": float(ll[-10:].mean()),
-                    "bias_mean_z2": float(np.mean(z * z))},
-        "gain_excl_learning": T_p / T_l,
-        "gain_incl_learning": T_p / (T_l + t_learn),
+                   "detector": "256x64 px x 128 E-bins", "parallelism": "none (1 GPU)"},
+        "time_to_1pct": r,
     }
     print(json.dumps(out), flush=True)
 
@@ -429,6 +438,10 @@ def main():
         "kernel_ms": kern_ms,
         "detected_fraction": detected / n,
     }
+    if not args.no_learned:
+        del tallies, I
+        torch.cuda.empty_cache()
+        out["time_to_1pct"] = time_to_1pct(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(instr, args.cpu_sample, n)
     print(json.dumps(out), flush=True)

@@ -299,7 +299,8 @@ mxr_status mxr_collect(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays,
  * gradients of the pre-activations, PARTIAL per-split gradient partials,
  * Y (n x 3 f64) and W (n f64) gathered targets and weights, ROWLOSS (n f64),
  * SCALARS (reduction scratch), WT (the weight matrices transposed, bf16,
- * out x in row-major, at the parameter offsets of W1, W2, W3). */
+ * out x in row-major, at the parameter offsets of W1, W2, W3), COLS
+ * (per-tile column sums for the bias gradients). */
 #define MXR_MLP_WS_X 0
 #define MXR_MLP_WS_Z1 1
 #define MXR_MLP_WS_H1 2
@@ -318,7 +319,8 @@ mxr_status mxr_collect(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays,
 #define MXR_MLP_WS_ROWLOSS 15
 #define MXR_MLP_WS_SCALARS 16
 #define MXR_MLP_WS_WT 17
-#define MXR_MLP_WS_REGIONS 18
+#define MXR_MLP_WS_COLS 18
+#define MXR_MLP_WS_REGIONS 19
 
 typedef struct {
     float lr, beta1, beta2, eps; /* Adam (Kingma and Ba 2015) */

@@ -100,7 +100,7 @@ class mxr_batch_schedule(ctypes.Structure):
 
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 6, 128, 56, 24632
 WS_REGIONS = ("X", "Z1", "H1", "Z2", "H2", "O", "DO", "DOH", "DZ2", "DZ2H", "DZ1", "DZ1H", "PARTIAL", "Y", "W",
-              "ROWLOSS", "SCALARS", "WT")
+              "ROWLOSS", "SCALARS", "WT", "COLS")
 
 
 class mxr_train_cfg(ctypes.Structure):

@@ -87,6 +87,7 @@ struct GemmArgs {
     float *C;              // kEpiOut: output; kEpiBackward: dZ (float32) out; kEpiPartial: partial base
     int64_t ldc;           // row stride of C / Z / H
     int64_t split_stride;  // kEpiPartial: floats between the partials of consecutive splits
+    float *colpart;        // strip kEpiBackward: per 16-row tile column sums of dZ (ldc columns)
 };
 
 // One wave per 16 x 16 tile of C, four waves per work-group along M.  The
@@ -181,6 +182,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_strip(GemmArgs g) {
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
+        float cs = 0.f;  // kEpiBackward: this lane's 4 rows of column t*16 + r
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t mm = tm * 16 + 4 * q + j, nn = (int64_t)t * 16 + r;
@@ -196,9 +198,30 @@ __global__ __launch_bounds__(kThreads) void k_gemm_strip(GemmArgs g) {
                 const float dz = v * silu_grad(g.Z[mm * g.ldc + nn]);
                 g.C[mm * g.ldc + nn] = dz;
                 g.H[mm * g.ldc + nn] = f32_to_bf16(dz);
+                cs += dz;
             }
         }
+        if constexpr (EPI == kEpiBackward) {
+            // the tile's 16 rows: the four row groups of lanes r, r+16, r+32, r+48
+            cs += __shfl_xor(cs, 16, 64);
+            cs += __shfl_xor(cs, 32, 64);
+            const int64_t nn = (int64_t)t * 16 + r;
+            if (q == 0 && nn < g.N) g.colpart[tm * g.ldc + nn] = cs;
+        }
     }
+}
+
+// Bias gradients from per-part column sums: the partial of split z is the
+// in-order sum of parts [z pps, (z+1) pps) of a column.
+__global__ void k_colpart_reduce(const float *colpart, int64_t n_parts, int64_t cols, int64_t pps, int64_t splits,
+                                 float *partial, int64_t off) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= splits * cols) return;
+    const int64_t z = t / cols, c = t % cols;
+    const int64_t p1 = std::min<int64_t>((z + 1) * pps, n_parts);
+    float acc = 0.f;
+    for (int64_t p = z * pps; p < p1; ++p) acc += colpart[p * cols + c];
+    partial[z * (int64_t)kParams + off + c] = acc;
 }
 
 bool vec_ok(const uint16_t *p, int64_t s_k, int64_t s_row) {
@@ -308,6 +331,7 @@ struct HeadArgs {
     float *dO;
     uint16_t *dOh;
     double *row_loss;
+    float *colpart;  // per wave (64 rows) column sums of dO, 56 per wave
 };
 
 __device__ __forceinline__ float phi_pdf(float z) { return 0.3989422804014327f * expf(-0.5f * z * z); }
@@ -320,10 +344,11 @@ __device__ __forceinline__ float box_mass(float za, float zb) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_head_loss_grad(HeadArgs h) {
-    const uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= h.n) return;
+    const uint64_t gi = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const bool live = gi < h.n;
+    const uint64_t i = live ? gi : 0;  // lanes past the end compute row 0 with weight 0
     const float *o = h.O + i * kOut;
-    const float a = (float)(h.W[i] / *h.wsum);
+    const float a = live ? (float)(h.W[i] / *h.wsum) : 0.f;
     float y[3];
     for (int d = 0; d < 3; ++d) y[d] = (float)h.Y[i * 3 + d];
     float mx = -INFINITY;
@@ -356,7 +381,11 @@ __global__ __launch_bounds__(kThreads) void k_head_loss_grad(HeadArgs h) {
         S += pi[k] * Z[k];
     }
     const float lse = cmax + logf(sr);
-    h.row_loss[i] = (double)(a * (logf(S) - lse));
+    if (live) h.row_loss[i] = (double)(a * (logf(S) - lse));
+    const uint64_t wave = gi >> 6;
+    // lane 0 of each wave that holds a row writes its column sums (the
+    // region has ceil(n / 64) rows; waves wholly past the end write nothing)
+    const bool lane0 = (threadIdx.x & 63) == 0 && (wave << 6) < h.n;
     for (int k = 0; k < 8; ++k) {
         const float r = expf(comp[k] - lse);
         const float s = pi[k] * Z[k] / S;
@@ -382,8 +411,14 @@ __global__ __launch_bounds__(kThreads) void k_head_loss_grad(HeadArgs h) {
         }
         for (int j = 0; j < 7; ++j) {
             const float v = a * g[j];
-            h.dO[i * kOut + 7 * k + j] = v;
-            h.dOh[i * kOut + 7 * k + j] = f32_to_bf16(v);
+            if (live) {
+                h.dO[i * kOut + 7 * k + j] = v;
+                h.dOh[i * kOut + 7 * k + j] = f32_to_bf16(v);
+            }
+            // the wave's 64 rows of this column, by a fixed butterfly
+            float cs = v;
+            for (int off = 32; off > 0; off >>= 1) cs += __shfl_xor(cs, off, 64);
+            if (lane0) h.colpart[wave * kOut + 7 * k + j] = cs;
         }
     }
 }
@@ -413,37 +448,6 @@ __global__ void k_head_params(const float *O, uint64_t n, float lo0, float lo1, 
             g[4 + d] = (double)(half * (1e-3f + sp));
         }
     }
-}
-
-// Bias gradients of one split: column sums of a float32 matrix over the
-// split's rows, into the split's partial.  A work-group of 4 waves takes 64
-// columns; wave v sums rows v, v + 4, ... of the split with 8 independent
-// accumulators (their loads in flight together), and the 32 partial sums of
-// a column are added in a fixed order (deterministic).
-__global__ __launch_bounds__(256) void k_colsum_partial(const float *X, int64_t n_rows, int64_t n_cols, int64_t ld,
-                                                        int64_t rows_per_split, float *partial, int64_t split_stride) {
-    __shared__ float red[4][64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t col = (int64_t)blockIdx.x * 64 + lane;
-    const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
-    const int64_t r1 = std::min<int64_t>(r0 + rows_per_split, n_rows);
-    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (col < n_cols) {
-        for (int64_t r = r0 + wave; r < r1; r += 32) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int64_t rr = r + 4 * u;
-                if (rr < r1) acc[u] += X[rr * ld + col];
-            }
-        }
-    }
-    float s = 0.f;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s += acc[u];
-    red[wave][lane] = s;
-    __syncthreads();
-    if (wave == 0 && col < n_cols)
-        partial[(int64_t)blockIdx.y * split_stride + col] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // gradient[p] = sum over splits, in split order
@@ -547,6 +551,7 @@ Layout layout_for(uint64_t n) {
         n * 3 * 8, n * 8, n * 8,        // gathered targets, weights, per-row loss
         (kSumBlocks + 2) * 8,           // reduction scratch + sum of weights + loss
         kParams * 2,                    // W^T copies (bf16), same offsets as W
+        ((n + 15) / 16 * kHid * 2 + (n + 63) / 64 * kOut) * 4,  // per-part column sums (bias gradients)
     };
     Layout L;
     uint64_t o = 0;
@@ -619,6 +624,9 @@ mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const 
     h.dO = at<float>(ws, L, MXR_MLP_WS_DO);
     h.dOh = at<uint16_t>(ws, L, MXR_MLP_WS_DOH);
     h.row_loss = at<double>(ws, L, MXR_MLP_WS_ROWLOSS);
+    const int64_t tiles16 = ((int64_t)n + 15) / 16, waves64 = ((int64_t)n + 63) / 64;
+    float *cp2 = at<float>(ws, L, MXR_MLP_WS_COLS), *cp1 = cp2 + tiles16 * kHid, *cp3 = cp1 + tiles16 * kHid;
+    h.colpart = cp3;
     hipLaunchKernelGGL(k_head_loss_grad, dim3(blocks_for(n)), dim3(kThreads), 0, st, h);
     if ((s = launch_check("head")) != MXR_OK) return s;
     if (loss) {
@@ -645,6 +653,7 @@ mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const 
     b.B = w + kW3, b.sbk = 1, b.sbn = kOut;
     b.Z = at<float>(ws, L, MXR_MLP_WS_Z2);
     b.C = at<float>(ws, L, MXR_MLP_WS_DZ2), b.H = at<uint16_t>(ws, L, MXR_MLP_WS_DZ2H), b.ldc = kHid;
+    b.colpart = cp2;
     if ((s = gemm_strip<kEpiBackward>(b, st)) != MXR_OK) return s;
     // dW2 = H1^T dZ2
     g.A = at<uint16_t>(ws, L, MXR_MLP_WS_H1), g.sam = 1, g.sak = kHid;
@@ -658,6 +667,7 @@ mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const 
     b.B = w + kW2, b.sbk = 1, b.sbn = kHid;
     b.Z = at<float>(ws, L, MXR_MLP_WS_Z1);
     b.C = at<float>(ws, L, MXR_MLP_WS_DZ1), b.H = at<uint16_t>(ws, L, MXR_MLP_WS_DZ1H);
+    b.colpart = cp1;
     if ((s = gemm_strip<kEpiBackward>(b, st)) != MXR_OK) return s;
     // dW1 = X^T dZ1
     g.A = at<uint16_t>(ws, L, MXR_MLP_WS_X), g.sam = 1, g.sak = kIn;
@@ -665,14 +675,14 @@ mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const 
     g.M = kIn, g.N = kHid, g.ldc = kHid;
     g.C = part + kW1;
     if ((s = gemm(kEpiPartial, g, splits, st)) != MXR_OK) return s;
-    // bias gradients: column sums of dO, dZ2, dZ1 per split
-    const dim3 cg1((kOut + 63) / 64, (unsigned)splits), cg2((kHid + 63) / 64, (unsigned)splits);
-    hipLaunchKernelGGL(k_colsum_partial, cg1, dim3(256), 0, st, (const float *)h.dO, (int64_t)n, (int64_t)kOut,
-                       (int64_t)kOut, (int64_t)kSplitRows, part + kB3, (int64_t)kParams);
-    hipLaunchKernelGGL(k_colsum_partial, cg2, dim3(256), 0, st, (const float *)at<float>(ws, L, MXR_MLP_WS_DZ2),
-                       (int64_t)n, (int64_t)kHid, (int64_t)kHid, (int64_t)kSplitRows, part + kB2, (int64_t)kParams);
-    hipLaunchKernelGGL(k_colsum_partial, cg2, dim3(256), 0, st, (const float *)at<float>(ws, L, MXR_MLP_WS_DZ1),
-                       (int64_t)n, (int64_t)kHid, (int64_t)kHid, (int64_t)kSplitRows, part + kB1, (int64_t)kParams);
+    // bias gradients: per-split in-order sums of the fused per-part column sums
+    const int64_t pps16 = kSplitRows / 16, pps64 = kSplitRows / 64;
+    hipLaunchKernelGGL(k_colpart_reduce, dim3(blocks_for(splits * kOut)), dim3(kThreads), 0, st, (const float *)cp3,
+                       waves64, (int64_t)kOut, pps64, splits, part, (int64_t)kB3);
+    hipLaunchKernelGGL(k_colpart_reduce, dim3(blocks_for(splits * kHid)), dim3(kThreads), 0, st, (const float *)cp2,
+                       tiles16, (int64_t)kHid, pps16, splits, part, (int64_t)kB2);
+    hipLaunchKernelGGL(k_colpart_reduce, dim3(blocks_for(splits * kHid)), dim3(kThreads), 0, st, (const float *)cp1,
+                       tiles16, (int64_t)kHid, pps16, splits, part, (int64_t)kB1);
     hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(kParams)), dim3(kThreads), 0, st, (const float *)part,
                        splits, grad);
     return launch_check("gradient reduction");
