@@ -218,10 +218,17 @@ __global__ void k_colpart_reduce(const float *colpart, int64_t n_parts, int64_t 
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= splits * cols) return;
     const int64_t z = t / cols, c = t % cols;
-    const int64_t p1 = std::min<int64_t>((z + 1) * pps, n_parts);
-    float acc = 0.f;
-    for (int64_t p = z * pps; p < p1; ++p) acc += colpart[p * cols + c];
-    partial[z * (int64_t)kParams + off + c] = acc;
+    const int64_t p0 = z * pps, p1 = std::min<int64_t>((z + 1) * pps, n_parts);
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // eight loads in flight
+    for (int64_t p = p0; p < p1; p += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (p + u < p1) acc[u] += colpart[(p + u) * cols + c];
+    }
+    float sum = 0.f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sum += acc[u];
+    partial[z * (int64_t)kParams + off + c] = sum;
 }
 
 bool vec_ok(const uint16_t *p, int64_t s_k, int64_t s_row) {
@@ -331,7 +338,7 @@ struct HeadArgs {
     float *dO;
     uint16_t *dOh;
     double *row_loss;
-    float *colpart;  // per wave (64 rows) column sums of dO, 56 per wave
+    float *colpart;  // per wave (8 rows) column sums of dO, 56 per wave
 };
 
 __device__ __forceinline__ float phi_pdf(float z) { return 0.3989422804014327f * expf(-0.5f * z * z); }
@@ -343,83 +350,79 @@ __device__ __forceinline__ float box_mass(float za, float zb) {
     return 1.0f - 0.5f * (erfcf(-za * 0.70710678f) + erfcf(zb * 0.70710678f));
 }
 
+// Eight lanes per row, lane k of the group holding mixture component k;
+// row-level maxima and sums are butterflies over the group (xor 1, 2, 4).
+__device__ __forceinline__ float group8_max(float v) {
+    v = fmaxf(v, __shfl_xor(v, 1, 64));
+    v = fmaxf(v, __shfl_xor(v, 2, 64));
+    return fmaxf(v, __shfl_xor(v, 4, 64));
+}
+__device__ __forceinline__ float group8_sum(float v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    return v + __shfl_xor(v, 4, 64);
+}
+
 __global__ __launch_bounds__(kThreads) void k_head_loss_grad(HeadArgs h) {
-    const uint64_t gi = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint64_t gt = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    const uint64_t gi = gt >> 3;
+    const int k = (int)(gt & 7);
     const bool live = gi < h.n;
-    const uint64_t i = live ? gi : 0;  // lanes past the end compute row 0 with weight 0
-    const float *o = h.O + i * kOut;
+    const uint64_t i = live ? gi : 0;  // groups past the end compute row 0 with weight 0
+    const float *o = h.O + i * kOut + 7 * k;
     const float a = live ? (float)(h.W[i] / *h.wsum) : 0.f;
-    float y[3];
-    for (int d = 0; d < 3; ++d) y[d] = (float)h.Y[i * 3 + d];
-    float mx = -INFINITY;
-    for (int k = 0; k < 8; ++k) mx = fmaxf(mx, o[7 * k]);
-    float se = 0.f;
-    for (int k = 0; k < 8; ++k) se += expf(o[7 * k] - mx);
-    const float lse_logit = mx + logf(se);
-    float comp[8], pi[8], Z[8];
-    float cmax = -INFINITY;
-    for (int k = 0; k < 8; ++k) {
-        pi[k] = expf(o[7 * k] - lse_logit);
-        float c = o[7 * k] - lse_logit, zk = 1.f;
-        for (int d = 0; d < 3; ++d) {
-            const float cen = 0.5f * (h.lo[d] + h.hi[d]), half = 0.5f * (h.hi[d] - h.lo[d]);
-            const float mu = cen + half * tanhf(o[7 * k + 1 + d]);
-            const float raw = o[7 * k + 4 + d];
-            const float sp = raw > 20.f ? raw : log1pf(expf(raw));
-            const float sg = half * (1e-3f + sp);
-            const float z = (y[d] - mu) / sg;
-            c += -0.5f * z * z - logf(sg) - 0.91893853f;
-            zk *= box_mass((h.lo[d] - mu) / sg, (h.hi[d] - mu) / sg);
-        }
-        comp[k] = c;
-        Z[k] = zk;
-        cmax = fmaxf(cmax, c);
+    const float lg = o[0];
+    const float mx = group8_max(lg);
+    const float lse_logit = mx + logf(group8_sum(expf(lg - mx)));
+    const float pi = expf(lg - lse_logit);
+    float c = lg - lse_logit, zk = 1.f;
+    float t[3], sg[3], z[3], za[3], zb[3], F[3], raw_s[3];
+    for (int d = 0; d < 3; ++d) {
+        const float cen = 0.5f * (h.lo[d] + h.hi[d]), half = 0.5f * (h.hi[d] - h.lo[d]);
+        t[d] = tanhf(o[1 + d]);
+        const float mu = cen + half * t[d];
+        raw_s[d] = o[4 + d];
+        const float sp = raw_s[d] > 20.f ? raw_s[d] : log1pf(expf(raw_s[d]));
+        sg[d] = half * (1e-3f + sp);
+        z[d] = ((float)h.Y[i * 3 + d] - mu) / sg[d];
+        za[d] = (h.lo[d] - mu) / sg[d];
+        zb[d] = (h.hi[d] - mu) / sg[d];
+        F[d] = box_mass(za[d], zb[d]);
+        c += -0.5f * z[d] * z[d] - logf(sg[d]) - 0.91893853f;
+        zk *= F[d];
     }
-    float sr = 0.f, S = 0.f;
-    for (int k = 0; k < 8; ++k) {
-        sr += expf(comp[k] - cmax);
-        S += pi[k] * Z[k];
+    const float cmax = group8_max(c);
+    const float lse = cmax + logf(group8_sum(expf(c - cmax)));
+    const float S = group8_sum(pi * zk);
+    if (live && k == 0) h.row_loss[i] = (double)(a * (logf(S) - lse));
+    const float r = expf(c - lse);
+    const float s = pi * zk / S;
+    float g[7];
+    g[0] = s - r;
+    for (int d = 0; d < 3; ++d) {
+        const float half = 0.5f * (h.hi[d] - h.lo[d]);
+        const float pa = phi_pdf(za[d]), pb = phi_pdf(zb[d]);
+        const float dF_mu = -(pb - pa) / sg[d];
+        const float dF_sg = -(zb[d] * pb - za[d] * pa) / sg[d];
+        const float g_mu = -r * z[d] / sg[d] + s * dF_mu / F[d];
+        const float g_sg = -r * (z[d] * z[d] - 1.f) / sg[d] + s * dF_sg / F[d];
+        g[1 + d] = g_mu * half * (1.f - t[d] * t[d]);
+        g[4 + d] = g_sg * half / (1.f + expf(-raw_s[d]));
     }
-    const float lse = cmax + logf(sr);
-    if (live) h.row_loss[i] = (double)(a * (logf(S) - lse));
-    const uint64_t wave = gi >> 6;
-    // lane 0 of each wave that holds a row writes its column sums (the
-    // region has ceil(n / 64) rows; waves wholly past the end write nothing)
-    const bool lane0 = (threadIdx.x & 63) == 0 && (wave << 6) < h.n;
-    for (int k = 0; k < 8; ++k) {
-        const float r = expf(comp[k] - lse);
-        const float s = pi[k] * Z[k] / S;
-        float g[7];
-        g[0] = s - r;
-        for (int d = 0; d < 3; ++d) {
-            const float half = 0.5f * (h.hi[d] - h.lo[d]), cen = 0.5f * (h.lo[d] + h.hi[d]);
-            const float t = tanhf(o[7 * k + 1 + d]);
-            const float mu = cen + half * t;
-            const float raw = o[7 * k + 4 + d];
-            const float sp = raw > 20.f ? raw : log1pf(expf(raw));
-            const float sg = half * (1e-3f + sp);
-            const float z = (y[d] - mu) / sg;
-            const float za = (h.lo[d] - mu) / sg, zb = (h.hi[d] - mu) / sg;
-            const float F = box_mass(za, zb);
-            const float pa = phi_pdf(za), pb = phi_pdf(zb);
-            const float dF_mu = -(pb - pa) / sg;
-            const float dF_sg = -(zb * pb - za * pa) / sg;
-            const float g_mu = -r * z / sg + s * dF_mu / F;
-            const float g_sg = -r * (z * z - 1.f) / sg + s * dF_sg / F;
-            g[1 + d] = g_mu * half * (1.f - t * t);
-            g[4 + d] = g_sg * half / (1.f + expf(-raw));
+    const uint64_t wave = gt >> 6;  // 8 rows per wave
+    const bool writer = (threadIdx.x & 63) < 8 && (wave << 3) < h.n;
+    for (int j = 0; j < 7; ++j) {
+        const float v = a * g[j];
+        if (live) {
+            h.dO[i * kOut + 7 * k + j] = v;
+            h.dOh[i * kOut + 7 * k + j] = f32_to_bf16(v);
         }
-        for (int j = 0; j < 7; ++j) {
-            const float v = a * g[j];
-            if (live) {
-                h.dO[i * kOut + 7 * k + j] = v;
-                h.dOh[i * kOut + 7 * k + j] = f32_to_bf16(v);
-            }
-            // the wave's 64 rows of this column, by a fixed butterfly
-            float cs = v;
-            for (int off = 32; off > 0; off >>= 1) cs += __shfl_xor(cs, off, 64);
-            if (lane0) h.colpart[wave * kOut + 7 * k + j] = cs;
-        }
+        // the wave's 8 rows of this column: lanes k, k + 8, ..., k + 56
+        float cs = v;
+        cs += __shfl_xor(cs, 8, 64);
+        cs += __shfl_xor(cs, 16, 64);
+        cs += __shfl_xor(cs, 32, 64);
+        if (writer) h.colpart[wave * kOut + 7 * k + j] = cs;
     }
 }
 
@@ -551,7 +554,7 @@ Layout layout_for(uint64_t n) {
         n * 3 * 8, n * 8, n * 8,        // gathered targets, weights, per-row loss
         (kSumBlocks + 2) * 8,           // reduction scratch + sum of weights + loss
         kParams * 2,                    // W^T copies (bf16), same offsets as W
-        ((n + 15) / 16 * kHid * 2 + (n + 63) / 64 * kOut) * 4,  // per-part column sums (bias gradients)
+        ((n + 15) / 16 * kHid * 2 + (n + 7) / 8 * kOut) * 4,  // per-part column sums (bias gradients)
     };
     Layout L;
     uint64_t o = 0;
@@ -624,10 +627,10 @@ mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const 
     h.dO = at<float>(ws, L, MXR_MLP_WS_DO);
     h.dOh = at<uint16_t>(ws, L, MXR_MLP_WS_DOH);
     h.row_loss = at<double>(ws, L, MXR_MLP_WS_ROWLOSS);
-    const int64_t tiles16 = ((int64_t)n + 15) / 16, waves64 = ((int64_t)n + 63) / 64;
+    const int64_t tiles16 = ((int64_t)n + 15) / 16, groups8 = ((int64_t)n + 7) / 8;
     float *cp2 = at<float>(ws, L, MXR_MLP_WS_COLS), *cp1 = cp2 + tiles16 * kHid, *cp3 = cp1 + tiles16 * kHid;
     h.colpart = cp3;
-    hipLaunchKernelGGL(k_head_loss_grad, dim3(blocks_for(n)), dim3(kThreads), 0, st, h);
+    hipLaunchKernelGGL(k_head_loss_grad, dim3(blocks_for(8 * n)), dim3(kThreads), 0, st, h);
     if ((s = launch_check("head")) != MXR_OK) return s;
     if (loss) {
         s = sum_f64(h.row_loss, n, red, loss, st);
@@ -676,9 +679,9 @@ mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const 
     g.C = part + kW1;
     if ((s = gemm(kEpiPartial, g, splits, st)) != MXR_OK) return s;
     // bias gradients: per-split in-order sums of the fused per-part column sums
-    const int64_t pps16 = kSplitRows / 16, pps64 = kSplitRows / 64;
+    const int64_t pps16 = kSplitRows / 16, pps8 = kSplitRows / 8;
     hipLaunchKernelGGL(k_colpart_reduce, dim3(blocks_for(splits * kOut)), dim3(kThreads), 0, st, (const float *)cp3,
-                       waves64, (int64_t)kOut, pps64, splits, part, (int64_t)kB3);
+                       groups8, (int64_t)kOut, pps8, splits, part, (int64_t)kB3);
     hipLaunchKernelGGL(k_colpart_reduce, dim3(blocks_for(splits * kHid)), dim3(kThreads), 0, st, (const float *)cp2,
                        tiles16, (int64_t)kHid, pps16, splits, part, (int64_t)kB2);
     hipLaunchKernelGGL(k_colpart_reduce, dim3(blocks_for(splits * kHid)), dim3(kThreads), 0, st, (const float *)cp1,
