@@ -212,23 +212,35 @@ __global__ __launch_bounds__(kThreads) void k_gemm_strip(GemmArgs g) {
 }
 
 // Bias gradients from per-part column sums: the partial of split z is the
-// in-order sum of parts [z pps, (z+1) pps) of a column.
-__global__ void k_colpart_reduce(const float *colpart, int64_t n_parts, int64_t cols, int64_t pps, int64_t splits,
-                                 float *partial, int64_t off) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= splits * cols) return;
-    const int64_t z = t / cols, c = t % cols;
-    const int64_t p0 = z * pps, p1 = std::min<int64_t>((z + 1) * pps, n_parts);
-    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // eight loads in flight
-    for (int64_t p = p0; p < p1; p += 8) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (p + u < p1) acc[u] += colpart[(p + u) * cols + c];
+// sum of parts [z pps, (z+1) pps) of a column.  One launch serves the three
+// bias vectors (blockIdx.z); a work-group takes 32 columns of one split, its
+// 8 sub-lanes per column sum every 8th part, and the 8 sub-sums are added
+// in a fixed order (deterministic).
+struct ColReduce {
+    const float *parts[3];
+    int64_t n_parts[3], cols[3], pps[3], off[3];
+    int64_t splits;
+    float *partial;
+};
+
+__global__ __launch_bounds__(256) void k_colpart_reduce(ColReduce a) {
+    __shared__ float red[8][32];
+    const int b = blockIdx.z;
+    const int64_t cols = a.cols[b], pps = a.pps[b], n_parts = a.n_parts[b];
+    const int sub = threadIdx.x >> 5, cl = threadIdx.x & 31;
+    const int64_t c = (int64_t)blockIdx.x * 32 + cl, z = blockIdx.y;
+    float acc = 0.f;
+    if (c < cols) {
+        const int64_t p1 = std::min<int64_t>((z + 1) * pps, n_parts);
+        for (int64_t p = z * pps + sub; p < p1; p += 8) acc += a.parts[b][p * cols + c];
     }
-    float sum = 0.f;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) sum += acc[u];
-    partial[z * (int64_t)kParams + off + c] = sum;
+    red[sub][cl] = acc;
+    __syncthreads();
+    if (sub == 0 && c < cols) {
+        float sum = 0.f;
+        for (int u = 0; u < 8; ++u) sum += red[u][cl];
+        a.partial[z * (int64_t)kParams + a.off[b] + c] = sum;
+    }
 }
 
 bool vec_ok(const uint16_t *p, int64_t s_k, int64_t s_row) {
@@ -678,14 +690,14 @@ mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const 
     g.M = kIn, g.N = kHid, g.ldc = kHid;
     g.C = part + kW1;
     if ((s = gemm(kEpiPartial, g, splits, st)) != MXR_OK) return s;
-    // bias gradients: per-split in-order sums of the fused per-part column sums
-    const int64_t pps16 = kSplitRows / 16, pps8 = kSplitRows / 8;
-    hipLaunchKernelGGL(k_colpart_reduce, dim3(blocks_for(splits * kOut)), dim3(kThreads), 0, st, (const float *)cp3,
-                       groups8, (int64_t)kOut, pps8, splits, part, (int64_t)kB3);
-    hipLaunchKernelGGL(k_colpart_reduce, dim3(blocks_for(splits * kHid)), dim3(kThreads), 0, st, (const float *)cp2,
-                       tiles16, (int64_t)kHid, pps16, splits, part, (int64_t)kB2);
-    hipLaunchKernelGGL(k_colpart_reduce, dim3(blocks_for(splits * kHid)), dim3(kThreads), 0, st, (const float *)cp1,
-                       tiles16, (int64_t)kHid, pps16, splits, part, (int64_t)kB1);
+    // bias gradients: per-split sums of the fused per-part column sums
+    ColReduce cr;
+    cr.parts[0] = cp3, cr.n_parts[0] = groups8, cr.cols[0] = kOut, cr.pps[0] = kSplitRows / 8, cr.off[0] = kB3;
+    cr.parts[1] = cp2, cr.n_parts[1] = tiles16, cr.cols[1] = kHid, cr.pps[1] = kSplitRows / 16, cr.off[1] = kB2;
+    cr.parts[2] = cp1, cr.n_parts[2] = tiles16, cr.cols[2] = kHid, cr.pps[2] = kSplitRows / 16, cr.off[2] = kB1;
+    cr.splits = splits;
+    cr.partial = part;
+    hipLaunchKernelGGL(k_colpart_reduce, dim3((kHid + 31) / 32, (unsigned)splits, 3), dim3(256), 0, st, cr);
     hipLaunchKernelGGL(k_reduce_partials, dim3(blocks_for(kParams)), dim3(kThreads), 0, st, (const float *)part,
                        splits, grad);
     return launch_check("gradient reduction");
