@@ -49,10 +49,11 @@ def parse():
     p.add_argument("--train-hits", type=int, default=10**8, help="learned: detector hits collected for training")
     p.add_argument("--epochs", type=int, default=5, help="learned: training epochs")
     p.add_argument("--eval-rays", type=int, default=16 * 10**8, help="learned: rays per error evaluation (16 replicas)")
-    p.add_argument("--workload", choices=("projection", "batch", "learned"), default="projection",
+    p.add_argument("--workload", choices=("projection", "batch", "learned", "train"), default="projection",
                    help="projection: one 1e9-ray projection of the 256^3 phantom per step; batch: every angle "
                         "of phantoms of uneven size in one captured launch per step, beside one launch per job; "
-                        "learned: time to 1%% per-bin error of the plain and the learned-proposal source")
+                        "learned: time to 1%% per-bin error of the plain and the learned-proposal source; "
+                        "train: proposal-network training steps")
     p.add_argument("--batch-rays", type=int, default=10**8, help="rays per job of the batch")
     p.add_argument("--batch-angles", type=int, default=360)
     p.add_argument("--batch-sizes", default="64,128,256,512", help="phantom edges (voxels) of the batch")
@@ -360,6 +361,43 @@ def learned_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def train_bench(args):
+    """Proposal-network training throughput: 2^20 seeded synthetic rows
+    (random contexts, targets uniform in the box, weights in [0.1, 2]),
+    one warm-up epoch, then args.steps epochs of 65,536-row Adam steps;
+    rows/s, ms per step and the step's MFMA / HBM rooflines."""
+    import torch
+    import paper_2410_08747_amd as mxr
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    rng = np.random.default_rng(1)
+    n, batch = 1 << 20, 65536
+    lo, hi = (-0.176, -0.176, 20.0), (0.176, 0.176, 150.0)
+    ctx = torch.tensor(rng.normal(size=(n, 6)).astype(np.float32), device=dev)
+    y = torch.tensor(np.stack([rng.uniform(lo[d], hi[d], n) for d in range(3)], 1), device=dev)
+    w = torch.tensor(rng.uniform(0.1, 2.0, n), device=dev)
+    net = mxr.ProposalNet(workloads.init_mlp_params(1), batch=batch, device=dev)
+    net.train(ctx, y, w, lo, hi, epochs=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.train(ctx, y, w, lo, hi, epochs=args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    steps = args.steps * (n // batch)
+    flop = 2 * (6 * 128 + 128 * 128 + 128 * 56) * 3 * batch  # forward + two backward products per row
+    out = {
+        "metric": "proposal-network training rows/s", "value": steps * batch / dt, "unit": "rows/s", "n_gpus": 1,
+        "steps": steps, "warmup": n // batch, "ms_per_step": dt / steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "proposal_training", "rows": n, "batch": batch, "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "mfma", "achieved": flop / (dt / steps) / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": flop / (dt / steps) / 1e12 / 2500.0, "traffic": None},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -371,6 +409,9 @@ def main():
         return
     if args.workload == "learned":
         learned_bench(args)
+        return
+    if args.workload == "train":
+        train_bench(args)
         return
     import torch
     import paper_2410_08747_amd as mxr
