@@ -1,7 +1,7 @@
 /*
  * mxo.c -- plain, slow, scalar CPU oracle for the per-ray X-ray Monte Carlo
  * tracer.  TEST INFRASTRUCTURE ONLY: it exists so that tests, the smoke check
- * and the CPU-baseline leg of the benchmark can judge the HIP library.  The
+ * and the CPU-baseline leg of the benchmark can check the HIP library.  The
  * product path never links, loads or calls it, and it shares no code, header,
  * table or constant generator with the HIP library.
  *

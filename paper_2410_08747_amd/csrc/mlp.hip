@@ -73,29 +73,31 @@ __device__ __forceinline__ float silu_grad(float z) {
 
 // ---------------------------------------------------------------- GEMM --
 
-enum Epi { kEpiHidden = 0, kEpiOut, kEpiBackward, kEpiPartial };
+enum Epi { kEpiHidden = 0, kEpiOut, kEpiBackward };
 
 struct GemmArgs {
     const uint16_t *A;  // A(m, k) = A[m * sam + k * sak]
     const uint16_t *B;  // B(k, n) = B[k * sbk + n * sbn]
     int64_t sam, sak, sbk, sbn;
     int64_t M, N, K;
-    int64_t kchunk;        // contraction range per split (blockIdx.z)
+    int64_t kchunk;        // split-K: contraction range per split (blockIdx.z)
     const uint16_t *bias;  // kEpiHidden / kEpiOut: bias[n] (bfloat16)
     float *Z;              // kEpiHidden: pre-activation out; kEpiBackward: pre-activation in
     uint16_t *H;           // kEpiHidden: silu(Z) out; kEpiBackward: dZ (bfloat16) out
-    float *C;              // kEpiOut: output; kEpiBackward: dZ (float32) out; kEpiPartial: partial base
+    float *C;              // kEpiOut: output; kEpiBackward: dZ (float32) out; split-K: partial base
     int64_t ldc;           // row stride of C / Z / H
-    int64_t split_stride;  // kEpiPartial: floats between the partials of consecutive splits
+    int64_t split_stride;  // split-K: floats between the partials of consecutive splits
     float *colpart;        // strip kEpiBackward: per 16-row tile column sums of dZ (ldc columns)
 };
 
-// One wave per 16 x 16 tile of C, four waves per work-group along M.  The
-// 16x16x16 bf16 MFMA takes from lane l the row (A) or column (B) l mod 16
-// and the four consecutive k = 4 (l / 16) .. 4 (l / 16) + 3, and leaves in
-// lane l the four outputs of rows 4 (l / 16) .. +3 in column l mod 16.
-template <int EPI>
-__global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
+// Split-K products (weight gradients: in x out, contracted over rows): one
+// wave per 16 x 16 tile of C, four waves per work-group along M, the
+// contraction split over blockIdx.z into chunks of kchunk rows, each split
+// writing its own partial (reduced later in a fixed order).  The 16x16x16
+// bf16 MFMA takes from lane l the row (A) or column (B) l mod 16 and the four
+// consecutive k = 4 (l / 16) .. 4 (l / 16) + 3, and leaves in lane l the four
+// outputs of rows 4 (l / 16) .. +3 in column l mod 16.
+__global__ __launch_bounds__(kThreads) void k_gemm_splitk(GemmArgs g) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t tm = (int64_t)blockIdx.y * 4 + wave, tn = blockIdx.x;
     if (tm * 16 >= g.M) return;  // whole wave: no barrier in this kernel
@@ -123,21 +125,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int64_t mm = tm * 16 + 4 * q + j, nn = tn * 16 + r;
-        if (mm >= g.M || nn >= g.N) continue;
-        const float v = acc[j];
-        if constexpr (EPI == kEpiHidden) {
-            const float z = v + bf16_to_f32(g.bias[nn]);
-            g.Z[mm * g.ldc + nn] = z;
-            g.H[mm * g.ldc + nn] = f32_to_bf16(silu(z));
-        } else if constexpr (EPI == kEpiOut) {
-            g.C[mm * g.ldc + nn] = v + bf16_to_f32(g.bias[nn]);
-        } else if constexpr (EPI == kEpiBackward) {
-            const float dz = v * silu_grad(g.Z[mm * g.ldc + nn]);
-            g.C[mm * g.ldc + nn] = dz;
-            g.H[mm * g.ldc + nn] = f32_to_bf16(dz);
-        } else {
-            g.C[(int64_t)blockIdx.z * g.split_stride + mm * g.ldc + nn] = v;
-        }
+        if (mm < g.M && nn < g.N) g.C[(int64_t)blockIdx.z * g.split_stride + mm * g.ldc + nn] = acc[j];
     }
 }
 
@@ -281,16 +269,11 @@ __global__ void k_transpose_weights(const uint16_t *w, uint16_t *wt) {
     }
 }
 
-mxr_status gemm(int epi, const GemmArgs &g, int64_t splits, hipStream_t st) {
+mxr_status gemm_splitk(const GemmArgs &g, int64_t splits, hipStream_t st) {
     if (g.M == 0 || g.N == 0) return MXR_OK;
     const dim3 grid((unsigned)((g.N + 15) / 16), (unsigned)((g.M + 63) / 64), (unsigned)splits);
-    switch (epi) {
-        case kEpiHidden: hipLaunchKernelGGL(k_gemm<kEpiHidden>, grid, dim3(kThreads), 0, st, g); break;
-        case kEpiOut: hipLaunchKernelGGL(k_gemm<kEpiOut>, grid, dim3(kThreads), 0, st, g); break;
-        case kEpiBackward: hipLaunchKernelGGL(k_gemm<kEpiBackward>, grid, dim3(kThreads), 0, st, g); break;
-        default: hipLaunchKernelGGL(k_gemm<kEpiPartial>, grid, dim3(kThreads), 0, st, g); break;
-    }
-    return launch_check("MLP product");
+    hipLaunchKernelGGL(k_gemm_splitk, grid, dim3(kThreads), 0, st, g);
+    return launch_check("MLP split-K product");
 }
 
 // ------------------------------------------------------ small kernels --
@@ -660,7 +643,7 @@ mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const 
     g.B = h.dOh, g.sbk = kOut, g.sbn = 1;
     g.M = kHid, g.N = kOut, g.ldc = kOut;
     g.C = part + kW3;
-    if ((s = gemm(kEpiPartial, g, splits, st)) != MXR_OK) return s;
+    if ((s = gemm_splitk(g, splits, st)) != MXR_OK) return s;
     // dZ2 = (dO W3^T) * silu'(Z2); B(k = out, n = in) = W3[in][out]
     GemmArgs b{};
     b.M = (int64_t)n, b.N = kHid, b.K = kOut;
@@ -675,7 +658,7 @@ mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const 
     g.B = at<uint16_t>(ws, L, MXR_MLP_WS_DZ2H), g.sbk = kHid, g.sbn = 1;
     g.M = kHid, g.N = kHid, g.ldc = kHid;
     g.C = part + kW2;
-    if ((s = gemm(kEpiPartial, g, splits, st)) != MXR_OK) return s;
+    if ((s = gemm_splitk(g, splits, st)) != MXR_OK) return s;
     // dZ1 = (dZ2 W2^T) * silu'(Z1)
     b.K = kHid;
     b.A = at<uint16_t>(ws, L, MXR_MLP_WS_DZ2H), b.sam = kHid, b.sak = 1;
@@ -689,7 +672,7 @@ mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const 
     g.B = at<uint16_t>(ws, L, MXR_MLP_WS_DZ1H), g.sbk = kHid, g.sbn = 1;
     g.M = kIn, g.N = kHid, g.ldc = kHid;
     g.C = part + kW1;
-    if ((s = gemm(kEpiPartial, g, splits, st)) != MXR_OK) return s;
+    if ((s = gemm_splitk(g, splits, st)) != MXR_OK) return s;
     // bias gradients: per-split sums of the fused per-part column sums
     ColReduce cr;
     cr.parts[0] = cp3, cr.n_parts[0] = groups8, cr.cols[0] = kOut, cr.pps[0] = kSplitRows / 8, cr.off[0] = kB3;
