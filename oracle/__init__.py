@@ -9,7 +9,8 @@ arrays).  It shares no code with the HIP library under
 
 What is computed is described in ``mxo.c``: rays are drawn at the source,
 carried through the components in order and tallied at the monitors (paper,
-sections 2 and 3).  The voxel phantom uses Siddon's merge form.
+sections 2 and 3).  The voxel phantom uses Siddon's merge form, or the paper's
+fixed-step model when the phantom dict gives a step length.
 
 How each function is pinned (tests marked ``not gpu``):
 
@@ -26,6 +27,10 @@ How each function is pinned (tests marked ``not gpu``):
 * phantom -- homogeneous and layered volumes against closed-form optical
   depths, brute-force per-voxel slab intersection on small volumes, segment
   sum equal to the chord, adjacency of consecutive voxels.
+* fixed-step phantom model -- homogeneous volumes give mu times the chord;
+  a hand-computed three-voxel row; the step count ceil(chord / h); the
+  distance to the exact (brute-force) optical depth within h times the
+  attenuation spread per material change, shrinking linearly with h.
 * mirror -- the focal property of the ellipse and equal angles in and out.
 * monochromator -- the exit direction equals the entrance direction, the
   Darwin curve integrals, Bragg's law at the plateau centre.
@@ -131,6 +136,9 @@ def _load():
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
         ]
         lib.mxo_siddon_debug.restype = ctypes.c_double
+        lib.mxo_step_debug.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                       ctypes.c_void_p]
+        lib.mxo_step_debug.restype = ctypes.c_double
         lib.mxo_ppnd16.argtypes = [ctypes.c_double]
         lib.mxo_ppnd16.restype = ctypes.c_double
         lib.mxo_truncnorm.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
@@ -215,6 +223,9 @@ class Instrument:
             s.data0, s.data1 = _ptr(vol), _ptr(mu)
             s.n0, s.n1 = vol.size, mu.size
             p[0], p[1], p[2] = c["voxel"], c["table_emin"], c["table_emax"]
+            if c.get("step") is not None:
+                s.flags = 1
+                p[3] = c["step"]
         elif t == "mirror_elliptic":
             tab = self._keep_arr(c["reflectivity"], np.float64)
             p[0], p[1], p[2], p[3], p[4], p[5] = c["p"], c["q"], c["theta0"], c["length"], c["width"], c["theta_max"]
@@ -326,6 +337,19 @@ def siddon_segments(phantom: Dict, q, dl, E: float, max_seg: int = 100000):
                                _ptr(vox), _ptr(ln), max_seg, _ptr(ns))
     k = int(min(ns[0], max_seg))
     return tau, vox[:k].copy(), ln[:k].copy()
+
+
+def step_tau(phantom: Dict, q, dl, E: float):
+    """(tau, number of steps) of one ray through the phantom under the
+    fixed-step model (the dict's ``step`` is the step length in mm), given in
+    the phantom's local frame."""
+    lib = _load()
+    ins = Instrument({"components": [phantom]})
+    qa = np.asarray(q, dtype=np.float64)
+    da = np.asarray(dl, dtype=np.float64)
+    ns = np.zeros(1, np.int64)
+    tau = lib.mxo_step_debug(ctypes.addressof(ins.arr[0]), _ptr(qa), _ptr(da), float(E), _ptr(ns))
+    return tau, int(ns[0])
 
 
 def ppnd16(p: float) -> float:

@@ -738,13 +738,86 @@ double mxo_siddon_debug(const mxo_comp *c, const double q[3], const double dl[3]
     return mxo_siddon(&V, q, dl, E, seg_voxel, seg_len, max_seg, n_seg);
 }
 
+/* The paper's own model of the voxel sample (section 3.3, Phantom_sample3D):
+ * the ray advances in fixed increments h (one third of a voxel by default);
+ * after each increment the voxel holding the new position gives the material
+ * and the weight is attenuated over the increment.  Readings: the chord is
+ * the same as Siddon's (entry a_in, exit a_out along the unit direction);
+ * step j (j = 1, 2, ...) ends at alpha_j = a_in + j h and covers
+ * [alpha_(j-1), min(alpha_j, a_out)], so the last step is clipped at the
+ * exit; its position is taken unclipped, in voxel units,
+ * u_j = u_in + j (h d / v) with u_in = (entry point - corner) / v, and the
+ * voxel index is floor(u_j) clamped into the volume (so the clipped last
+ * step reads the voxel at the exit).  tau = sum mu(voxel of step j) * length
+ * of step j / 10.  *n_steps receives the number of steps. */
+double mxo_step_tau(const mxo_volume *V, const double q[3], const double dl[3], double E, double h,
+                    int64_t *n_steps)
+{
+    if (n_steps)
+        *n_steps = 0;
+    double a_in = 0.0, a_out = INFINITY;
+    for (int i = 0; i < 3; ++i) {
+        double lo_plane = V->corner[i];
+        double hi_plane = V->corner[i] + (double)V->n[i] * V->v;
+        if (dl[i] == 0.0) {
+            if (!(q[i] > lo_plane && q[i] < hi_plane))
+                return 0.0;
+        } else {
+            double inv = 1.0 / dl[i];
+            double a0 = (lo_plane - q[i]) * inv, a1 = (hi_plane - q[i]) * inv;
+            double lo = a0 < a1 ? a0 : a1, hi = a0 < a1 ? a1 : a0;
+            if (lo > a_in) a_in = lo;
+            if (hi < a_out) a_out = hi;
+        }
+    }
+    if (!(a_out > a_in))
+        return 0.0;
+    double u_in[3], du[3];
+    for (int i = 0; i < 3; ++i) {
+        u_in[i] = ((q[i] + a_in * dl[i]) - V->corner[i]) / V->v;
+        du[i] = (h * dl[i]) / V->v;
+    }
+    double ebin_scale = (double)V->n_ebin / (V->t_emax - V->t_emin);
+    int64_t e = floor_index((E - V->t_emin) * ebin_scale, V->n_ebin);
+    double tau = 0.0, a_prev = a_in;
+    int64_t j = 0;
+    for (;;) {
+        j++;
+        double a_j = a_in + (double)j * h;
+        double end = a_j < a_out ? a_j : a_out;
+        int64_t idx[3];
+        for (int i = 0; i < 3; ++i)
+            idx[i] = floor_index(u_in[i] + (double)j * du[i], V->n[i]);
+        int64_t mat = V->vol[idx[0] + V->n[0] * (idx[1] + V->n[1] * idx[2])];
+        if (mat >= V->n_mat)
+            mat = V->n_mat - 1;
+        tau = tau + V->mu[mat * V->n_ebin + e] * (end - a_prev) / 10.0;
+        a_prev = end;
+        if (!(a_j < a_out))
+            break;
+    }
+    if (n_steps)
+        *n_steps = j;
+    return tau;
+}
+
+double mxo_step_debug(const mxo_comp *c, const double q[3], const double dl[3], double E, int64_t *n_steps)
+{
+    mxo_volume V;
+    volume_from(c, &V);
+    return mxo_step_tau(&V, q, dl, E, c->par[3], n_steps);
+}
+
+/* flags bit 0: the fixed-step model with step length par[3] (mm) instead of
+ * Siddon's exact path */
 static void comp_phantom(const mxo_comp *c, mxo_ray *ray)
 {
     double q[3], dl[3];
     to_local(c, ray->r, ray->d, q, dl);
     mxo_volume V;
     volume_from(c, &V);
-    double tau = mxo_siddon(&V, q, dl, ray->E, NULL, NULL, 0, NULL);
+    double tau = (c->flags & 1u) ? mxo_step_tau(&V, q, dl, ray->E, c->par[3], NULL)
+                                 : mxo_siddon(&V, q, dl, ray->E, NULL, NULL, 0, NULL);
     ray->w = ray->w * exp(-tau);
 }
 
