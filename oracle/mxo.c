@@ -746,9 +746,10 @@ double mxo_siddon_debug(const mxo_comp *c, const double q[3], const double dl[3]
  * step j (j = 1, 2, ...) ends at alpha_j = a_in + j h and covers
  * [alpha_(j-1), min(alpha_j, a_out)], so the last step is clipped at the
  * exit; its position is taken unclipped, in voxel units,
- * u_j = u_in + j (h d / v) with u_in = (entry point - corner) / v, and the
- * voxel index is floor(u_j) clamped into the volume (so the clipped last
- * step reads the voxel at the exit).  tau = sum mu(voxel of step j) * length
+ * u_j = u_in + j (h d / v) with u_in = (entry point - corner) / v (evaluated
+ * as one correctly rounded fused multiply-add per axis), and the voxel index
+ * is floor(u_j) clamped into the volume (so the clipped last step reads the
+ * voxel at the exit).  tau = sum mu(voxel of step j) * length
  * of step j / 10.  *n_steps receives the number of steps. */
 double mxo_step_tau(const mxo_volume *V, const double q[3], const double dl[3], double E, double h,
                     int64_t *n_steps)
@@ -787,7 +788,7 @@ double mxo_step_tau(const mxo_volume *V, const double q[3], const double dl[3], 
         double end = a_j < a_out ? a_j : a_out;
         int64_t idx[3];
         for (int i = 0; i < 3; ++i)
-            idx[i] = floor_index(u_in[i] + (double)j * du[i], V->n[i]);
+            idx[i] = floor_index(fma((double)j, du[i], u_in[i]), V->n[i]);
         int64_t mat = V->vol[idx[0] + V->n[0] * (idx[1] + V->n[1] * idx[2])];
         if (mat >= V->n_mat)
             mat = V->n_mat - 1;
