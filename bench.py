@@ -49,11 +49,14 @@ def parse():
     p.add_argument("--train-hits", type=int, default=10**8, help="learned: detector hits collected for training")
     p.add_argument("--epochs", type=int, default=5, help="learned: training epochs")
     p.add_argument("--eval-rays", type=int, default=16 * 10**8, help="learned: rays per error evaluation (16 replicas)")
-    p.add_argument("--workload", choices=("projection", "batch", "learned", "train"), default="projection",
+    p.add_argument("--workload", choices=("projection", "batch", "learned", "train", "stepping"),
+                   default="projection",
                    help="projection: one 1e9-ray projection of the 256^3 phantom per step; batch: every angle "
                         "of phantoms of uneven size in one captured launch per step, beside one launch per job; "
                         "learned: time to 1%% per-bin error of the plain and the learned-proposal source; "
-                        "train: proposal-network training steps")
+                        "train: proposal-network training steps; stepping: the same projection with the "
+                        "fixed-step phantom model beside the exact path (speed and optical-depth error)")
+    p.add_argument("--step", type=float, default=1.0 / 3.0, help="stepping: step length (mm)")
     p.add_argument("--batch-rays", type=int, default=10**8, help="rays per job of the batch")
     p.add_argument("--batch-angles", type=int, default=360)
     p.add_argument("--batch-sizes", default="64,128,256,512", help="phantom edges (voxels) of the batch")
@@ -66,10 +69,11 @@ def parse():
 KERNEL_SOURCES = ["paper_2410_08747_amd/csrc/mxr.hip", "paper_2410_08747_amd/csrc/mxr_device.h", "include/mxr.h",
                   "paper_2410_08747_amd/build.py"]
 PROFILE = "profiles/k_trace_edct_projection_256.md"
+PROFILE_STEP = "profiles/k_trace_edct_step_256.md"
 
 
-def measured_traffic():
-    """HBM bytes per launch of the projection kernel from the committed
+def measured_traffic(profile=PROFILE):
+    """HBM bytes per launch of a tracing kernel from the committed
     FETCH_SIZE / WRITE_SIZE counters, scaled by the copy calibration; None
     when the kernel sources changed since the counters were taken."""
     import hashlib
@@ -78,7 +82,7 @@ def measured_traffic():
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     try:
-        with open(os.path.join(ROOT, PROFILE)) as fh:
+        with open(os.path.join(ROOT, profile)) as fh:
             line = [l for l in fh if l.startswith("counters:")][-1]
     except (OSError, IndexError):
         return None
@@ -107,10 +111,11 @@ def cpu_baseline(instr, n_sample: int, n_total: int):
                       f"({done} rays, {threads} host threads, {dt:.1f} s)"}
 
 
-def visits_per_ray(instr, samples: int = 200000, seed: int = 7) -> float:
+def visits_per_ray(instr, samples: int = 200000, seed: int = 7, step: float = None) -> float:
     """Mean number of voxels a source ray visits: directions uniform over
     the cone's solid angle, chord through the phantom's box, one visit per
-    voxel the chord enters (1 + the voxel planes it crosses)."""
+    voxel the chord enters (1 + the voxel planes it crosses); with ``step``,
+    the fixed-step model's steps per ray instead (ceil(chord / step))."""
     src, ph = instr["components"][0], instr["components"][1]
     rng = np.random.default_rng(seed)
     ct = 1.0 - rng.random(samples) * (1.0 - np.cos(src["half_angle"]))
@@ -130,6 +135,8 @@ def visits_per_ray(instr, samples: int = 200000, seed: int = 7) -> float:
     tmin = np.nanmax(np.minimum(t1, t2), axis=1)
     tmax = np.nanmin(np.maximum(t1, t2), axis=1)
     hit = tmax > np.maximum(tmin, 0.0)
+    if step is not None:
+        return float(np.sum(np.ceil((tmax[hit] - np.maximum(tmin[hit], 0.0)) / step)) / samples)
     a = o + np.maximum(tmin[hit], 0.0)[:, None] * dl[hit]
     b = o + tmax[hit][:, None] * dl[hit]
     n = np.array([nx, ny, nz])
@@ -426,6 +433,102 @@ def train_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def stepping_bench(args):
+    """The projection with the paper's fixed-step phantom model (step h)
+    beside the exact path: kernel time of each on the same 1e9 rays, the
+    per-ray optical-depth error on a sample of those rays (same seeds, so
+    the same source rays), and the image bias in units of the per-bin
+    statistical error."""
+    import torch
+    import paper_2410_08747_amd as mxr
+    import workloads
+    from paper_2410_08747_amd import metrics
+
+    vol = workloads.make_phantom(256, seed=1)
+    mu = workloads.make_mu_tables(1)
+    exact = workloads.edct_projection(vol, mu, angle=0.0, strata=STRATA)
+    stepped = workloads.edct_projection(vol, mu, angle=0.0, strata=STRATA, step=args.step)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    n = args.rays
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    shared = {}
+    res = {}
+    for name, ins in (("exact", exact), ("step", stepped)):
+        I = mxr.Instrument(ins, dev, shared=shared)
+        tallies = I.new_tallies()
+
+        def zero():
+            for v in tallies[0].values():
+                v.zero_()
+
+        for w in range(args.warmup):
+            zero()
+            I.run(n, seed=100 + w, n_total=n, tallies=tallies, stream=stream)
+        torch.cuda.synchronize()
+        ms = []
+        for k in range(args.steps):
+            zero()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            I.run(n, seed=1, n_total=n, tallies=tallies, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+            print(f"[stepping] {name} step {k}: {ms[-1]:.1f} ms", file=sys.stderr, flush=True)
+        ids = (np.arange(1 << 20, dtype=np.uint64) * np.uint64(n // (1 << 20))).astype(np.uint64)
+        rays = I.trace_rays(ids, seed=1, n_total=n)
+        res[name] = {"ms": float(np.mean(ms)), "sum_w": tallies[0]["sum_w"].cpu().numpy(),
+                     "sum_w2": tallies[0]["sum_w2"].cpu().numpy(), "w": rays["w"].cpu().numpy()}
+        del I, tallies
+    # source weights of the same rays: the instrument without its phantom
+    bare = {"components": [exact["components"][0], exact["components"][2]]}
+    w0 = mxr.Instrument(bare, dev).trace_rays(ids, seed=1, n_total=n)["w"].cpu().numpy()
+    e, s = res["exact"], res["step"]
+    tau_e = np.log(w0 / e["w"])
+    live = (w0 > 0) & (e["w"] > 0) & (s["w"] > 0) & (tau_e > 0)  # rays that cross material
+    tau_e = tau_e[live]
+    dtau = np.log(e["w"][live] / s["w"][live])  # tau_step - tau_exact
+    I_ref = e["sum_w"] / n
+    sig = metrics.signal_bins(I_ref, metrics.flat_field(exact))
+    rel = (s["sum_w"][sig] - e["sum_w"][sig]) / e["sum_w"][sig]
+    stat = np.sqrt(e["sum_w2"][sig]) / e["sum_w"][sig]
+    steps = visits_per_ray(stepped, step=args.step)
+    bytes_per_ray = steps + 0.302 * 24
+    achieved = bytes_per_ray * n / (s["ms"] * 1e-3) / 1e9
+    out = {
+        "metric": f"rays/s (ED-CT projection, fixed-step phantom model, step {args.step:.4g} mm)",
+        "value": n / (s["ms"] * 1e-3), "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": s["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "edct_projection_fixed_step", "n_rays": n, "step_mm": args.step,
+                   "phantom": "256^3 uint8, 1 mm voxels, seed 1", "detector": "256x64 px x 128 E-bins",
+                   "strata": STRATA, "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(PROFILE_STEP)},
+        "steps_per_ray": steps,
+        "exact": {"kernel_ms": e["ms"], "rays_per_s": n / (e["ms"] * 1e-3), "visits_per_ray": visits_per_ray(exact)},
+        "time_vs_exact": s["ms"] / e["ms"],
+        "tau_error": {"rays": int(live.sum()), "mean_tau_exact": float(np.mean(tau_e)),
+                      "mean": float(np.mean(dtau)), "rms": float(np.sqrt(np.mean(dtau ** 2))),
+                      "max_abs": float(np.max(np.abs(dtau))),
+                      "median_abs_rel": float(np.median(np.abs(dtau) / tau_e)),
+                      "frac_abs_gt_1e-3": float(np.mean(np.abs(dtau) > 1e-3)),
+                      "frac_abs_gt_1e-2": float(np.mean(np.abs(dtau) > 1e-2))},
+        "image_bias": {"signal_bins": int(sig.sum()), "median_abs_rel": float(np.median(np.abs(rel))),
+                       "mean_rel": float(np.mean(rel)), "median_stat_rel_err": float(np.median(stat)),
+                       "frac_bias_gt_stat": float(np.mean(np.abs(rel) > stat)),
+                       "frac_bias_gt_3stat": float(np.mean(np.abs(rel) > 3 * stat))},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -440,6 +543,9 @@ def main():
         return
     if args.workload == "train":
         train_bench(args)
+        return
+    if args.workload == "stepping":
+        stepping_bench(args)
         return
     import torch
     import paper_2410_08747_amd as mxr

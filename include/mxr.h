@@ -91,7 +91,16 @@ typedef enum {
  *   2 table E max.  dims: 0 nx, 1 ny, 2 nz, 3 n_mat (1..16), n_ebin =
  *   data_len[1] / n_mat (1..256).  A volume holding an id >= n_mat is
  *   rejected at create (the volume is scanned once on the device).  At most
- *   one phantom per instrument.
+ *   one phantom per instrument.  flags bit 0: the paper's fixed-step model
+ *   instead (section 3.3: the ray advances by a fixed increment, the voxel
+ *   holding the new position gives the material, the weight is attenuated
+ *   over the increment) with par 3 = step length h (mm, > 0; the paper's
+ *   default is a third of the voxel edge): step j covers [a_in + (j-1) h,
+ *   min(a_in + j h, a_out)] of the chord and reads the voxel holding
+ *   u_in + j h d / v (voxel units, j h d / v + u_in as one fused
+ *   multiply-add per axis, clamped into the volume).  Other flag bits are
+ *   rejected; MXR_E_UNSUPPORTED when the longest chord needs more than 2^26
+ *   steps or ny * nz >= 2^24.
  * MXR_MIRROR_ELLIPTIC -- elliptic-cylinder mirror; local origin at the pole,
  *   z along the incoming axis, y to the reflected side; foci at (0,0,-p)
  *   and q (0, sin 2t0, cos 2t0).  Specular reflection, weight times the

@@ -381,6 +381,9 @@ def _params(c: Dict, s: mxr_component_desc, upload) -> None:
         s.data[1], s.data_len[1] = upload(mu, np.float64)
         s.dims[0], s.dims[1], s.dims[2], s.dims[3] = nx, ny, nz, mu.shape[0]
         p[0], p[1], p[2] = c["voxel"], c["table_emin"], c["table_emax"]
+        if c.get("step") is not None:
+            s.flags = 1
+            p[3] = c["step"]
     elif t == "mirror_elliptic":
         s.data[0], s.data_len[0] = upload(c["reflectivity"], np.float64)
         p[0], p[1], p[2], p[3], p[4], p[5] = c["p"], c["q"], c["theta0"], c["length"], c["width"], c["theta_max"]

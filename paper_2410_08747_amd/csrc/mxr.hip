@@ -38,6 +38,8 @@ constexpr uint32_t kMaxBranches = 4;  // graph branches of a batch in the launch
 // drawing from a proposal mixture, and a monitor that also records its hits
 constexpr int kSrcConeProposal = 100;
 constexpr int kDetectorCollect = 101;
+// the phantom component (same descriptor) under the fixed-step model
+constexpr int kPhantomStep = 102;
 
 constexpr bool is_detector(int T) { return T == MXR_DETECTOR || T == kDetectorCollect; }
 
@@ -115,7 +117,7 @@ __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream 
         int64_t bin = -1;
         if constexpr (T == MXR_SLIT) ok = comp_slit(c, ray);
         if constexpr (T == MXR_BOX) comp_box(c, ray);
-        if constexpr (T == MXR_PHANTOM) {
+        if constexpr (T == MXR_PHANTOM || T == kPhantomStep) {
             double q[3], dl[3];
             to_local(c, ray, q, dl);
             PhantomGeo g;
@@ -130,7 +132,11 @@ __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream 
             g.nvox = (uint32_t)c.n0;
             double f = floor((ray.E - c.par[1]) * c.aux[3]);
             int e = (int)fmin(fmax(f, 0.0), (double)(n_ebin - 1));
-            double tau = siddon_tau<EXACT>(g, q, dl, mu_lds + e * n_mat);
+            double tau;
+            if constexpr (T == kPhantomStep)
+                tau = step_tau(g, q, dl, c.par[3], (int)c.aux[5], mu_lds + e * n_mat);
+            else
+                tau = siddon_tau<EXACT>(g, q, dl, mu_lds + e * n_mat);
             ray.w = ray.w * exp(-tau);
         }
         if constexpr (T == MXR_MIRROR_ELLIPTIC) ok = comp_mirror(c, ray);
@@ -177,7 +183,9 @@ __device__ __forceinline__ bool apply_dynamic(const DevComp &c, int k, Ray &ray,
         MXR_CASE(MXR_SRC_GAUSSIAN)
         MXR_CASE(MXR_SLIT)
         MXR_CASE(MXR_BOX)
-        MXR_CASE(MXR_PHANTOM)
+        case MXR_PHANTOM:
+            if (c.flags & 1u) return apply<kPhantomStep, LEDGER, TRACE, EXACT>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
+            return apply<MXR_PHANTOM, LEDGER, TRACE, EXACT>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
         MXR_CASE(MXR_MIRROR_ELLIPTIC)
         MXR_CASE(MXR_DCM)
         MXR_CASE(MXR_POWDER)
@@ -214,6 +222,10 @@ struct WavesHint<Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, kDetectorCollect>> {
 };
 template <>
 struct WavesHint<Chain<kSrcConeProposal, MXR_PHANTOM, MXR_DETECTOR>> {
+    static constexpr int value = 8;
+};
+template <>
+struct WavesHint<Chain<MXR_SRC_CONE_BEAM, kPhantomStep, MXR_DETECTOR>> {
     static constexpr int value = 8;
 };
 // The batch kernels read their per-job arguments from memory rather than the
@@ -470,8 +482,9 @@ using ChainEdct = Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR>;
 using ChainBeamline = Chain<MXR_SRC_GAUSSIAN, MXR_MIRROR_ELLIPTIC, MXR_DCM, MXR_POWDER, MXR_DETECTOR>;
 using ChainEdctProposal = Chain<kSrcConeProposal, MXR_PHANTOM, MXR_DETECTOR>;
 using ChainEdctCollect = Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, kDetectorCollect>;
+using ChainEdctStep = Chain<MXR_SRC_CONE_BEAM, kPhantomStep, MXR_DETECTOR>;
 
-enum Recipe { kRecipeGeneric = 0, kRecipeBasic, kRecipeEdct, kRecipeBeamline, kNumRecipes };
+enum Recipe { kRecipeGeneric = 0, kRecipeBasic, kRecipeEdct, kRecipeBeamline, kRecipeEdctStep, kNumRecipes };
 
 typedef void (*KernelFn)(const DevInstr *, RunArgs);
 
@@ -504,6 +517,7 @@ KernelFn pick_kernel(int recipe, bool ledger, bool trace, bool exact, int mode) 
         case kRecipeEdct:
             return exact ? KernelSet<ChainEdct, true>::get(ledger, trace) : KernelSet<ChainEdct, false>::get(ledger, trace);
         case kRecipeBeamline: return KernelSet<ChainBeamline, true>::get(ledger, trace);
+        case kRecipeEdctStep: return KernelSet<ChainEdctStep, true>::get(ledger, trace);
         default:
             return exact ? KernelSet<ChainGeneric, true>::get(ledger, trace)
                          : KernelSet<ChainGeneric, false>::get(ledger, trace);
@@ -540,7 +554,7 @@ int match_recipe(const DevInstr &d) {
         return true;
     };
     if (is({MXR_SRC_RECT_CONE, MXR_SLIT, MXR_BOX, MXR_DETECTOR})) return kRecipeBasic;
-    if (is({MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR})) return kRecipeEdct;
+    if (is({MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR})) return (d.c[1].flags & 1u) ? kRecipeEdctStep : kRecipeEdct;
     if (is({MXR_SRC_GAUSSIAN, MXR_MIRROR_ELLIPTIC, MXR_DCM, MXR_POWDER, MXR_DETECTOR})) return kRecipeBeamline;
     return kRecipeGeneric;
 }
@@ -665,6 +679,19 @@ static mxr_status derive(const mxr_component_desc &s, DevComp &c, int k, uint32_
             if (s.data_len[1] % s.dims[3] != 0 || s.data_len[1] / s.dims[3] < 1 || s.data_len[1] / s.dims[3] > 256)
                 return fail(MXR_E_UNSUPPORTED, "component %d: 1..256 energy bins per material", k);
             if (!(p[0] > 0 && p[2] > p[1])) return fail(MXR_E_INVALID, "component %d: bad voxel size or table range", k);
+            if (s.flags & ~1u) return fail(MXR_E_INVALID, "component %d: unknown phantom flags", k);
+            if (s.flags & 1u) {
+                // fixed-step model: bound the steps of the longest chord
+                if (!(p[3] > 0)) return fail(MXR_E_INVALID, "component %d: step length must be positive", k);
+                const double diag = p[0] * std::sqrt((double)s.dims[0] * s.dims[0] + (double)s.dims[1] * s.dims[1] +
+                                                     (double)s.dims[2] * s.dims[2]);
+                const double jmax = std::ceil(diag / p[3]) + 2.0;
+                if (!(jmax <= (double)(1 << 26)))
+                    return fail(MXR_E_UNSUPPORTED, "component %d: more than 2^26 steps per chord", k);
+                if ((uint64_t)s.dims[1] * s.dims[2] >= (1ull << 24))
+                    return fail(MXR_E_UNSUPPORTED, "component %d: fixed-step model needs ny * nz < 2^24", k);
+                c.aux[5] = jmax;
+            }
             n_mat = s.dims[3];
             n_ebin = (uint32_t)(s.data_len[1] / s.dims[3]);
             for (int i = 0; i < 3; ++i) c.aux[i] = -0.5 * ((double)s.dims[i] * p[0]);
@@ -1298,6 +1325,7 @@ mxr_status mxr_batch_create(const mxr_batch_job *jobs, uint32_t n_jobs, const mx
         if (ins->host.ncomp != i0->host.ncomp) return fail(MXR_E_INVALID, "job %u: component chain differs from job 0", k);
         for (uint32_t c = 0; c < ins->host.ncomp; ++c)
             if (ins->host.c[c].type != i0->host.c[c].type) return fail(MXR_E_INVALID, "job %u: component chain differs from job 0", k);
+        if (ins->recipe != i0->recipe) return fail(MXR_E_INVALID, "job %u: phantom model differs from job 0", k);
         if (j.n_rays < 1) return fail(MXR_E_INVALID, "job %u: n_rays must be positive", k);
         if (j.job > 0xFFFFFFu) return fail(MXR_E_INVALID, "job %u: RNG job field must be < 2^24", k);
         BatchJob &bj = hj[k];

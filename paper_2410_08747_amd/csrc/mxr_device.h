@@ -642,6 +642,91 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
     return siddon_walk<EXACT, kWalkRound>(g, S, D, A, B, off, a_in, a_out, mu_row);
 }
 
+// ---------------------------------------------------- fixed-step model ----
+// The paper's own way through the voxel sample (section 3.3): fixed steps of
+// length h, each reading the voxel that holds its end position and
+// attenuating over its length.  The chord is the exact walk's; step j covers
+// [a_in + (j-1) h, min(a_in + j h, a_out)] (the last step is clipped at the
+// exit) and reads the voxel at u_in + j (h d / v) in voxel units (one fused
+// multiply-add per axis), taken unclipped and clamped into the volume.  Both numbers come from j directly,
+// with no running sum, so the steps are independent: kStepRound voxel loads
+// are issued per round.  The optical depth is summed per material run as in
+// the exact walk.  jmax (volume diagonal / h + 2, from the host) bounds every
+// loop; a voxel index is clamped per axis, so every load is in range.
+constexpr int kStepRound = 4;
+
+__device__ __forceinline__ double step_tau(const PhantomGeo &g, const double q[3], const double dl[3], double h,
+                                           int jmax, const double *__restrict__ mu_row) {
+    double a_in = 0.0, a_out = kInf;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double lo_p = g.corner[i];
+        const double hi_p = g.corner[i] + (double)g.n[i] * g.v;
+        if (dl[i] == 0.0) {
+            if (!(q[i] > lo_p && q[i] < hi_p)) return 0.0;
+        } else {
+            const double inv = 1.0 / dl[i];
+            const double a0 = (lo_p - q[i]) * inv, a1 = (hi_p - q[i]) * inv;
+            const double lo = a0 < a1 ? a0 : a1, hi = a0 < a1 ? a1 : a0;
+            if (lo > a_in) a_in = lo;
+            if (hi < a_out) a_out = hi;
+        }
+    }
+    if (!(a_out > a_in)) return 0.0;
+    double u0[3], du[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        u0[i] = ((q[i] + a_in * dl[i]) - g.corner[i]) / g.v;
+        du[i] = (h * dl[i]) / g.v;
+    }
+    // this lane's step count: the first j with a_in + j h >= a_out
+    // (a_in + j h is non-decreasing in j, so the fix-ups end at that j)
+    int J = (int)fmin(fmax(ceil((a_out - a_in) / h), 1.0), (double)jmax);
+    while (J > 1 && !(a_in + (double)(J - 1) * h < a_out)) --J;
+    while (J < jmax && a_in + (double)J * h < a_out) ++J;
+
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)g.vol, (short)0, (int)g.nvox, 0x00020000);
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    // voxel of step j: truncation then clamping at 0 equals floor then
+    // clamping, for every value in int range.  The host admits the model
+    // only for ny nz < 2^24, so the offset takes two 24-bit multiply-adds
+    // (full rate) instead of 32-bit multiplies (quarter rate).
+    auto voxel_of = [&](int j) -> uint32_t {
+        const double dj = (double)j;
+        int ix = (int)fma(dj, du[0], u0[0]);
+        int iy = (int)fma(dj, du[1], u0[1]);
+        int iz = (int)fma(dj, du[2], u0[2]);
+        ix = min(max(ix, 0), nx - 1);
+        iy = min(max(iy, 0), ny - 1);
+        iz = min(max(iz, 0), nz - 1);
+        return __umul24((uint32_t)nx, __umul24((uint32_t)ny, (uint32_t)iz) + (uint32_t)iy) + (uint32_t)ix;
+    };
+    uint32_t run_m = load_voxel(rs, voxel_of(1));
+    double a_start = a_in, tau = 0.0;
+    const int max_rounds = (jmax + kStepRound - 1) / kStepRound + 1;
+    int j0 = 2;
+    for (int round = 0; round < max_rounds; ++round, j0 += kStepRound) {
+        if (__builtin_amdgcn_ballot_w64(j0 <= J) == 0) break;
+        uint32_t m[kStepRound];
+#pragma unroll
+        for (int k = 0; k < kStepRound; ++k) m[k] = load_voxel(rs, voxel_of(j0 + k));
+#pragma unroll
+        for (int k = 0; k < kStepRound; ++k) {
+            // a step past this lane's last one starts at or beyond a_out:
+            // clamped there, it closes the open run exactly as the final
+            // term would and adds zero-length runs after it, so no per-step
+            // j <= J test is needed
+            if (m[k] != run_m) {
+                const double a = fmin(a_in + (double)(j0 + k - 1) * h, a_out);
+                tau = fma(mu_row[run_m], a - a_start, tau);
+                a_start = a;
+                run_m = m[k];
+            }
+        }
+    }
+    return fma(mu_row[run_m], a_out - a_start, tau);
+}
+
 // ------------------------------------------------------------- mirror ----
 __device__ __forceinline__ bool comp_mirror(const DevComp &c, Ray &ray) {
     // aux: 0 Cy, 1 Cz, 2 uy, 3 uz, 4 vy, 5 vz, 6 1/a^2, 7 1/b^2,

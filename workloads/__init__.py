@@ -192,13 +192,16 @@ def edct_half_angle() -> float:
 
 
 def edct_projection(volume: np.ndarray, mu_table: np.ndarray, angle: float = 0.0,
-                    strata: int = 1024, nx: int = EDCT_NX, ny: int = EDCT_NY, ne: int = EDCT_NE) -> Dict:
+                    strata: int = 1024, nx: int = EDCT_NX, ny: int = EDCT_NY, ne: int = EDCT_NE,
+                    step: float = None) -> Dict:
     """Energy-dispersive CT projection: cone-beam point source (Kramers
     continuum (150 - E)/E on 20-150 keV plus lines at 59.3 and 67.2 keV,
     sigma 0.3 keV, 10 % of the photons each), voxel phantom of 1 mm voxels
     centred 0.8 m from the source and turned by ``angle`` about +y, ideal
     energy-resolving detector of nx x ny pixels of 1.6 mm and ne energy bins
-    over [20, 150) keV at 1.2 m.  The cone circumscribes the detector."""
+    over [20, 150) keV at 1.2 m.  The cone circumscribes the detector.
+    ``step`` (mm): cross the phantom with the fixed-step model instead of the
+    exact path (the paper's default step is a third of the voxel)."""
     hx = 0.5 * nx * EDCT_PITCH
     hy = 0.5 * ny * EDCT_PITCH
     return {"name": "edct_projection", "components": [
@@ -206,7 +209,7 @@ def edct_projection(volume: np.ndarray, mu_table: np.ndarray, angle: float = 0.0
            emin=20.0, emax=150.0, e0=150.0, f_cont=0.8, e_line1=59.3, f_line1=0.1,
            e_line2=67.2, f_line2=0.1, line_sigma=0.3, strata=strata),
         _c("phantom", pos=(0, 0, EDCT_SOD), rot=rot_y(angle), voxel=1.0, volume=volume,
-           mu_table=mu_table, table_emin=20.0, table_emax=150.0),
+           mu_table=mu_table, table_emin=20.0, table_emax=150.0, step=step),
         _c("detector", pos=(0, 0, EDCT_SDD), xmin=-hx, xmax=hx, ymin=-hy, ymax=hy,
            emin=20.0, emax=150.0, nx=nx, ny=ny, ne=ne),
     ]}
