@@ -36,6 +36,11 @@ How each function is pinned (tests marked ``not gpu``):
   Darwin curve integrals, Bragg's law at the plateau centre.
 * powder -- the scattering angle equals 2 asin(lambda / 2d) and the azimuth
   is uniform.
+* compound refractive lens -- Snell's law at every surface (unit direction,
+  tangential component scaled by n1 / n2, normal on the paraboloid), the
+  paraxial focal length R / (2 N delta) and the image distance of the thin
+  lens, transmission exp(-mu N (w + rho^2 / R)) for paraxial rays, the
+  aperture and the refraction-free limit delta = 0.
 * ledger -- weight emitted equals absorbed + attenuated + exiting weight.
 """
 from __future__ import annotations
@@ -63,6 +68,7 @@ TYPE_CODES = {
     "dcm": 7,
     "powder": 8,
     "detector": 9,
+    "lens_crl": 10,
 }
 STATUS_EXITED = 1
 STATUS_ABSORBED = 2
@@ -139,6 +145,9 @@ def _load():
         lib.mxo_step_debug.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                        ctypes.c_void_p]
         lib.mxo_step_debug.restype = ctypes.c_double
+        lib.mxo_lens_debug.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.mxo_lens_debug.restype = ctypes.c_int
         lib.mxo_ppnd16.argtypes = [ctypes.c_double]
         lib.mxo_ppnd16.restype = ctypes.c_double
         lib.mxo_truncnorm.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
@@ -241,6 +250,11 @@ class Instrument:
             s.dims[0], s.dims[1], s.dims[2] = c["nx"], c["ny"], c["ne"]
             s.flags = 1 if c.get("wavelength", False) else 0
             self.detectors.append(c)
+        elif t == "lens_crl":
+            vals = [c["R"], c["n_lenses"], c["web"], c["pitch"], c["aperture"], c["delta_ref"], c["e_ref"],
+                    c["mu_a"], c["mu_b"]]
+            for i, v in enumerate(vals):
+                p[i] = v
         else:
             raise ValueError(f"unknown component type {t}")
 
@@ -350,6 +364,18 @@ def step_tau(phantom: Dict, q, dl, E: float):
     ns = np.zeros(1, np.int64)
     tau = lib.mxo_step_debug(ctypes.addressof(ins.arr[0]), _ptr(qa), _ptr(da), float(E), _ptr(ns))
     return tau, int(ns[0])
+
+
+def lens(lens_dict: Dict, q, dl, E: float):
+    """One ray through a compound refractive lens, given in the lens frame:
+    (ok, position, direction, weight factor) after the stack."""
+    lib = _load()
+    ins = Instrument({"components": [lens_dict]})
+    qa = np.asarray(q, dtype=np.float64)
+    da = np.asarray(dl, dtype=np.float64)
+    qo, do, w = np.zeros(3), np.zeros(3), np.zeros(1)
+    ok = lib.mxo_lens_debug(ctypes.addressof(ins.arr[0]), _ptr(qa), _ptr(da), float(E), _ptr(qo), _ptr(do), _ptr(w))
+    return bool(ok), qo, do, float(w[0])
 
 
 def ppnd16(p: float) -> float:

@@ -48,7 +48,8 @@ enum {
     MXO_MIRROR_ELLIPTIC = 6,
     MXO_DCM = 7,
     MXO_POWDER = 8,
-    MXO_DETECTOR = 9
+    MXO_DETECTOR = 9,
+    MXO_LENS_CRL = 10
 };
 
 enum { MXO_ALIVE = 0, MXO_EXITED = 1, MXO_ABSORBED = 2 };
@@ -822,6 +823,112 @@ static void comp_phantom(const mxo_comp *c, mxo_ray *ray)
     ray->w = ray->w * exp(-tau);
 }
 
+/* Compound refractive lens: a stack of N identical bi-concave parabolic
+ * lenses (section 3.2, the focusing instrument: sixteen double-sided
+ * parabolic beryllium lenses of 200 um apex radius).  Local frame: z along
+ * the stack axis, origin at the stack centre; lens k (k = 0 .. N-1) is
+ * centred at c_k = (k - (N-1)/2) p.  Its material lies between the front
+ * surface z = c_k - w/2 - rho^2 / 2R and the back surface
+ * z = c_k + w/2 + rho^2 / 2R (rho^2 = x^2 + y^2; on-axis thickness w, the
+ * thickness at rho is w + rho^2 / R), inside the aperture radius r_a; the
+ * frame beyond r_a is opaque.  Refractive index n = 1 - delta with
+ * delta(E) = delta_ref (E_ref / E)^2; attenuation mu(E) = a / E^3 + b (1/cm).
+ *
+ * At every surface the ray meets the paraboloid at the root of the
+ * intersection quadratic nearest to -C/B (the stable form C / q'), is
+ * absorbed if it cannot reach it moving forward or meets it outside the
+ * aperture, and is refracted by the vector form of Snell's law,
+ * d' = eta d + (sqrt(k) - eta cos_i) m (m the unit normal pointing into the
+ * second medium, cos_i = d . m, eta = n_1 / n_2, k = 1 - eta^2 (1 - cos_i^2);
+ * k < 0, total reflection, absorbs).  sqrt(k) - eta cos_i is evaluated as
+ * (1 - eta^2) / (sqrt(k) + eta cos_i), the same number without cancellation,
+ * with 1 - eta^2 written out for each side: -delta (2 - delta) / (1 - delta)^2
+ * entering the lens, delta (2 - delta) leaving it.  The weight is multiplied
+ * once by exp(-mu L / 10), L the summed path length inside the material (mm). */
+static int lens_surface(double q[3], double dl[3], double z0, double s, double R, double ra2, double eta,
+                        double one_m_eta2, double *t_out)
+{
+    double A = -s * (dl[0] * dl[0] + dl[1] * dl[1]) / (2.0 * R);
+    double B = dl[2] - s * (q[0] * dl[0] + q[1] * dl[1]) / R;
+    double C = (q[2] - z0) - s * (q[0] * q[0] + q[1] * q[1]) / (2.0 * R);
+    double disc = B * B - 4.0 * A * C;
+    if (!(disc >= 0.0))
+        return 0;
+    double qq = -0.5 * (B + copysign(sqrt(disc), B));
+    if (qq == 0.0)
+        return 0;
+    double t = C / qq;
+    if (!(t >= 0.0))
+        return 0;
+    for (int i = 0; i < 3; ++i)
+        q[i] = q[i] + t * dl[i];
+    if (q[0] * q[0] + q[1] * q[1] > ra2)
+        return 0;
+    /* gradient of z - z0 - s rho^2 / 2R: (-s x / R, -s y / R, 1), downstream */
+    double g[3] = {-s * q[0] / R, -s * q[1] / R, 1.0};
+    double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    double m[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
+    double cos_i = dl[0] * m[0] + dl[1] * m[1] + dl[2] * m[2];
+    if (!(cos_i > 0.0))
+        return 0;
+    double k = 1.0 - eta * eta * (1.0 - cos_i * cos_i);
+    if (!(k >= 0.0))
+        return 0;
+    double gcoef = one_m_eta2 / (sqrt(k) + eta * cos_i);
+    for (int i = 0; i < 3; ++i)
+        dl[i] = eta * dl[i] + gcoef * m[i];
+    *t_out = t;
+    return 1;
+}
+
+static int comp_lens(const mxo_comp *c, mxo_ray *ray)
+{
+    double q[3], dl[3];
+    to_local(c, ray->r, ray->d, q, dl);
+    const double R = c->par[0], w = c->par[2], pitch = c->par[3], ra2 = c->par[4] * c->par[4];
+    const int64_t N = (int64_t)c->par[1];
+    const double E = ray->E;
+    const double delta = c->par[5] * ((c->par[6] / E) * (c->par[6] / E));
+    const double mu = c->par[7] / (E * E * E) + c->par[8];
+    const double eta_in = 1.0 / (1.0 - delta), eta_out = 1.0 - delta;
+    const double ome_in = -delta * (2.0 - delta) / ((1.0 - delta) * (1.0 - delta));
+    const double ome_out = delta * (2.0 - delta);
+    double L = 0.0, t;
+    for (int64_t k = 0; k < N; ++k) {
+        double ck = ((double)k - 0.5 * (double)(N - 1)) * pitch;
+        if (!lens_surface(q, dl, ck - 0.5 * w, -1.0, R, ra2, eta_in, ome_in, &t))
+            return 0;
+        if (!lens_surface(q, dl, ck + 0.5 * w, 1.0, R, ra2, eta_out, ome_out, &t))
+            return 0;
+        L = L + t;
+    }
+    ray->w = ray->w * exp(-(mu * L) / 10.0);
+    to_lab(c, q, dl, ray->r, ray->d);
+    return 1;
+}
+
+/* exported debug entry: one ray given in the lens frame (the component's
+ * pos and rot are ignored); returns 0 if absorbed, else the ray after the
+ * stack in q, dl and the weight factor in *w */
+int mxo_lens_debug(const mxo_comp *c, const double q[3], const double dl[3], double E, double q_out[3],
+                   double dl_out[3], double *w)
+{
+    mxo_comp cc = *c;
+    memset(cc.pos, 0, sizeof cc.pos);
+    memset(cc.rot, 0, sizeof cc.rot);
+    cc.rot[0] = cc.rot[4] = cc.rot[8] = 1.0;
+    mxo_ray ray;
+    memcpy(ray.r, q, sizeof ray.r);
+    memcpy(ray.d, dl, sizeof ray.d);
+    ray.E = E;
+    ray.w = 1.0;
+    int ok = comp_lens(&cc, &ray);
+    memcpy(q_out, ray.r, sizeof ray.r);
+    memcpy(dl_out, ray.d, sizeof ray.d);
+    *w = ray.w;
+    return ok;
+}
+
 /* Rectangular (or circular) aperture in the local plane z = 0; edges pass. */
 static int comp_slit(const mxo_comp *c, mxo_ray *ray)
 {
@@ -1116,6 +1223,7 @@ static void trace_from(const mxo_instr *I, uint64_t ray_id, int k0, mxo_ray *ray
         case MXO_DCM: ok = comp_dcm(c, ray); break;
         case MXO_POWDER: ok = comp_powder(c, &s, draw, ray); break;
         case MXO_DETECTOR: ok = comp_detector(c, ray, &bin); break;
+        case MXO_LENS_CRL: ok = comp_lens(c, ray); break;
         default: ok = 0; break;
         }
         draw += draws_of(c->type);

@@ -11,7 +11,8 @@ with ``rot`` the lab-to-local rotation (local = rot @ (lab - pos)), lengths
 in mm, energies in keV, angles in rad, attenuation in 1/cm.
 
 The paper's own workloads (section 3: a basic source + monitor instrument, a
-focusing beamline, an energy-dispersive CT scanner with a voxel phantom)
+focusing instrument with a compound refractive lens, an energy-dispersive CT
+scanner with a voxel phantom)
 need data that is not available here (tungsten spectrum, water, iron and
 lead attenuation, the test piece geometry); the generators below stand in
 for them with the shapes the paper gives (1 mm voxels, 128 energy bins,
@@ -246,6 +247,58 @@ def beamline(d_spacings: np.ndarray = None, reflectivity: np.ndarray = None) -> 
         _c("powder", pos=focus, rot=R, w=1.0, h=1.0, d_spacings=d_spacings),
         _c("detector", pos=det_pos, rot=R, xmin=-51.2, xmax=51.2, ymin=-51.2, ymax=51.2,
            emin=0.0, emax=1000.0, nx=1024, ny=1024, ne=1),
+    ]}
+
+
+# focusing instrument with a compound refractive lens (beryllium stand-in)
+BE_DENSITY = 1.848           # g/cm^3
+BE_Z, BE_A = 4.0, 9.0121831  # electrons per atom, g/mol
+CLASSICAL_ELECTRON_RADIUS_M = 2.8179403262e-15
+AVOGADRO = 6.02214076e23
+# attenuation of the stand-in, mu(E) = a / E^3 + b (1/cm): a photoabsorption
+# term and a constant scattering term, Be-like in size (~0.42 1/cm at 20 keV,
+# ~0.33 1/cm at 30 keV)
+BE_MU_A, BE_MU_B = 950.0, 0.30
+
+
+def be_delta(E: float) -> float:
+    """Refractive decrement of beryllium at E keV from its electron density:
+    delta = r_e lambda^2 n_e / (2 pi) (far from absorption edges)."""
+    n_e = BE_DENSITY * AVOGADRO * BE_Z / BE_A * 1e6  # electrons per m^3
+    lam = HC_KEV_ANGSTROM / E * 1e-10                 # m
+    return CLASSICAL_ELECTRON_RADIUS_M * lam * lam * n_e / (2.0 * math.pi)
+
+
+CRL_E0 = 23.32           # keV
+CRL_LENS_DIST = 31500.0  # source to the lens stack centre (mm)
+CRL_SLIT_DIST = 14000.0  # lens centre to the focusing slit (mm)
+
+
+def crl_focusing(n_lenses: int = 16, aperture: float = 0.75) -> Dict:
+    """Focusing instrument of the paper's section 3.2: a Gaussian
+    undulator-like source (sigma 48.2 x 9.5 um, divergence 100 x 4.3 urad,
+    23.32 keV +-1 keV flat), cropped to a 1 x 1 mm window just before a stack
+    of n_lenses bi-concave parabolic beryllium lenses (apex radius 200 um,
+    on-axis thickness 50 um -- the paper's lens-to-lens distance --, aperture
+    radius ``aperture`` mm, lenses touching at the aperture rim) centred 31.5 m
+    from the source; a circular slit of 0.1 mm diameter 14 m after the lens
+    centre; a position-sensitive monitor (120 x 120 px of 1 um) and an energy
+    monitor (130 bins of 20 eV) just behind it."""
+    R, web = 0.2, 0.05
+    pitch = web + aperture * aperture / R
+    half = 0.5 * n_lenses * pitch
+    zl, zs = CRL_LENS_DIST, CRL_LENS_DIST + CRL_SLIT_DIST
+    return {"name": "crl_focusing", "components": [
+        _c("source_gaussian", sigma_x=0.0482, sigma_y=0.0095, sigma_xp=100e-6, sigma_yp=4.3e-6,
+           e0=CRL_E0, rel_halfwidth=1.0 / CRL_E0),
+        _c("slit", pos=(0, 0, zl - half - 1.0), w=1.0, h=1.0),
+        _c("lens_crl", pos=(0, 0, zl), R=R, n_lenses=n_lenses, web=web, pitch=pitch, aperture=aperture,
+           delta_ref=be_delta(CRL_E0), e_ref=CRL_E0, mu_a=BE_MU_A, mu_b=BE_MU_B),
+        _c("slit", pos=(0, 0, zs), circular=True, radius=0.05),
+        _c("detector", pos=(0, 0, zs + 1.0), xmin=-0.06, xmax=0.06, ymin=-0.06, ymax=0.06,
+           emin=20.0, emax=27.0, nx=120, ny=120, ne=1),
+        _c("detector", pos=(0, 0, zs + 2.0), xmin=-0.06, xmax=0.06, ymin=-0.06, ymax=0.06,
+           emin=22.0, emax=24.6, nx=1, ny=1, ne=130),
     ]}
 
 
