@@ -49,13 +49,14 @@ def parse():
     p.add_argument("--train-hits", type=int, default=10**8, help="learned: detector hits collected for training")
     p.add_argument("--epochs", type=int, default=5, help="learned: training epochs")
     p.add_argument("--eval-rays", type=int, default=16 * 10**8, help="learned: rays per error evaluation (16 replicas)")
-    p.add_argument("--workload", choices=("projection", "batch", "learned", "train", "stepping"),
+    p.add_argument("--workload", choices=("projection", "batch", "learned", "train", "stepping", "crl"),
                    default="projection",
                    help="projection: one 1e9-ray projection of the 256^3 phantom per step; batch: every angle "
                         "of phantoms of uneven size in one captured launch per step, beside one launch per job; "
                         "learned: time to 1%% per-bin error of the plain and the learned-proposal source; "
                         "train: proposal-network training steps; stepping: the same projection with the "
-                        "fixed-step phantom model beside the exact path (speed and optical-depth error)")
+                        "fixed-step phantom model beside the exact path (speed and optical-depth error); "
+                        "crl: the focusing instrument with a 16-lens compound refractive lens")
     p.add_argument("--step", type=float, default=1.0 / 3.0, help="stepping: step length (mm)")
     p.add_argument("--batch-rays", type=int, default=10**8, help="rays per job of the batch")
     p.add_argument("--batch-angles", type=int, default=360)
@@ -70,6 +71,14 @@ KERNEL_SOURCES = ["paper_2410_08747_amd/csrc/mxr.hip", "paper_2410_08747_amd/csr
                   "paper_2410_08747_amd/build.py"]
 PROFILE = "profiles/k_trace_edct_projection_256.md"
 PROFILE_STEP = "profiles/k_trace_edct_step_256.md"
+PROFILE_CRL = "profiles/k_trace_crl_focusing.md"
+# FP64 VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (one add, multiply, divide or square root counted as one operation)
+FP64_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+# FP64 operations per lens of the compound refractive lens: two surfaces of
+# 66 (intersection quadratic 19 + root 4 + hit point 6 + aperture 4 + normal
+# 10 + Snell 14 + direction update 9) plus the lens centre and path sum (4)
+CRL_OPS_PER_LENS = 2 * 66 + 4
 
 
 def measured_traffic(profile=PROFILE):
@@ -529,6 +538,76 @@ def stepping_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def crl_bench(args):
+    """The focusing instrument (Gaussian source, 1 x 1 mm crop, 16-lens
+    compound refractive lens, 0.1 mm slit 14 m downstream, position and
+    energy monitors) at args.rays rays per step: rays/s and the FP64
+    arithmetic roofline of the lens."""
+    import torch
+    import paper_2410_08747_amd as mxr
+    import workloads
+
+    instr = workloads.crl_focusing()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    I = mxr.Instrument(instr, dev)
+    tallies = I.new_tallies()
+    stream = torch.cuda.current_stream()
+    n = args.rays
+
+    def zero():
+        for t in tallies:
+            for v in t.values():
+                v.zero_()
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    for w in range(args.warmup):
+        zero()
+        I.run(n, seed=100 + w, n_total=n, tallies=tallies, stream=stream)
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        zero()
+        events[k][0].record(stream)
+        I.run(n, seed=1 + k, n_total=n, tallies=tallies, stream=stream)
+        events[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    # rays entering the lens: the source emits weight 1, so the ledger's
+    # weight entering the lens counts them
+    m = min(n, 1 << 26)
+    led = I.new_ledger()
+    zero()
+    I.run(m, seed=1, n_total=m, tallies=tallies, ledger=led, stream=stream)
+    lv = led.cpu().numpy()
+    f_lens = float(lv[4 * 2] / m)
+    f_det = float(lv[4 * 4 + 3] / lv[0])
+    ops = f_lens * 16 * CRL_OPS_PER_LENS
+    achieved = ops * n / (kern_ms * 1e-3)
+    out = {
+        "metric": "rays/s (focusing instrument, 16-lens compound refractive lens)", "value": n * args.steps / wall,
+        "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "crl_focusing", "n_rays": n, "lenses": 16, "source": "Gaussian 48.2 x 9.5 um, "
+                   "100 x 4.3 urad, 23.32 keV +-1 keV", "monitors": "120x120 px PSD, 130-bin energy",
+                   "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_OPS_PEAK / 1e12,
+                     "unit": "T FP64 ops/s", "frac": achieved / FP64_OPS_PEAK, "traffic": measured_traffic(PROFILE_CRL)},
+        "kernel_ms": kern_ms,
+        "fraction_through_crop": f_lens,
+        "fraction_weight_detected": f_det,
+        "fp64_ops_per_ray": ops,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -546,6 +625,9 @@ def main():
         return
     if args.workload == "stepping":
         stepping_bench(args)
+        return
+    if args.workload == "crl":
+        crl_bench(args)
         return
     import torch
     import paper_2410_08747_amd as mxr

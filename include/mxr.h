@@ -122,6 +122,18 @@ typedef enum {
  *   (iy * nx + ix) * ne + ie.  Monitors do not absorb; rays that cannot
  *   reach the plane are absorbed.  par: 0 x min, 1 x max, 2 y min, 3 y max,
  *   4 E min, 5 E max.  dims: 0 nx, 1 ny, 2 ne.
+ * MXR_LENS_CRL -- compound refractive lens (paper, section 3.2: a stack of
+ *   double-sided parabolic beryllium lenses): N bi-concave lenses on the
+ *   local z axis, lens k centred at (k - (N-1)/2) pitch, its material between
+ *   the paraboloids z = c_k - w/2 - rho^2/2R and z = c_k + w/2 + rho^2/2R
+ *   inside the aperture radius (the frame beyond it is opaque: a surface
+ *   met outside it absorbs the ray, as does a surface the ray cannot reach
+ *   moving forward, or total reflection).  Refraction by Snell's law with
+ *   n = 1 - delta, delta(E) = delta_ref (E_ref / E)^2; weight times
+ *   exp(-mu(E) L / 10) with L the path inside the material (mm) and
+ *   mu = a / E^3 + b (1/cm).  par: 0 R, 1 N (integer, 1..1024), 2 on-axis
+ *   thickness w, 3 pitch (>= w + r_a^2 / R), 4 aperture radius r_a,
+ *   5 delta_ref (0 <= delta_ref < 0.5), 6 E_ref, 7 a, 8 b.
  */
 typedef enum {
     MXR_SRC_RECT_CONE = 0,
@@ -133,7 +145,8 @@ typedef enum {
     MXR_MIRROR_ELLIPTIC = 6,
     MXR_DCM = 7,
     MXR_POWDER = 8,
-    MXR_DETECTOR = 9
+    MXR_DETECTOR = 9,
+    MXR_LENS_CRL = 10
 } mxr_component_type;
 
 typedef struct {

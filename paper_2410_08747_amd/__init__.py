@@ -32,6 +32,7 @@ TYPE_CODES = {
     "dcm": 7,
     "powder": 8,
     "detector": 9,
+    "lens_crl": 10,
 }
 STATUS_EXITED = 1
 STATUS_ABSORBED = 2
@@ -396,6 +397,11 @@ def _params(c: Dict, s: mxr_component_desc, upload) -> None:
         p[0], p[1], p[2], p[3], p[4], p[5] = c["xmin"], c["xmax"], c["ymin"], c["ymax"], c["emin"], c["emax"]
         s.dims[0], s.dims[1], s.dims[2] = c["nx"], c["ny"], c["ne"]
         s.flags = 1 if c.get("wavelength", False) else 0
+    elif t == "lens_crl":
+        vals = [c["R"], c["n_lenses"], c["web"], c["pitch"], c["aperture"], c["delta_ref"], c["e_ref"],
+                c["mu_a"], c["mu_b"]]
+        for i, v in enumerate(vals):
+            p[i] = v
     else:
         raise ValueError(f"unknown component type {t}")
 

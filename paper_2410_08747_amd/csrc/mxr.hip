@@ -40,8 +40,11 @@ constexpr int kSrcConeProposal = 100;
 constexpr int kDetectorCollect = 101;
 // the phantom component (same descriptor) under the fixed-step model
 constexpr int kPhantomStep = 102;
+// a monitor whose histogram may be accumulated in a work-group private LDS
+// copy (small monitors of the compacting kernel), flushed once per group
+constexpr int kDetectorLds = 103;
 
-constexpr bool is_detector(int T) { return T == MXR_DETECTOR || T == kDetectorCollect; }
+constexpr bool is_detector(int T) { return T == MXR_DETECTOR || T == kDetectorCollect || T == kDetectorLds; }
 
 // ---------------------------------------------------------------- state --
 
@@ -52,6 +55,12 @@ struct RayEnd {
 
 struct LedgerLds {
     double *slots;  // 4 * ncomp + 1 doubles in LDS, or null
+    // work-group private monitors (kDetectorLds): the LDS block, and per
+    // tally slot the first word of the monitor's block (-1: not private)
+    // and its bin count; the block holds count (u64), sum w, sum w^2
+    double *tl = nullptr;
+    const int32_t *tl_off = nullptr;
+    const uint32_t *tl_nb = nullptr;
 };
 
 template <bool LEDGER>
@@ -117,6 +126,7 @@ __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream 
         int64_t bin = -1;
         if constexpr (T == MXR_SLIT) ok = comp_slit(c, ray);
         if constexpr (T == MXR_BOX) comp_box(c, ray);
+        if constexpr (T == MXR_LENS_CRL) ok = comp_lens(c, ray);
         if constexpr (T == MXR_PHANTOM || T == kPhantomStep) {
             double q[3], dl[3];
             to_local(c, ray, q, dl);
@@ -158,9 +168,22 @@ __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream 
                 end.bin = bin;
                 if constexpr (!TRACE) {
                     const uint32_t sl = c.slot;
-                    atomicAdd(a.tally.count[sl] + bin, 1ull);
-                    atomicAdd(a.tally.sum_w[sl] + bin, ray.w);
-                    atomicAdd(a.tally.sum_w2[sl] + bin, ray.w * ray.w);
+                    bool done = false;
+                    if constexpr (T == kDetectorLds) {
+                        const int32_t o = L.tl_off[sl];
+                        if (o >= 0) {
+                            const uint32_t nb = L.tl_nb[sl];
+                            atomicAdd((unsigned long long *)(L.tl + o) + bin, 1ull);
+                            atomicAdd(L.tl + o + nb + bin, ray.w);
+                            atomicAdd(L.tl + o + 2 * nb + bin, ray.w * ray.w);
+                            done = true;
+                        }
+                    }
+                    if (!done) {
+                        atomicAdd(a.tally.count[sl] + bin, 1ull);
+                        atomicAdd(a.tally.sum_w[sl] + bin, ray.w);
+                        atomicAdd(a.tally.sum_w2[sl] + bin, ray.w * ray.w);
+                    }
                 }
                 ledger_add<LEDGER>(L, 4 * k + 3, ray.w);
             }
@@ -189,6 +212,7 @@ __device__ __forceinline__ bool apply_dynamic(const DevComp &c, int k, Ray &ray,
         MXR_CASE(MXR_MIRROR_ELLIPTIC)
         MXR_CASE(MXR_DCM)
         MXR_CASE(MXR_POWDER)
+        MXR_CASE(MXR_LENS_CRL)
         case MXR_DETECTOR:
             if (a.hits.count) return apply<kDetectorCollect, LEDGER, TRACE, EXACT>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
             return apply<MXR_DETECTOR, LEDGER, TRACE, EXACT>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
@@ -338,6 +362,172 @@ __global__ __launch_bounds__(kBlock, WavesHint<C>::value) void k_trace(const Dev
     }
 }
 
+// ------------------------------------------------- survivor compaction --
+// Chains whose first components discard most rays (a crop aperture right
+// after the source: 87 % of the focusing instrument's rays, 98.7 % of the
+// basic absorber's) would run their costly later components on waves that
+// are mostly idle.  The compacting kernel runs only the cheap prefix
+// (components 0 .. CompactCut) per ray id, collects the ids of the rays that
+// survive it in a per-wave LDS queue (ballot + rank), and whenever 64 are
+// queued traces those 64 through the whole chain -- source again included,
+// which redraws exactly the same ray -- with every lane busy.  Used for plain
+// runs (no ledger, no per-ray output); the result is the same set of rays,
+// tallied in another order.
+template <class C>
+struct CompactCut {
+    static constexpr int value = -1;  // no compaction
+};
+
+// 64-ray rounds per wave: at most kCompactRounds, fewer for small runs so
+// that a launch still has several work-groups per compute unit
+constexpr int kCompactRounds = 64;
+
+// Monitors of the compacting kernel with at most kLdsTallyBins bins (and at
+// most kLdsTallyTotal bins over all of them, in instrument order) are
+// accumulated in a work-group private LDS histogram and added to the
+// caller's tallies once per work-group: a small monitor (e.g. 130 energy
+// bins) hit by every surviving ray would otherwise serialise its global
+// atomics on a few hundred addresses.  Layout per private monitor: count
+// (u64), sum w, sum w^2, n_bins each.  Returns the LDS bytes; off[slot] is
+// the private monitor's first bin in units of 8 bytes, or -1.
+__host__ __device__ inline uint32_t lds_tally_layout(const DevInstr &d, int32_t off[MXR_MAX_DETECTORS]) {
+    constexpr uint64_t kLdsTallyBins = 1024, kLdsTallyTotal = 2048;
+    uint64_t used = 0;
+    for (uint32_t s = 0; s < MXR_MAX_DETECTORS; ++s) off[s] = -1;
+    for (uint32_t k = 0; k < d.ncomp; ++k) {
+        const DevComp &c = d.c[k];
+        if (c.type != MXR_DETECTOR) continue;
+        const uint64_t nb = (uint64_t)c.dims[0] * c.dims[1] * c.dims[2];
+        if (nb <= kLdsTallyBins && used + nb <= kLdsTallyTotal) {
+            off[c.slot] = (int32_t)(3 * used);
+            used += nb;
+        }
+    }
+    return (uint32_t)(3 * used * 8);
+}
+
+template <bool EXACT, int CUT, int I, int T, int... Rest>
+__device__ __forceinline__ bool run_prefix(const DevInstr *ins, Ray &ray, Stream &s, uint64_t ray_id,
+                                           const RunArgs &a, RayEnd &end, const LedgerLds &L) {
+    static_assert(!is_detector(T), "the compaction prefix must end before the first monitor");
+    if (!apply<T, false, false, EXACT>(ins->c[I], I, ray, s, ray_id, a, nullptr, 0u, 1u, end, L)) return false;
+    if constexpr (I < CUT) return run_prefix<EXACT, CUT, I + 1, Rest...>(ins, ray, s, ray_id, a, end, L);
+    return true;
+}
+
+template <bool EXACT, int CUT, int... Ts>
+__device__ __forceinline__ bool run_prefix_chain(Chain<Ts...>, const DevInstr *ins, Ray &ray, Stream &s,
+                                                 uint64_t ray_id, const RunArgs &a, RayEnd &end,
+                                                 const LedgerLds &L) {
+    return run_prefix<EXACT, CUT, 0, Ts...>(ins, ray, s, ray_id, a, end, L);
+}
+
+__device__ __forceinline__ void fresh_ray(Ray &ray) {
+    ray.r[0] = ray.r[1] = ray.r[2] = 0.0;
+    ray.d[0] = ray.d[1] = ray.d[2] = 0.0;
+    ray.E = 0.0;
+    ray.w = 0.0;
+}
+
+// Each wave owns 64 * a.compact_rounds consecutive ray ids of the launch
+// (work-groups remapped to XCDs as in k_trace); the queue never holds more
+// than 127 ids (it is drained as soon as it reaches 64), every loop is
+// bounded by the wave's id count, and every wave reaches the two barriers.
+// The chains compacted here hold no phantom, so no attenuation table is
+// staged; the dynamic LDS holds the private monitors.
+template <class C, bool EXACT>
+__global__ __launch_bounds__(kBlock, WavesHint<C>::value) void k_trace_compact(const DevInstr *__restrict__ ins,
+                                                                               RunArgs a) {
+    constexpr int CUT = CompactCut<C>::value;
+    static_assert(CUT >= 0, "chain without a compaction prefix");
+    extern __shared__ double smem[];
+    __shared__ uint64_t queue[kBlock / 64][128];
+    // the private monitors' layout, set up once per work-group
+    __shared__ int32_t tl_off[MXR_MAX_DETECTORS];
+    __shared__ uint32_t tl_nb[MXR_MAX_DETECTORS];
+    __shared__ uint32_t lds_words;
+    if (threadIdx.x == 0) {
+        lds_words = lds_tally_layout(*ins, tl_off) / 8;
+        for (uint32_t sl = 0; sl < MXR_MAX_DETECTORS; ++sl) tl_nb[sl] = 0;
+        for (uint32_t k = 0; k < ins->ncomp; ++k) {
+            const DevComp &c = ins->c[k];
+            if (c.type == MXR_DETECTOR) tl_nb[c.slot] = c.dims[0] * c.dims[1] * c.dims[2];
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < lds_words; i += kBlock) smem[i] = 0.0;
+    __syncthreads();
+    LedgerLds L{nullptr};
+    L.tl = smem;
+    L.tl_off = tl_off;
+    L.tl_nb = tl_nb;
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    uint64_t *Q = queue[wave];
+    const uint64_t logical = (uint64_t)(blockIdx.x & 7u) * a.blocks_per_xcd + (blockIdx.x >> 3);
+    const uint64_t per_wave = 64ull * a.compact_rounds;
+    const uint64_t wbase = (logical * (kBlock / 64) + wave) * per_wave;
+    const uint64_t wend = wbase + per_wave < a.n ? wbase + per_wave : a.n;
+    uint32_t qn = 0;  // wave-uniform
+    for (uint64_t i0 = wbase; i0 < wend; i0 += 64) {
+        const uint64_t i = i0 + lane;
+        bool pass = false;
+        if (i < wend) {
+            Stream s;
+            s.init(a.seed, a.first + i, a.word3);
+            Ray ray;
+            fresh_ray(ray);
+            RayEnd end{kExited, -1, -1};
+            pass = run_prefix_chain<EXACT, CUT>(C{}, ins, ray, s, a.first + i, a, end, L);
+        }
+        const uint64_t mask = __builtin_amdgcn_ballot_w64(pass);
+        if (pass) {
+            const uint32_t rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            Q[qn + rank] = a.first + i;
+        }
+        qn += (uint32_t)__builtin_popcountll(mask);
+        __builtin_amdgcn_wave_barrier();
+        if (qn >= 64) {
+            const uint64_t ray_id = Q[lane];
+            Stream s;
+            s.init(a.seed, ray_id, a.word3);
+            Ray ray;
+            fresh_ray(ray);
+            RayEnd end{kExited, -1, -1};
+            (void)run_chain<false, false, EXACT>(C{}, ins, ray, s, ray_id, a, nullptr, 0u, 1u, end, L);
+            const uint32_t rest = qn - 64;
+            const uint64_t carry = lane < rest ? Q[64 + lane] : 0ull;
+            __builtin_amdgcn_wave_barrier();
+            if (lane < rest) Q[lane] = carry;
+            __builtin_amdgcn_wave_barrier();
+            qn = rest;
+        }
+    }
+    if (lane < qn) {
+        const uint64_t ray_id = Q[lane];
+        Stream s;
+        s.init(a.seed, ray_id, a.word3);
+        Ray ray;
+        fresh_ray(ray);
+        RayEnd end{kExited, -1, -1};
+        (void)run_chain<false, false, EXACT>(C{}, ins, ray, s, ray_id, a, nullptr, 0u, 1u, end, L);
+    }
+    // add the private monitors to the caller's tallies (bins nobody hit skipped)
+    __syncthreads();
+    for (uint32_t sl = 0; sl < MXR_MAX_DETECTORS; ++sl) {
+        const int32_t o = tl_off[sl];
+        if (o < 0) continue;
+        const uint32_t nb = tl_nb[sl];
+        for (uint32_t b = threadIdx.x; b < nb; b += kBlock) {
+            const unsigned long long n = ((const unsigned long long *)(smem + o))[b];
+            if (n == 0) continue;
+            atomicAdd(a.tally.count[sl] + b, n);
+            atomicAdd(a.tally.sum_w[sl] + b, smem[o + nb + b]);
+            atomicAdd(a.tally.sum_w2[sl] + b, smem[o + 2 * nb + b]);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- batch --
 
 // One job of a batch: its instrument and the arguments of its run (read in
@@ -483,8 +673,30 @@ using ChainBeamline = Chain<MXR_SRC_GAUSSIAN, MXR_MIRROR_ELLIPTIC, MXR_DCM, MXR_
 using ChainEdctProposal = Chain<kSrcConeProposal, MXR_PHANTOM, MXR_DETECTOR>;
 using ChainEdctCollect = Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, kDetectorCollect>;
 using ChainEdctStep = Chain<MXR_SRC_CONE_BEAM, kPhantomStep, MXR_DETECTOR>;
+using ChainCrl = Chain<MXR_SRC_GAUSSIAN, MXR_SLIT, MXR_LENS_CRL, MXR_SLIT, MXR_DETECTOR, MXR_DETECTOR>;
 
-enum Recipe { kRecipeGeneric = 0, kRecipeBasic, kRecipeEdct, kRecipeBeamline, kRecipeEdctStep, kNumRecipes };
+// their compacting forms: compaction after the crop aperture (component 1),
+// small monitors in work-group private LDS
+using ChainCrlCompact = Chain<MXR_SRC_GAUSSIAN, MXR_SLIT, MXR_LENS_CRL, MXR_SLIT, kDetectorLds, kDetectorLds>;
+using ChainBasicCompact = Chain<MXR_SRC_RECT_CONE, MXR_SLIT, MXR_BOX, kDetectorLds>;
+template <>
+struct CompactCut<ChainCrlCompact> {
+    static constexpr int value = 1;
+};
+template <>
+struct CompactCut<ChainBasicCompact> {
+    static constexpr int value = 1;
+};
+
+enum Recipe {
+    kRecipeGeneric = 0,
+    kRecipeBasic,
+    kRecipeEdct,
+    kRecipeBeamline,
+    kRecipeEdctStep,
+    kRecipeCrl,
+    kNumRecipes
+};
 
 typedef void (*KernelFn)(const DevInstr *, RunArgs);
 
@@ -518,9 +730,20 @@ KernelFn pick_kernel(int recipe, bool ledger, bool trace, bool exact, int mode) 
             return exact ? KernelSet<ChainEdct, true>::get(ledger, trace) : KernelSet<ChainEdct, false>::get(ledger, trace);
         case kRecipeBeamline: return KernelSet<ChainBeamline, true>::get(ledger, trace);
         case kRecipeEdctStep: return KernelSet<ChainEdctStep, true>::get(ledger, trace);
+        case kRecipeCrl: return KernelSet<ChainCrl, true>::get(ledger, trace);
         default:
             return exact ? KernelSet<ChainGeneric, true>::get(ledger, trace)
                          : KernelSet<ChainGeneric, false>::get(ledger, trace);
+    }
+}
+
+// the compacting kernel for plain runs of a chain with a compaction prefix,
+// or nullptr
+KernelFn pick_compact(int recipe) {
+    switch (recipe) {
+        case kRecipeBasic: return k_trace_compact<ChainBasicCompact, true>;
+        case kRecipeCrl: return k_trace_compact<ChainCrlCompact, true>;
+        default: return nullptr;
     }
 }
 
@@ -556,6 +779,7 @@ int match_recipe(const DevInstr &d) {
     if (is({MXR_SRC_RECT_CONE, MXR_SLIT, MXR_BOX, MXR_DETECTOR})) return kRecipeBasic;
     if (is({MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR})) return (d.c[1].flags & 1u) ? kRecipeEdctStep : kRecipeEdct;
     if (is({MXR_SRC_GAUSSIAN, MXR_MIRROR_ELLIPTIC, MXR_DCM, MXR_POWDER, MXR_DETECTOR})) return kRecipeBeamline;
+    if (is({MXR_SRC_GAUSSIAN, MXR_SLIT, MXR_LENS_CRL, MXR_SLIT, MXR_DETECTOR, MXR_DETECTOR})) return kRecipeCrl;
     return kRecipeGeneric;
 }
 
@@ -613,6 +837,7 @@ struct mxr_instrument {
     uint32_t n_det;
     uint64_t det_bins[MXR_MAX_DETECTORS];
     uint64_t strata;      // G of the cone-beam source, 0 if none
+    int n_cu;             // compute units of the device
     PropTable *prop_dev;  // proposal mixture (device), allocated on first use
     PropTable prop_host;  // its host copy (branch sizes are set per run)
     bool prop_on;
@@ -709,6 +934,19 @@ static mxr_status derive(const mxr_component_desc &s, DevComp &c, int k, uint32_
                 }
             }
             c.aux[4] = exact ? 1.0 : 0.0;
+            break;
+        }
+        case MXR_LENS_CRL: {
+            // 0 R, 1 N, 2 on-axis thickness w, 3 pitch, 4 aperture radius,
+            // 5 delta at 6 E ref, 7-8 mu = a / E^3 + b
+            if (!(p[0] > 0 && p[1] >= 1 && p[1] <= 1024 && p[1] == std::floor(p[1]) && p[2] >= 0 && p[4] > 0 &&
+                  p[5] >= 0 && p[5] < 0.5 && p[6] > 0 && p[7] >= 0 && p[8] >= 0))
+                return fail(MXR_E_INVALID, "component %d: bad lens parameters", k);
+            if (!(p[3] >= p[2] + p[4] * p[4] / p[0]))
+                return fail(MXR_E_INVALID, "component %d: lens pitch below w + r_a^2 / R (lenses would overlap)", k);
+            c.aux[0] = 1.0 / p[0];
+            c.aux[1] = 1.0 / (2.0 * p[0]);
+            c.aux[2] = p[4] * p[4];
             break;
         }
         case MXR_MIRROR_ELLIPTIC: {
@@ -830,6 +1068,9 @@ mxr_status mxr_instrument_create(const mxr_instrument_desc *desc, mxr_instrument
         delete ins;
         return hip_fail(e, "hipGetDevice");
     }
+    if (hipDeviceGetAttribute(&ins->n_cu, hipDeviceAttributeMultiprocessorCount, ins->device) != hipSuccess ||
+        ins->n_cu < 1)
+        ins->n_cu = 256;
     e = hipMalloc((void **)&ins->dev, sizeof(DevInstr));
     if (e != hipSuccess) {
         delete ins;
@@ -886,9 +1127,14 @@ static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, b
     const int mode = base.hits.count ? (base.prop ? kModeProposalCollect : kModeCollect)
                                      : (base.prop ? kModeProposal : kModePlain);
     KernelFn k = pick_kernel(ins->recipe, ledger, trace, exact, mode);
+    KernelFn kc = (!ledger && !trace && mode == kModePlain) ? pick_compact(ins->recipe) : nullptr;
     size_t shmem = 0;
     if (ins->host.phantom >= 0) shmem += (size_t)ins->host.n_mat * ins->host.n_ebin * sizeof(double);
     if (ledger) shmem += (size_t)(4 * ins->host.ncomp + 1) * sizeof(double);
+    if (kc) {
+        int32_t off[MXR_MAX_DETECTORS];
+        shmem = lds_tally_layout(ins->host, off);
+    }
     // one lane per ray; launches of at most 2^30 work-groups (a multiple of
     // the 8 XCDs), so ray ranges beyond that are split into several launches
     const uint64_t max_rays = (1ull << 30) * kBlock;
@@ -912,10 +1158,15 @@ static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, b
         } else {
             a.first = base.first + done;
         }
-        const uint64_t groups = (m + kBlock - 1) / kBlock;
+        // compacting kernel: as many rounds as keep >= 4 work-groups per CU
+        a.compact_rounds = (uint32_t)std::max<uint64_t>(
+            1, std::min<uint64_t>(kCompactRounds, m / ((uint64_t)kBlock * 4 * ins->n_cu)));
+        const uint64_t rays_per_group = kc ? (uint64_t)kBlock * a.compact_rounds : (uint64_t)kBlock;
+        const uint64_t groups = (m + rays_per_group - 1) / rays_per_group;
         a.blocks_per_xcd = (uint32_t)((groups + 7) / 8);
         const uint64_t blocks = (uint64_t)a.blocks_per_xcd * 8;
-        hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kBlock), shmem, stream, (const DevInstr *)ins->dev, a);
+        hipLaunchKernelGGL(kc ? kc : k, dim3((unsigned)blocks), dim3(kBlock), shmem, stream,
+                           (const DevInstr *)ins->dev, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         done += m;

@@ -92,6 +92,7 @@ struct RunArgs {
     uint64_t G, G2;  // strata per side used, and its square
     uint32_t word3;  // purpose << 24 | job
     uint32_t blocks_per_xcd;
+    uint32_t compact_rounds;  // compacting kernel: 64-ray rounds per wave
     TallyPtrs tally;
     double *ledger;
     const uint64_t *ids;  // trace mode: ray ids
@@ -421,6 +422,74 @@ __device__ __forceinline__ void comp_box(const DevComp &c, Ray &ray) {
     double E = ray.E;
     double mu = c.par[3] / (E * E * E) + c.par[4];
     ray.w = ray.w * exp(-(mu * L) / 10.0);
+}
+
+// --------------------------------------------------------------- lens ----
+// Compound refractive lens (section 3.2): N identical bi-concave parabolic
+// lenses; lens k (centre c_k = (k - (N-1)/2) p on the local z axis) holds
+// material between z = c_k - w/2 - rho^2/2R and z = c_k + w/2 + rho^2/2R
+// inside the aperture radius.  Per surface: the intersection quadratic's
+// root nearest -C/B in the stable form C / q', the aperture test, the unit
+// normal into the next medium, and Snell's law in vector form with the
+// normal coefficient sqrt(k) - eta cos_i written as
+// (1 - eta^2) / (sqrt(k) + eta cos_i) (no cancellation; 1 - eta^2 comes
+// in closed form from delta).  The path inside the material is summed and
+// the weight attenuated once.  S = -1 front surface, +1 back surface.
+template <int S>
+__device__ __forceinline__ bool lens_surface(double q[3], double dl[3], double z0, double inv_R, double inv_2R,
+                                             double ra2, double eta, double one_m_eta2, double &t_out) {
+    const double A = (double)(-S) * ((dl[0] * dl[0] + dl[1] * dl[1]) * inv_2R);
+    const double B = dl[2] - (double)S * ((q[0] * dl[0] + q[1] * dl[1]) * inv_R);
+    const double C = (q[2] - z0) - (double)S * ((q[0] * q[0] + q[1] * q[1]) * inv_2R);
+    const double disc = B * B - 4.0 * A * C;
+    if (!(disc >= 0.0)) return false;
+    const double qq = -0.5 * (B + copysign(sqrt(disc), B));
+    if (qq == 0.0) return false;
+    const double t = C / qq;
+    if (!(t >= 0.0)) return false;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) q[i] = q[i] + t * dl[i];
+    if (q[0] * q[0] + q[1] * q[1] > ra2) return false;
+    const double g0 = (double)(-S) * (q[0] * inv_R), g1 = (double)(-S) * (q[1] * inv_R);
+    const double inv_gn = 1.0 / sqrt(g0 * g0 + g1 * g1 + 1.0);
+    const double m0 = g0 * inv_gn, m1 = g1 * inv_gn, m2 = inv_gn;
+    const double cos_i = dl[0] * m0 + dl[1] * m1 + dl[2] * m2;
+    if (!(cos_i > 0.0)) return false;
+    const double k = 1.0 - eta * eta * (1.0 - cos_i * cos_i);
+    if (!(k >= 0.0)) return false;
+    const double gc = one_m_eta2 / (sqrt(k) + eta * cos_i);
+    dl[0] = eta * dl[0] + gc * m0;
+    dl[1] = eta * dl[1] + gc * m1;
+    dl[2] = eta * dl[2] + gc * m2;
+    t_out = t;
+    return true;
+}
+
+// aux: 0 1/R, 1 1/(2R), 2 aperture radius^2
+__device__ __forceinline__ bool comp_lens(const DevComp &c, Ray &ray) {
+    double q[3], dl[3];
+    to_local(c, ray, q, dl);
+    const double inv_R = c.aux[0], inv_2R = c.aux[1], ra2 = c.aux[2];
+    const double w = c.par[2], pitch = c.par[3];
+    const int N = (int)c.par[1];
+    const double E = ray.E;
+    const double er = c.par[6] / E;
+    const double delta = c.par[5] * (er * er);
+    const double mu = c.par[7] / (E * E * E) + c.par[8];
+    const double eta_in = 1.0 / (1.0 - delta), eta_out = 1.0 - delta;
+    const double ome_in = -delta * (2.0 - delta) / ((1.0 - delta) * (1.0 - delta));
+    const double ome_out = delta * (2.0 - delta);
+    const double half_n1 = 0.5 * (double)(N - 1);
+    double L = 0.0, t;
+    for (int k = 0; k < N; ++k) {
+        const double ck = ((double)k - half_n1) * pitch;
+        if (!lens_surface<-1>(q, dl, ck - 0.5 * w, inv_R, inv_2R, ra2, eta_in, ome_in, t)) return false;
+        if (!lens_surface<1>(q, dl, ck + 0.5 * w, inv_R, inv_2R, ra2, eta_out, ome_out, t)) return false;
+        L = L + t;
+    }
+    ray.w = ray.w * exp(-(mu * L) / 10.0);
+    to_lab(c, q, dl, ray);
+    return true;
 }
 
 // ------------------------------------------------------------ phantom ----
