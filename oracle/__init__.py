@@ -41,6 +41,14 @@ How each function is pinned (tests marked ``not gpu``):
   paraxial focal length R / (2 N delta) and the image distance of the thin
   lens, transmission exp(-mu N (w + rho^2 / R)) for paraxial rays, the
   aperture and the refraction-free limit delta = 0.
+* scattering phantom (scatter orders) -- the Klein-Nishina total cross
+  section against a quadrature of the differential one and its Thomson
+  limit; the forced interaction depth against the truncated exponential
+  (KS); the weighted angular distribution of single scatter against
+  Klein-Nishina and Thomson (binned); Compton energies against the
+  scattering angle ray by ray; the mean weight of single scatter in a
+  homogeneous cube against the closed form; no scattering material gives
+  no weight.
 * ledger -- weight emitted equals absorbed + attenuated + exiting weight.
 """
 from __future__ import annotations
@@ -148,6 +156,8 @@ def _load():
         lib.mxo_lens_debug.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.mxo_lens_debug.restype = ctypes.c_int
+        lib.mxo_kn_f.argtypes = [ctypes.c_double]
+        lib.mxo_kn_f.restype = ctypes.c_double
         lib.mxo_ppnd16.argtypes = [ctypes.c_double]
         lib.mxo_ppnd16.restype = ctypes.c_double
         lib.mxo_truncnorm.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
@@ -228,13 +238,20 @@ class Instrument:
             mu = self._keep_arr(c["mu_table"], np.float64)
             nz, ny, nx = vol.shape
             s.dims[0], s.dims[1], s.dims[2] = nx, ny, nz
-            s.dims[3] = mu.shape[0]
+            s.dims[3] = mu.shape[1] if mu.ndim == 3 else mu.shape[0]
             s.data0, s.data1 = _ptr(vol), _ptr(mu)
             s.n0, s.n1 = vol.size, mu.size
             p[0], p[1], p[2] = c["voxel"], c["table_emin"], c["table_emax"]
             if c.get("step") is not None:
                 s.flags = 1
                 p[3] = c["step"]
+            if c.get("scatter_order") is not None:
+                s.flags = 2
+                p[4] = c["scatter_order"]
+                if c.get("scatter_target") is not None:
+                    s.flags = 2 | 4
+                    for i, v in enumerate(np.asarray(c["scatter_target"], dtype=np.float64).reshape(9)):
+                        p[5 + i] = v
         elif t == "mirror_elliptic":
             tab = self._keep_arr(c["reflectivity"], np.float64)
             p[0], p[1], p[2], p[3], p[4], p[5] = c["p"], c["q"], c["theta0"], c["length"], c["width"], c["theta_max"]
@@ -376,6 +393,11 @@ def lens(lens_dict: Dict, q, dl, E: float):
     qo, do, w = np.zeros(3), np.zeros(3), np.zeros(1)
     ok = lib.mxo_lens_debug(ctypes.addressof(ins.arr[0]), _ptr(qa), _ptr(da), float(E), _ptr(qo), _ptr(do), _ptr(w))
     return bool(ok), qo, do, float(w[0])
+
+
+def kn_f(k: float) -> float:
+    """Klein-Nishina total cross section over 2 pi r_e^2 at k = E / m_e c^2."""
+    return _load().mxo_kn_f(float(k))
 
 
 def ppnd16(p: float) -> float:

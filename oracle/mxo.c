@@ -644,7 +644,10 @@ static void volume_from(const mxo_comp *c, mxo_volume *V)
     V->t_emin = c->par[1];
     V->t_emax = c->par[2];
     V->n_mat = c->dims[3];
-    V->n_ebin = c->n1 / (c->dims[3] > 0 ? c->dims[3] : 1);
+    /* a scattering phantom's table holds three channels (total, Rayleigh,
+     * Compton), each n_mat x n_ebin */
+    int64_t channels = (c->flags & 2u) ? 3 : 1;
+    V->n_ebin = c->n1 / ((c->dims[3] > 0 ? c->dims[3] : 1) * channels);
 }
 
 static int64_t floor_index(double x, int64_t n)
@@ -809,6 +812,253 @@ double mxo_step_debug(const mxo_comp *c, const double q[3], const double dl[3], 
     volume_from(c, &V);
     return mxo_step_tau(&V, q, dl, E, c->par[3], n_steps);
 }
+
+/* ------------------------------------------------ scattering phantom ---- */
+/* Scattering in the voxel sample (section 3.3: the sample models absorption
+ * and scattering; scattering prolongs the paths).  Estimator: the image is
+ * split by scatter order.  A run of order K traces, for every source ray,
+ * the contribution of photons that interact exactly K times in the volume,
+ * each interaction forced:
+ *   - along the current direction the chord's optical depth tau_tot (total
+ *     attenuation, channel 0) is computed; the interaction depth is drawn
+ *     from the truncated exponential, tau* = -log(1 - u1 (1 - e^-tau_tot)),
+ *     and located on the segment list (the point where the running optical
+ *     depth reaches tau*); the weight takes the factor 1 - e^-tau_tot;
+ *   - at that point the scatter albedo (mu_R + mu_C) / mu_tot of the voxel's
+ *     material multiplies the weight; Rayleigh is chosen with probability
+ *     mu_R / (mu_R + mu_C) (u2), Compton otherwise;
+ *   - the new direction is drawn uniformly on the sphere (cos theta = 2 u3 - 1,
+ *     phi = 2 pi u4 about the old direction, in the frame e1 = (d x a) / |d x a|,
+ *     e2 = d x e1, a = y unless |d_y| >= 1/2, then x) and the weight takes
+ *     4 pi times the normalised angular density: Rayleigh as Thomson
+ *     scattering, 3 (1 + cos^2) / 4 (no form factor); Compton as
+ *     Klein-Nishina for free electrons, rho^2 (rho + 1/rho - sin^2) / f(k)
+ *     with k = E / m_e c^2, rho = E' / E = 1 / (1 + k (1 - cos theta)) and
+ *     2 pi f(k) r_e^2 the Klein-Nishina total cross section; Compton scattering
+ *     lowers the energy to E' = rho E;
+ * and after the K-th interaction the ray leaves the volume along its new
+ * direction attenuated by e^-tau_exit at its new energy.
+ * Aimed last scatter (flags bit 2, a next-event form for a monitor of
+ * known extent): the K-th direction points instead at a point drawn
+ * uniformly on a target rectangle (centre par[5..7], half-axes par[8..10]
+ * and par[11..13], lab frame; the point is centre + (2 u3 - 1) a +
+ * (2 u4 - 1) b), whose density per steradian is dist^2 / (|n . d'| area),
+ * and the weight takes the ratio of the scattering density per steradian
+ * (Thomson 3 (1 + cos^2) / 16 pi, Klein-Nishina rho^2 (rho + 1/rho -
+ * sin^2) / 4 pi f(k)) to it; photons scattered off the target are not
+ * followed, so the estimator serves tallies on the target.  The ray reported
+ * by the component sits at the last interaction point.  Order 0 is the
+ * plain (uncollided) run; the orders add up to the image.  A ray that meets
+ * no material (tau_tot = 0) or no scattering material (mu_R + mu_C = 0)
+ * carries no weight in this estimator and is absorbed here.
+ * Draws: four per order (u1 .. u4). */
+static const double ME_C2_KEV = 510.99895;
+
+/* Klein-Nishina total cross section over 2 pi r_e^2 */
+static double kn_f(double k)
+{
+    double l = log1p(2.0 * k);
+    return ((1.0 + k) / (k * k)) * (2.0 * (1.0 + k) / (1.0 + 2.0 * k) - l / k) + l / (2.0 * k) -
+           (1.0 + 3.0 * k) / ((1.0 + 2.0 * k) * (1.0 + 2.0 * k));
+}
+
+/* segments of the chord in traversal order: start and end alpha and the
+ * voxel of each (zero-length segments dropped), from the sorted list of all
+ * plane crossings as in mxo_siddon */
+static int64_t chord_segments(const mxo_volume *V, const double q[3], const double dl[3], double *a0, double *a1,
+                              int64_t *vox, int64_t cap)
+{
+    double inv[3];
+    double a_in = 0.0, a_out = INFINITY;
+    for (int i = 0; i < 3; ++i) {
+        double lo_plane = V->corner[i];
+        double hi_plane = V->corner[i] + (double)V->n[i] * V->v;
+        if (dl[i] == 0.0) {
+            inv[i] = 0.0;
+            if (!(q[i] > lo_plane && q[i] < hi_plane))
+                return 0;
+        } else {
+            inv[i] = 1.0 / dl[i];
+            double b0 = (lo_plane - q[i]) * inv[i], b1 = (hi_plane - q[i]) * inv[i];
+            double lo = b0 < b1 ? b0 : b1, hi = b0 < b1 ? b1 : b0;
+            if (lo > a_in) a_in = lo;
+            if (hi < a_out) a_out = hi;
+        }
+    }
+    if (!(a_out > a_in))
+        return 0;
+    int64_t m = 0;
+    double *alpha = (double *)malloc((size_t)(V->n[0] + V->n[1] + V->n[2] + 5) * sizeof(double));
+    alpha[m++] = a_in;
+    for (int i = 0; i < 3; ++i) {
+        if (dl[i] == 0.0)
+            continue;
+        for (int64_t p = 0; p <= V->n[i]; ++p) {
+            double a = ((V->corner[i] + (double)p * V->v) - q[i]) * inv[i];
+            if (a > a_in && a < a_out)
+                alpha[m++] = a;
+        }
+    }
+    alpha[m++] = a_out;
+    qsort(alpha, (size_t)m, sizeof(double), cmp_double);
+    int64_t ns = 0;
+    for (int64_t k = 0; k + 1 < m && ns < cap; ++k) {
+        if (!(alpha[k + 1] - alpha[k] > 0.0))
+            continue;
+        double mid = 0.5 * (alpha[k] + alpha[k + 1]);
+        int64_t idx[3];
+        for (int i = 0; i < 3; ++i)
+            idx[i] = floor_index((q[i] + mid * dl[i] - V->corner[i]) / V->v, V->n[i]);
+        a0[ns] = alpha[k];
+        a1[ns] = alpha[k + 1];
+        vox[ns] = idx[0] + V->n[0] * (idx[1] + V->n[1] * idx[2]);
+        ns++;
+    }
+    free(alpha);
+    return ns;
+}
+
+/* one forced interaction along dl from q: returns 0 if the chord holds no
+ * attenuating material, else moves q to the interaction point and gives the
+ * weight factor 1 - e^-tau_tot and the material there */
+static int forced_interaction(const mxo_volume *V, double q[3], const double dl[3], int64_t e, double u1,
+                              double *p_int, int64_t *mat_out)
+{
+    int64_t cap = V->n[0] + V->n[1] + V->n[2] + 5;
+    double *a0 = (double *)malloc((size_t)cap * sizeof(double));
+    double *a1 = (double *)malloc((size_t)cap * sizeof(double));
+    int64_t *vox = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
+    int64_t ns = chord_segments(V, q, dl, a0, a1, vox, cap);
+    double tau_tot = 0.0;
+    for (int64_t j = 0; j < ns; ++j)
+        tau_tot = tau_tot + V->mu[V->vol[vox[j]] * V->n_ebin + e] * (a1[j] - a0[j]) / 10.0;
+    int ok = 0;
+    if (tau_tot > 0.0) {
+        double p = -expm1(-tau_tot);
+        double tau_star = -log1p(-u1 * p);
+        double tc = 0.0, s = 0.0;
+        int64_t m = -1;
+        for (int64_t j = 0; j < ns; ++j) {
+            int64_t mj = V->vol[vox[j]];
+            double mu = V->mu[mj * V->n_ebin + e] / 10.0;
+            if (!(mu > 0.0))
+                continue;
+            double d = mu * (a1[j] - a0[j]);
+            m = mj;
+            s = a1[j];
+            if (tc + d >= tau_star) {
+                s = a0[j] + (tau_star - tc) / mu;
+                break;
+            }
+            tc = tc + d;
+        }
+        for (int i = 0; i < 3; ++i)
+            q[i] = q[i] + s * dl[i];
+        *p_int = p;
+        *mat_out = m;
+        ok = 1;
+    }
+    free(a0);
+    free(a1);
+    free(vox);
+    return ok;
+}
+
+static int comp_phantom_scatter(const mxo_comp *c, mxo_stream *st, int draw0, mxo_ray *ray)
+{
+    double q[3], dl[3];
+    to_local(c, ray->r, ray->d, q, dl);
+    mxo_volume V;
+    volume_from(c, &V);
+    const int64_t K = (int64_t)c->par[4];
+    const int64_t plane = V.n_mat * V.n_ebin;
+    double E = ray->E, w = ray->w;
+    double ebin_scale = (double)V.n_ebin / (V.t_emax - V.t_emin);
+    for (int64_t k = 0; k < K; ++k) {
+        int64_t e = floor_index((E - V.t_emin) * ebin_scale, V.n_ebin);
+        double p_int;
+        int64_t m;
+        if (!forced_interaction(&V, q, dl, e, stream_uniform(st, draw0 + 4 * (int)k), &p_int, &m))
+            return 0;
+        double mu_t = V.mu[m * V.n_ebin + e];
+        double mu_r = V.mu[plane + m * V.n_ebin + e];
+        double mu_c = V.mu[2 * plane + m * V.n_ebin + e];
+        if (!(mu_r + mu_c > 0.0))
+            return 0;
+        double albedo = (mu_r + mu_c) / mu_t;
+        int rayleigh = stream_uniform(st, draw0 + 4 * (int)k + 1) < mu_r / (mu_r + mu_c);
+        double ct = 2.0 * stream_uniform(st, draw0 + 4 * (int)k + 2) - 1.0;
+        double phi = 2.0 * M_PI * stream_uniform(st, draw0 + 4 * (int)k + 3);
+        double nd[3], dens_ratio = 4.0 * M_PI; /* isotropic: 1 / density = 4 pi */
+        if ((c->flags & 4u) && k == K - 1) {
+            /* aimed: a point on the target rectangle, in the local frame */
+            double tl[3], ta[3], tb[3], tw[3];
+            for (int i = 0; i < 3; ++i)
+                tw[i] = c->par[5 + i] - c->pos[i];
+            for (int i = 0; i < 3; ++i) {
+                tl[i] = c->rot[3 * i] * tw[0] + c->rot[3 * i + 1] * tw[1] + c->rot[3 * i + 2] * tw[2];
+                ta[i] = c->rot[3 * i] * c->par[8] + c->rot[3 * i + 1] * c->par[9] + c->rot[3 * i + 2] * c->par[10];
+                tb[i] = c->rot[3 * i] * c->par[11] + c->rot[3 * i + 1] * c->par[12] + c->rot[3 * i + 2] * c->par[13];
+            }
+            double sa = 2.0 * stream_uniform(st, draw0 + 4 * (int)k + 2) - 1.0;
+            double sb = 2.0 * stream_uniform(st, draw0 + 4 * (int)k + 3) - 1.0;
+            double r[3];
+            for (int i = 0; i < 3; ++i)
+                r[i] = (tl[i] + sa * ta[i] + sb * tb[i]) - q[i];
+            double dist2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            double dist = sqrt(dist2);
+            double nrm[3] = {ta[1] * tb[2] - ta[2] * tb[1], ta[2] * tb[0] - ta[0] * tb[2], ta[0] * tb[1] - ta[1] * tb[0]};
+            double area4 = sqrt(nrm[0] * nrm[0] + nrm[1] * nrm[1] + nrm[2] * nrm[2]); /* |a x b| */
+            if (!(dist > 0.0) || !(area4 > 0.0))
+                return 0;
+            for (int i = 0; i < 3; ++i)
+                nd[i] = r[i] / dist;
+            double cosn = fabs(nd[0] * nrm[0] + nd[1] * nrm[1] + nd[2] * nrm[2]) / area4;
+            if (!(cosn > 0.0))
+                return 0;
+            /* density of the aimed direction: dist^2 / (cos_n * 4 |a x b|) */
+            dens_ratio = (cosn * 4.0 * area4) / dist2;
+            ct = dl[0] * nd[0] + dl[1] * nd[1] + dl[2] * nd[2];
+        } else {
+            double a[3] = {0.0, 1.0, 0.0};
+            if (!(fabs(dl[1]) < 0.5)) {
+                a[0] = 1.0;
+                a[1] = 0.0;
+            }
+            double e1[3] = {dl[1] * a[2] - dl[2] * a[1], dl[2] * a[0] - dl[0] * a[2], dl[0] * a[1] - dl[1] * a[0]};
+            double n1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+            for (int i = 0; i < 3; ++i)
+                e1[i] = e1[i] / n1;
+            double e2[3] = {dl[1] * e1[2] - dl[2] * e1[1], dl[2] * e1[0] - dl[0] * e1[2],
+                            dl[0] * e1[1] - dl[1] * e1[0]};
+            double sn = sqrt(1.0 - ct * ct), cp = cos(phi), sp = sin(phi);
+            for (int i = 0; i < 3; ++i)
+                nd[i] = ct * dl[i] + sn * (cp * e1[i] + sp * e2[i]);
+        }
+        /* scattering density per steradian at cos theta = ct */
+        double st2 = 1.0 - ct * ct, dens;
+        if (rayleigh) {
+            dens = 3.0 * (1.0 + ct * ct) / (16.0 * M_PI);
+        } else {
+            double kk = E / ME_C2_KEV;
+            double rho = 1.0 / (1.0 + kk * (1.0 - ct));
+            dens = rho * rho * (rho + 1.0 / rho - st2) / (4.0 * M_PI * kn_f(kk));
+            E = rho * E;
+        }
+        w = w * (p_int * albedo * (dens * dens_ratio));
+        for (int i = 0; i < 3; ++i)
+            dl[i] = nd[i];
+    }
+    /* leave the volume along the last direction at the last energy */
+    double tau = mxo_siddon(&V, q, dl, E, NULL, NULL, 0, NULL);
+    ray->E = E;
+    ray->w = w * exp(-tau);
+    to_lab(c, q, dl, ray->r, ray->d);
+    return 1;
+}
+
+/* exported debug entry: the Klein-Nishina f(k) */
+double mxo_kn_f(double k) { return kn_f(k); }
 
 /* flags bit 0: the fixed-step model with step length par[3] (mm) instead of
  * Siddon's exact path */
@@ -1147,13 +1397,14 @@ static int comp_detector(const mxo_comp *c, mxo_ray *ray, int64_t *bin)
     return 1;
 }
 
-static int draws_of(int type)
+static int draws_of(const mxo_comp *c)
 {
-    switch (type) {
+    switch (c->type) {
     case MXO_SRC_RECT_CONE: return 5;
     case MXO_SRC_CONE_BEAM: return 3;
     case MXO_SRC_GAUSSIAN: return 5;
     case MXO_POWDER: return 2;
+    case MXO_PHANTOM: return (c->flags & 2u) ? 4 * (int)c->par[4] : 0;
     default: return 0;
     }
 }
@@ -1199,7 +1450,7 @@ static void trace_from(const mxo_instr *I, uint64_t ray_id, int k0, mxo_ray *ray
     ray->bin = -1;
     int draw = 0, det = 0;
     for (int k = 0; k < k0; ++k)
-        draw += draws_of(I->comps[k].type);
+        draw += draws_of(&I->comps[k]);
     for (int k = k0; k < I->ncomp; ++k) {
         const mxo_comp *c = &I->comps[k];
         double w_in = ray->w;
@@ -1218,7 +1469,12 @@ static void trace_from(const mxo_instr *I, uint64_t ray_id, int k0, mxo_ray *ray
         case MXO_SRC_GAUSSIAN: src_gaussian(c, &s, ray); w_in = ray->w; break;
         case MXO_SLIT: ok = comp_slit(c, ray); break;
         case MXO_BOX: comp_box(c, ray); break;
-        case MXO_PHANTOM: comp_phantom(c, ray); break;
+        case MXO_PHANTOM:
+            if (c->flags & 2u)
+                ok = comp_phantom_scatter(c, &s, draw, ray);
+            else
+                comp_phantom(c, ray);
+            break;
         case MXO_MIRROR_ELLIPTIC: ok = comp_mirror(c, ray); break;
         case MXO_DCM: ok = comp_dcm(c, ray); break;
         case MXO_POWDER: ok = comp_powder(c, &s, draw, ray); break;
@@ -1226,7 +1482,7 @@ static void trace_from(const mxo_instr *I, uint64_t ray_id, int k0, mxo_ray *ray
         case MXO_LENS_CRL: ok = comp_lens(c, ray); break;
         default: ok = 0; break;
         }
-        draw += draws_of(c->type);
+        draw += draws_of(c);
         if (ledger)
             kadd(&ledger[4 * k + 0], w_in);
         if (!ok && k == 0) {

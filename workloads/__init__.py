@@ -80,6 +80,30 @@ def make_mu_tables(seed: int = 1, n_mat: int = 8, n_ebin: int = 256, emin: float
     return tab
 
 
+def make_scatter_tables(mu_total: np.ndarray, seed: int = 1, emin: float = 20.0, emax: float = 150.0) -> np.ndarray:
+    """Three-channel table (total, Rayleigh, Compton) for a scattering
+    phantom, shape (3, n_mat, n_ebin), 1/cm at the bin centres.  Channel 0
+    is ``mu_total`` unchanged; the synthetic scattering channels are
+    Compton c_m (60/E)^0.3 and Rayleigh r_m (60/E)^2 with c_m = U(0.3, 0.6)
+    and r_m = U(0.02, 0.08) times mu_total(60 keV), scaled down per bin where
+    needed so that Rayleigh + Compton never exceed 0.9 of the total."""
+    rng = np.random.default_rng(seed)
+    n_mat, n_ebin = mu_total.shape
+    centres = emin + (np.arange(n_ebin) + 0.5) * ((emax - emin) / n_ebin)
+    i60 = int(np.argmin(np.abs(centres - 60.0)))
+    out = np.zeros((3, n_mat, n_ebin))
+    out[0] = mu_total
+    for m in range(n_mat):
+        c = rng.uniform(0.3, 0.6) * mu_total[m, i60]
+        r = rng.uniform(0.02, 0.08) * mu_total[m, i60]
+        comp = c * (60.0 / centres) ** 0.3
+        ray = r * (60.0 / centres) ** 2
+        scale = np.minimum(1.0, 0.9 * mu_total[m] / (comp + ray))
+        out[1, m] = ray * scale
+        out[2, m] = comp * scale
+    return out
+
+
 def _random_rotation(rng) -> np.ndarray:
     q = rng.normal(size=4)
     q /= np.linalg.norm(q)
@@ -194,7 +218,7 @@ def edct_half_angle() -> float:
 
 def edct_projection(volume: np.ndarray, mu_table: np.ndarray, angle: float = 0.0,
                     strata: int = 1024, nx: int = EDCT_NX, ny: int = EDCT_NY, ne: int = EDCT_NE,
-                    step: float = None) -> Dict:
+                    step: float = None, scatter_order: int = None, aim: bool = True) -> Dict:
     """Energy-dispersive CT projection: cone-beam point source (Kramers
     continuum (150 - E)/E on 20-150 keV plus lines at 59.3 and 67.2 keV,
     sigma 0.3 keV, 10 % of the photons each), voxel phantom of 1 mm voxels
@@ -202,15 +226,23 @@ def edct_projection(volume: np.ndarray, mu_table: np.ndarray, angle: float = 0.0
     energy-resolving detector of nx x ny pixels of 1.6 mm and ne energy bins
     over [20, 150) keV at 1.2 m.  The cone circumscribes the detector.
     ``step`` (mm): cross the phantom with the fixed-step model instead of the
-    exact path (the paper's default step is a third of the voxel)."""
+    exact path (the paper's default step is a third of the voxel).
+    ``scatter_order`` K >= 1: trace the photons scattered exactly K times in
+    the phantom instead of the uncollided ones; ``mu_table`` must then be
+    the three-channel table of ``make_scatter_tables``; with ``aim`` the last
+    scatter is aimed at the detector rectangle."""
     hx = 0.5 * nx * EDCT_PITCH
     hy = 0.5 * ny * EDCT_PITCH
+    target = None
+    if scatter_order is not None and aim:
+        target = ((0.0, 0.0, EDCT_SDD), (hx, 0.0, 0.0), (0.0, hy, 0.0))
     return {"name": "edct_projection", "components": [
         _c("source_cone_beam", half_angle=math.atan(math.sqrt(hx * hx + hy * hy) / EDCT_SDD),
            emin=20.0, emax=150.0, e0=150.0, f_cont=0.8, e_line1=59.3, f_line1=0.1,
            e_line2=67.2, f_line2=0.1, line_sigma=0.3, strata=strata),
         _c("phantom", pos=(0, 0, EDCT_SOD), rot=rot_y(angle), voxel=1.0, volume=volume,
-           mu_table=mu_table, table_emin=20.0, table_emax=150.0, step=step),
+           mu_table=mu_table, table_emin=20.0, table_emax=150.0, step=step, scatter_order=scatter_order,
+           scatter_target=target),
         _c("detector", pos=(0, 0, EDCT_SDD), xmin=-hx, xmax=hx, ymin=-hy, ymax=hy,
            emin=20.0, emax=150.0, nx=nx, ny=ny, ne=ne),
     ]}
