@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -49,14 +50,15 @@ def parse():
     p.add_argument("--train-hits", type=int, default=10**8, help="learned: detector hits collected for training")
     p.add_argument("--epochs", type=int, default=5, help="learned: training epochs")
     p.add_argument("--eval-rays", type=int, default=16 * 10**8, help="learned: rays per error evaluation (16 replicas)")
-    p.add_argument("--workload", choices=("projection", "batch", "learned", "train", "stepping", "crl"),
+    p.add_argument("--workload", choices=("projection", "batch", "learned", "train", "stepping", "crl", "scatter"),
                    default="projection",
                    help="projection: one 1e9-ray projection of the 256^3 phantom per step; batch: every angle "
                         "of phantoms of uneven size in one captured launch per step, beside one launch per job; "
                         "learned: time to 1%% per-bin error of the plain and the learned-proposal source; "
                         "train: proposal-network training steps; stepping: the same projection with the "
                         "fixed-step phantom model beside the exact path (speed and optical-depth error); "
-                        "crl: the focusing instrument with a 16-lens compound refractive lens")
+                        "crl: the focusing instrument with a 16-lens compound refractive lens; scatter: the "
+                        "projection's once- and twice-scattered images beside the uncollided one")
     p.add_argument("--step", type=float, default=1.0 / 3.0, help="stepping: step length (mm)")
     p.add_argument("--batch-rays", type=int, default=10**8, help="rays per job of the batch")
     p.add_argument("--batch-angles", type=int, default=360)
@@ -72,6 +74,7 @@ KERNEL_SOURCES = ["paper_2410_08747_amd/csrc/mxr.hip", "paper_2410_08747_amd/csr
 PROFILE = "profiles/k_trace_edct_projection_256.md"
 PROFILE_STEP = "profiles/k_trace_edct_step_256.md"
 PROFILE_CRL = "profiles/k_trace_crl_focusing.md"
+PROFILE_SCATTER = "profiles/k_trace_edct_scatter_256.md"
 # FP64 VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # (one add, multiply, divide or square root counted as one operation)
 FP64_OPS_PEAK = 256 * 4 * 16 * 2.4e9
@@ -608,6 +611,86 @@ def crl_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def scatter_bench(args):
+    """The 256^3 projection split by scatter order: the uncollided image
+    (order 0, the plain kernel) and the photons scattered once and twice
+    (forced interactions, the last one aimed at the detector), each over
+    args.rays rays: kernel times, rays/s of the order-1 kernel, and the
+    share of each order in the detected intensity."""
+    import torch
+    import paper_2410_08747_amd as mxr
+    import workloads
+
+    vol = workloads.make_phantom(256, seed=1)
+    mu = workloads.make_mu_tables(1)
+    tab = workloads.make_scatter_tables(mu, 1)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    n = args.rays
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    shared = {}
+    res = {}
+    for order in (0, 1, 2):
+        ins = workloads.edct_projection(vol, tab if order else mu, angle=0.0, strata=STRATA,
+                                        scatter_order=order if order else None)
+        I = mxr.Instrument(ins, dev, shared=shared)
+        tallies = I.new_tallies()
+
+        def zero():
+            for v in tallies[0].values():
+                v.zero_()
+
+        for w in range(args.warmup):
+            zero()
+            I.run(n, seed=100 + w, n_total=n, tallies=tallies, stream=stream)
+        torch.cuda.synchronize()
+        ms = []
+        for k in range(args.steps):
+            zero()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            I.run(n, seed=1, n_total=n, tallies=tallies, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+            print(f"[scatter] order {order} step {k}: {ms[-1]:.1f} ms", file=sys.stderr, flush=True)
+        sw = tallies[0]["sum_w"].sum().item()
+        sw2 = tallies[0]["sum_w2"].sum().item()
+        res[order] = {"kernel_ms": float(np.mean(ms)), "rays_per_s": n / (np.mean(ms) * 1e-3),
+                      "intensity_per_ray": sw / n, "rel_err_total": math.sqrt(max(sw2 - sw * sw / n, 0.0)) / sw,
+                      "detected": int(tallies[0]["count"].sum().item())}
+        del I, tallies
+    total = sum(r["intensity_per_ray"] for r in res.values())
+    for r in res.values():
+        r["share"] = r["intensity_per_ray"] / total
+    visits = visits_per_ray(workloads.edct_projection(vol, mu, angle=0.0, strata=STRATA))
+    # proxy bytes of an order-1 ray: two walks of the primary chord (optical
+    # depth, then the interaction point), one exit walk (counted as a full
+    # chord), one voxel byte per visit, plus the tally
+    bytes_per_ray = 3 * visits + 0.302 * 24
+    achieved = bytes_per_ray * n / (res[1]["kernel_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "rays/s (ED-CT projection, once-scattered photons, forced interaction aimed at the detector)",
+        "value": res[1]["rays_per_s"], "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res[1]["kernel_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "edct_projection_scatter", "n_rays": n, "phantom": "256^3 uint8, 1 mm voxels, seed 1",
+                   "tables": "total/Rayleigh/Compton, seed 1", "detector": "256x64 px x 128 E-bins",
+                   "strata": STRATA, "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(PROFILE_SCATTER)},
+        "orders": {str(k): v for k, v in res.items()},
+        "scatter_to_primary": (res[1]["intensity_per_ray"] + res[2]["intensity_per_ray"]) / res[0]["intensity_per_ray"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -628,6 +711,9 @@ def main():
         return
     if args.workload == "crl":
         crl_bench(args)
+        return
+    if args.workload == "scatter":
+        scatter_bench(args)
         return
     import torch
     import paper_2410_08747_amd as mxr

@@ -98,9 +98,27 @@ typedef enum {
  *   default is a third of the voxel edge): step j covers [a_in + (j-1) h,
  *   min(a_in + j h, a_out)] of the chord and reads the voxel holding
  *   u_in + j h d / v (voxel units, j h d / v + u_in as one fused
- *   multiply-add per axis, clamped into the volume).  Other flag bits are
- *   rejected; MXR_E_UNSUPPORTED when the longest chord needs more than 2^26
- *   steps or ny * nz >= 2^24.
+ *   multiply-add per axis, clamped into the volume).  MXR_E_UNSUPPORTED
+ *   when the longest chord needs more than 2^26 steps or ny * nz >= 2^24.
+ *   flags bit 1: scattering (section 3.3: the sample models absorption and
+ *   scattering): the run traces the photons scattered exactly K = par 4
+ *   (1..3) times in the volume instead of the uncollided ones; the image is
+ *   the sum of the order-0 (plain) and the order-K runs.  data[1] then holds
+ *   three channels, 3 * n_mat * n_ebin doubles (total attenuation, Rayleigh,
+ *   Compton, each material-major; n_ebin = data_len[1] / (3 n_mat)), with
+ *   Rayleigh + Compton <= total expected of the caller.  Each interaction is
+ *   forced on the chord ahead: depth -log(1 - u (1 - e^-tau)), weight times
+ *   1 - e^-tau, the scatter albedo (mu_R + mu_C) / mu_tot, and the angular
+ *   density (Rayleigh: Thomson; Compton: Klein-Nishina for free electrons,
+ *   E' = E / (1 + (E / 510.99895 keV)(1 - cos))) over the sampling density:
+ *   directions uniform on the sphere, or, with flags bit 2, the last
+ *   interaction aimed at a point drawn uniformly on the rectangle with
+ *   centre par 5..7 and half-axes par 8..10, par 11..13 (lab frame; for a
+ *   monitor of that extent).  Four uniforms per interaction.  The ray leaves
+ *   the component at its last interaction point, attenuated along its new
+ *   direction at its new energy; a chord without attenuating or scattering
+ *   material absorbs it.  Bits 0 and 1 exclude each other; bit 2 needs bit
+ *   1; other bits are rejected.
  * MXR_MIRROR_ELLIPTIC -- elliptic-cylinder mirror; local origin at the pole,
  *   z along the incoming axis, y to the reflected side; foci at (0,0,-p)
  *   and q (0, sin 2t0, cos 2t0).  Specular reflection, weight times the

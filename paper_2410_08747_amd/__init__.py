@@ -380,11 +380,19 @@ def _params(c: Dict, s: mxr_component_desc, upload) -> None:
         mu = np.asarray(c["mu_table"], dtype=np.float64)
         s.data[0], s.data_len[0] = upload(vol, np.uint8)
         s.data[1], s.data_len[1] = upload(mu, np.float64)
-        s.dims[0], s.dims[1], s.dims[2], s.dims[3] = nx, ny, nz, mu.shape[0]
+        # a scattering phantom's table has three channels: (3, n_mat, n_ebin)
+        s.dims[0], s.dims[1], s.dims[2], s.dims[3] = nx, ny, nz, mu.shape[1] if mu.ndim == 3 else mu.shape[0]
         p[0], p[1], p[2] = c["voxel"], c["table_emin"], c["table_emax"]
         if c.get("step") is not None:
-            s.flags = 1
+            s.flags |= 1
             p[3] = c["step"]
+        if c.get("scatter_order") is not None:
+            s.flags |= 2
+            p[4] = c["scatter_order"]
+            if c.get("scatter_target") is not None:
+                s.flags |= 4
+                for i, v in enumerate(np.asarray(c["scatter_target"], dtype=np.float64).reshape(9)):
+                    p[5 + i] = v
     elif t == "mirror_elliptic":
         s.data[0], s.data_len[0] = upload(c["reflectivity"], np.float64)
         p[0], p[1], p[2], p[3], p[4], p[5] = c["p"], c["q"], c["theta0"], c["length"], c["width"], c["theta_max"]

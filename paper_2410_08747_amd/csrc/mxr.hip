@@ -43,6 +43,8 @@ constexpr int kPhantomStep = 102;
 // a monitor whose histogram may be accumulated in a work-group private LDS
 // copy (small monitors of the compacting kernel), flushed once per group
 constexpr int kDetectorLds = 103;
+// the phantom component (same descriptor) tracing photons scattered K times
+constexpr int kPhantomScatter = 104;
 
 constexpr bool is_detector(int T) { return T == MXR_DETECTOR || T == kDetectorCollect || T == kDetectorLds; }
 
@@ -127,6 +129,7 @@ __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream 
         if constexpr (T == MXR_SLIT) ok = comp_slit(c, ray);
         if constexpr (T == MXR_BOX) comp_box(c, ray);
         if constexpr (T == MXR_LENS_CRL) ok = comp_lens(c, ray);
+        if constexpr (T == kPhantomScatter) ok = comp_phantom_scatter<EXACT>(c, s, ray, mu_lds, n_mat, n_ebin);
         if constexpr (T == MXR_PHANTOM || T == kPhantomStep) {
             double q[3], dl[3];
             to_local(c, ray, q, dl);
@@ -207,6 +210,7 @@ __device__ __forceinline__ bool apply_dynamic(const DevComp &c, int k, Ray &ray,
         MXR_CASE(MXR_SLIT)
         MXR_CASE(MXR_BOX)
         case MXR_PHANTOM:
+            if (c.flags & 2u) return apply<kPhantomScatter, LEDGER, TRACE, EXACT>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
             if (c.flags & 1u) return apply<kPhantomStep, LEDGER, TRACE, EXACT>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
             return apply<MXR_PHANTOM, LEDGER, TRACE, EXACT>(c, k, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
         MXR_CASE(MXR_MIRROR_ELLIPTIC)
@@ -251,6 +255,12 @@ struct WavesHint<Chain<kSrcConeProposal, MXR_PHANTOM, MXR_DETECTOR>> {
 template <>
 struct WavesHint<Chain<MXR_SRC_CONE_BEAM, kPhantomStep, MXR_DETECTOR>> {
     static constexpr int value = 8;
+};
+// the scattering chain holds three walks: 6 waves (at most 80 VGPRs)
+// measured 17 % faster than its natural 141 VGPRs at 3 waves, and than 4 or 8
+template <>
+struct WavesHint<Chain<MXR_SRC_CONE_BEAM, kPhantomScatter, MXR_DETECTOR>> {
+    static constexpr int value = 6;
 };
 // The batch kernels read their per-job arguments from memory rather than the
 // kernel-argument segment and hold more live values: the projection chain
@@ -673,6 +683,7 @@ using ChainBeamline = Chain<MXR_SRC_GAUSSIAN, MXR_MIRROR_ELLIPTIC, MXR_DCM, MXR_
 using ChainEdctProposal = Chain<kSrcConeProposal, MXR_PHANTOM, MXR_DETECTOR>;
 using ChainEdctCollect = Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, kDetectorCollect>;
 using ChainEdctStep = Chain<MXR_SRC_CONE_BEAM, kPhantomStep, MXR_DETECTOR>;
+using ChainEdctScatter = Chain<MXR_SRC_CONE_BEAM, kPhantomScatter, MXR_DETECTOR>;
 using ChainCrl = Chain<MXR_SRC_GAUSSIAN, MXR_SLIT, MXR_LENS_CRL, MXR_SLIT, MXR_DETECTOR, MXR_DETECTOR>;
 
 // their compacting forms: compaction after the crop aperture (component 1),
@@ -695,6 +706,7 @@ enum Recipe {
     kRecipeBeamline,
     kRecipeEdctStep,
     kRecipeCrl,
+    kRecipeEdctScatter,
     kNumRecipes
 };
 
@@ -731,6 +743,9 @@ KernelFn pick_kernel(int recipe, bool ledger, bool trace, bool exact, int mode) 
         case kRecipeBeamline: return KernelSet<ChainBeamline, true>::get(ledger, trace);
         case kRecipeEdctStep: return KernelSet<ChainEdctStep, true>::get(ledger, trace);
         case kRecipeCrl: return KernelSet<ChainCrl, true>::get(ledger, trace);
+        case kRecipeEdctScatter:
+            return exact ? KernelSet<ChainEdctScatter, true>::get(ledger, trace)
+                         : KernelSet<ChainEdctScatter, false>::get(ledger, trace);
         default:
             return exact ? KernelSet<ChainGeneric, true>::get(ledger, trace)
                          : KernelSet<ChainGeneric, false>::get(ledger, trace);
@@ -777,7 +792,8 @@ int match_recipe(const DevInstr &d) {
         return true;
     };
     if (is({MXR_SRC_RECT_CONE, MXR_SLIT, MXR_BOX, MXR_DETECTOR})) return kRecipeBasic;
-    if (is({MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR})) return (d.c[1].flags & 1u) ? kRecipeEdctStep : kRecipeEdct;
+    if (is({MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR}))
+        return (d.c[1].flags & 2u) ? kRecipeEdctScatter : ((d.c[1].flags & 1u) ? kRecipeEdctStep : kRecipeEdct);
     if (is({MXR_SRC_GAUSSIAN, MXR_MIRROR_ELLIPTIC, MXR_DCM, MXR_POWDER, MXR_DETECTOR})) return kRecipeBeamline;
     if (is({MXR_SRC_GAUSSIAN, MXR_SLIT, MXR_LENS_CRL, MXR_SLIT, MXR_DETECTOR, MXR_DETECTOR})) return kRecipeCrl;
     return kRecipeGeneric;
@@ -809,12 +825,13 @@ bool finite_all(const double *p, int n) {
 
 bool is_source(uint32_t t) { return t == MXR_SRC_RECT_CONE || t == MXR_SRC_CONE_BEAM || t == MXR_SRC_GAUSSIAN; }
 
-int draws_of(uint32_t t) {
-    switch (t) {
+int draws_of(const mxr_component_desc &s) {
+    switch (s.type) {
         case MXR_SRC_RECT_CONE: return 5;
         case MXR_SRC_CONE_BEAM: return 3;
         case MXR_SRC_GAUSSIAN: return 5;
         case MXR_POWDER: return 2;
+        case MXR_PHANTOM: return (s.flags & 2u) ? 4 * (int)s.par[4] : 0;  // four per forced interaction
         default: return 0;
     }
 }
@@ -901,10 +918,25 @@ static mxr_status derive(const mxr_component_desc &s, DevComp &c, int k, uint32_
             if (nvox >= (1ull << 31) || s.dims[0] + s.dims[1] + s.dims[2] > (1u << 20))
                 return fail(MXR_E_UNSUPPORTED, "component %d: volume too large", k);
             if (s.dims[3] < 1 || s.dims[3] > 16) return fail(MXR_E_UNSUPPORTED, "component %d: 1..16 materials", k);
-            if (s.data_len[1] % s.dims[3] != 0 || s.data_len[1] / s.dims[3] < 1 || s.data_len[1] / s.dims[3] > 256)
+            if (s.flags & ~7u) return fail(MXR_E_INVALID, "component %d: unknown phantom flags", k);
+            if ((s.flags & 3u) == 3u || (s.flags & 6u) == 4u)
+                return fail(MXR_E_INVALID, "component %d: phantom flags: scattering excludes the fixed-step model, aiming needs scattering", k);
+            // a scattering phantom's table holds three channels (total, Rayleigh, Compton)
+            const uint64_t per_mat = (s.flags & 2u) ? 3ull * s.dims[3] : (uint64_t)s.dims[3];
+            if (s.data_len[1] % per_mat != 0 || s.data_len[1] / per_mat < 1 || s.data_len[1] / per_mat > 256)
                 return fail(MXR_E_UNSUPPORTED, "component %d: 1..256 energy bins per material", k);
             if (!(p[0] > 0 && p[2] > p[1])) return fail(MXR_E_INVALID, "component %d: bad voxel size or table range", k);
-            if (s.flags & ~1u) return fail(MXR_E_INVALID, "component %d: unknown phantom flags", k);
+            if (s.flags & 2u) {
+                if (!(p[4] >= 1 && p[4] <= 3 && p[4] == std::floor(p[4])))
+                    return fail(MXR_E_INVALID, "component %d: scatter order must be 1, 2 or 3", k);
+                if (s.flags & 4u) {
+                    const double *a = p + 8, *b = p + 11;
+                    const double n0 = a[1] * b[2] - a[2] * b[1], n1 = a[2] * b[0] - a[0] * b[2],
+                                 n2 = a[0] * b[1] - a[1] * b[0];
+                    if (!(n0 * n0 + n1 * n1 + n2 * n2 > 0))
+                        return fail(MXR_E_INVALID, "component %d: degenerate scatter target", k);
+                }
+            }
             if (s.flags & 1u) {
                 // fixed-step model: bound the steps of the longest chord
                 if (!(p[3] > 0)) return fail(MXR_E_INVALID, "component %d: step length must be positive", k);
@@ -918,7 +950,7 @@ static mxr_status derive(const mxr_component_desc &s, DevComp &c, int k, uint32_
                 c.aux[5] = jmax;
             }
             n_mat = s.dims[3];
-            n_ebin = (uint32_t)(s.data_len[1] / s.dims[3]);
+            n_ebin = (uint32_t)(s.data_len[1] / per_mat);
             for (int i = 0; i < 3; ++i) c.aux[i] = -0.5 * ((double)s.dims[i] * p[0]);
             c.aux[3] = (double)n_ebin / (p[2] - p[1]);
             // can the walk step planes by adding v and stay exact?
@@ -1040,7 +1072,7 @@ mxr_status mxr_instrument_create(const mxr_instrument_desc *desc, mxr_instrument
             return st;
         }
         d.c[k].draw0 = draw;
-        draw += draws_of(s.type);
+        draw += draws_of(s);
         if (s.type == MXR_PHANTOM) {
             if (++n_phantom > 1) {
                 delete ins;
@@ -1274,7 +1306,7 @@ mxr_status mxr_collect(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays,
         return fail(MXR_E_UNSUPPORTED, "hit collection needs exactly one monitor, the last component");
     for (uint32_t k = 1; k + 1 < d.ncomp; ++k) {
         const uint32_t t = d.c[k].type;
-        if (t != MXR_SLIT && t != MXR_BOX && t != MXR_PHANTOM)
+        if ((t != MXR_SLIT && t != MXR_BOX && t != MXR_PHANTOM) || (t == MXR_PHANTOM && (d.c[k].flags & 2u)))
             return fail(MXR_E_UNSUPPORTED, "hit collection: component %u changes direction or energy", k);
     }
     for (int i = 0; i < 6; ++i)

@@ -711,6 +711,284 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
     return siddon_walk<EXACT, kWalkRound>(g, S, D, A, B, off, a_in, a_out, mu_row);
 }
 
+// ------------------------------------------------- scattering phantom ----
+// Photons scattered exactly K times in the volume (section 3.3: the voxel
+// sample models absorption and scattering), each interaction forced: on the
+// chord ahead the total optical depth tau is taken by the exact walk, the
+// depth tau* = -log(1 - u1 (1 - e^-tau)) is located by siddon_locate (the
+// same voxel segments, summed one by one until the running depth reaches
+// tau*), and the weight takes 1 - e^-tau, the scatter albedo
+// (mu_R + mu_C) / mu_tot of the voxel's material and the angular factor;
+// Rayleigh (Thomson law, no form factor) is chosen with probability
+// mu_R / (mu_R + mu_C) (u2), Compton (Klein-Nishina, free electrons)
+// otherwise, lowering E to E / (1 + k (1 - cos)).  Directions: uniform on
+// the sphere (cos = 2 u3 - 1, phi = 2 pi u4 about the old direction, frame
+// e1 = d x a / |d x a| with a = y unless |d_y| >= 1/2, then x, e2 = d x e1),
+// weight 4 pi x the density per steradian; or, for the last interaction of
+// an aimed phantom (flags bit 2), towards the point c + (2 u3 - 1) a +
+// (2 u4 - 1) b of a target rectangle, weight = density / (dist^2 /
+// (|n . d| 4 |a x b|)).  After the K-th interaction the walk to the exit
+// attenuates at the final energy.  The total-attenuation channel is read
+// from LDS (mu / 10 per mm, as for the plain phantom), the Rayleigh and
+// Compton channels from the table in global memory at each interaction.
+constexpr double kMeC2Kev = 510.99895;
+
+// Klein-Nishina total cross section over 2 pi r_e^2
+__device__ __forceinline__ double kn_f(double k) {
+    const double l = log1p(2.0 * k);
+    return ((1.0 + k) / (k * k)) * (2.0 * (1.0 + k) / (1.0 + 2.0 * k) - l / k) + l / (2.0 * k) -
+           (1.0 + 3.0 * k) / ((1.0 + 2.0 * k) * (1.0 + 2.0 * k));
+}
+
+// Walk the chord from q along dl voxel by voxel (every plane crossing at
+// alpha = (plane - q) / d with plane = corner + p v, as in the exact walk),
+// summing mu * length segment by segment until the running optical depth
+// reaches tau_star.  Returns true with the interaction distance s and the
+// voxel's material (if rounding leaves tau_star beyond the last attenuating
+// segment: the end of that segment); with tau_star = infinity it walks the
+// whole chord and tau_out is the chord's optical depth.  False if the ray
+// misses the volume.  Bounded by nx + ny + nz + 3 steps.
+__device__ __forceinline__ bool siddon_locate(const PhantomGeo &g, const double q[3], const double dl[3],
+                                              const double *__restrict__ mu_row, double tau_star, double &s_out,
+                                              uint32_t &m_out, double &tau_out) {
+    double inv[3], a_in = 0.0, a_out = kInf;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double lo_p = g.corner[i], hi_p = g.corner[i] + (double)g.n[i] * g.v;
+        if (dl[i] == 0.0) {
+            inv[i] = 0.0;
+            if (!(q[i] > lo_p && q[i] < hi_p)) return false;
+        } else {
+            inv[i] = 1.0 / dl[i];
+            const double a0 = (lo_p - q[i]) * inv[i], a1 = (hi_p - q[i]) * inv[i];
+            const double lo = a0 < a1 ? a0 : a1, hi = a0 < a1 ? a1 : a0;
+            if (lo > a_in) a_in = lo;
+            if (hi < a_out) a_out = hi;
+        }
+    }
+    if (!(a_out > a_in)) return false;
+    int idx[3], p[3], st[3];
+    double na[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int n = g.n[i];
+        const double c = g.corner[i], v = g.v;
+        if (dl[i] == 0.0) {
+            const double f = floor((q[i] - c) / v);
+            idx[i] = (int)fmin(fmax(f, 0.0), (double)(n - 1));
+            p[i] = 0;
+            st[i] = 0;
+            na[i] = kInf;
+            continue;
+        }
+        const double f = ((q[i] + a_in * dl[i]) - c) / v;
+        if (dl[i] > 0.0) {
+            int pp = (int)fmin(fmax(floor(f) + 1.0, 1.0), (double)n);
+            if (pp > 1 && ((c + (double)(pp - 1) * v) - q[i]) * inv[i] > a_in) pp -= 1;
+            if (pp < n && !(((c + (double)pp * v) - q[i]) * inv[i] > a_in)) pp += 1;
+            idx[i] = pp - 1;
+            p[i] = pp;
+            st[i] = 1;
+        } else {
+            int pp = (int)fmin(fmax(ceil(f) - 1.0, 0.0), (double)(n - 1));
+            if (pp < n - 1 && ((c + (double)(pp + 1) * v) - q[i]) * inv[i] > a_in) pp += 1;
+            if (pp > 0 && !(((c + (double)pp * v) - q[i]) * inv[i] > a_in)) pp -= 1;
+            idx[i] = pp;
+            p[i] = pp;
+            st[i] = -1;
+        }
+        na[i] = ((c + (double)p[i] * v) - q[i]) * inv[i];
+    }
+    // per-axis state in scalars (an array indexed by the crossing axis
+    // would live in scratch memory)
+    const int nx = g.n[0], nxy = g.n[0] * g.n[1];
+    int i0 = idx[0], i1 = idx[1], i2 = idx[2];
+    int p0 = p[0], p1 = p[1], p2 = p[2];
+    double n0 = na[0], n1 = na[1], n2 = na[2];
+    double a_prev = a_in, tc = 0.0, last_end = a_in;
+    uint32_t last_m = 0;
+    // the next voxel's load is issued before the current segment is summed
+    // (its index does not depend on the material), hiding its latency
+    uint32_t m = g.vol[i0 + nx * i1 + nxy * i2];
+    const int max_steps = g.n[0] + g.n[1] + g.n[2] + 3;
+    for (int step = 0; step < max_steps; ++step) {
+        const int ax = (n1 < n0) ? ((n2 < n1) ? 2 : 1) : ((n2 < n0) ? 2 : 0);
+        const double nmin = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
+        const double a_next = nmin < a_out ? nmin : a_out;
+        const bool more = nmin < a_out;
+        if (more) {
+            // cross the plane: the next voxel along that axis (clamped)
+            if (ax == 0) {
+                i0 = min(max(i0 + st[0], 0), g.n[0] - 1);
+                p0 += st[0];
+                n0 = ((g.corner[0] + (double)p0 * g.v) - q[0]) * inv[0];
+            } else if (ax == 1) {
+                i1 = min(max(i1 + st[1], 0), g.n[1] - 1);
+                p1 += st[1];
+                n1 = ((g.corner[1] + (double)p1 * g.v) - q[1]) * inv[1];
+            } else {
+                i2 = min(max(i2 + st[2], 0), g.n[2] - 1);
+                p2 += st[2];
+                n2 = ((g.corner[2] + (double)p2 * g.v) - q[2]) * inv[2];
+            }
+        }
+        const uint32_t m_next = g.vol[i0 + nx * i1 + nxy * i2];
+        const double mu = mu_row[m];
+        if (mu > 0.0 && a_next > a_prev) {
+            const double d = mu * (a_next - a_prev);
+            last_m = m;
+            last_end = a_next;
+            if (tc + d >= tau_star) {
+                s_out = a_prev + (tau_star - tc) / mu;
+                m_out = m;
+                tau_out = tc + d;
+                return true;
+            }
+            tc = tc + d;
+        }
+        if (!more) break;
+        m = m_next;
+        a_prev = a_next;
+    }
+    s_out = last_end;
+    m_out = last_m;
+    tau_out = tc;
+    return true;
+}
+
+// The scattering phantom component: par 4 = K; flags bit 2 aims the last
+// interaction at the rectangle par 5..7 (centre), 8..10 and 11..13 (half
+// axes), lab frame.  T: the three-channel table (1/cm) in global memory.
+// The 2K + 1 walks (optical depth ahead, interaction point, ..., exit) run
+// as passes of one loop around a single walk, so that only one walk's
+// registers are live with the scattering state.
+template <bool EXACT>
+__device__ __forceinline__ bool comp_phantom_scatter(const DevComp &c, Stream &s, Ray &ray, const double *mu_lds,
+                                                     uint32_t n_mat, uint32_t n_ebin) {
+    double q[3], dl[3];
+    to_local(c, ray, q, dl);
+    PhantomGeo g;
+    g.vol = (const uint8_t *)c.data0;
+    g.n[0] = (int)c.dims[0];
+    g.n[1] = (int)c.dims[1];
+    g.n[2] = (int)c.dims[2];
+    g.v = c.par[0];
+    g.corner[0] = c.aux[0];
+    g.corner[1] = c.aux[1];
+    g.corner[2] = c.aux[2];
+    g.nvox = (uint32_t)c.n0;
+    const double *__restrict__ T = (const double *)c.data1;
+    const uint32_t plane = n_mat * n_ebin;
+    const int K = (int)c.par[4];
+    const bool aimed = (c.flags & 4u) != 0;
+    double E = ray.E, w = ray.w, tau_star = kInf, pint = 0.0;
+    int e = 0;
+    for (int pass = 0; pass <= 2 * K; ++pass) {
+        const int k = pass >> 1;
+        const bool locate = (pass & 1) != 0;
+        if (!locate) {
+            const double f = floor((E - c.par[1]) * c.aux[3]);
+            e = (int)fmin(fmax(f, 0.0), (double)(n_ebin - 1));
+            tau_star = kInf;
+        }
+        double sint = 0.0, tau = 0.0;
+        uint32_t m = 0;
+        bool inside;
+        if (pass == 0) {
+            // the primary's chord: the coherent rays of a wave take the
+            // event walk of the plain phantom
+            tau = siddon_tau<EXACT>(g, q, dl, mu_lds + e * n_mat);
+            inside = true;
+        } else {
+            inside = siddon_locate(g, q, dl, mu_lds + e * n_mat, tau_star, sint, m, tau);
+        }
+        if (pass == 2 * K) {  // the exit walk
+            ray.E = E;
+            ray.w = w * exp(-(inside ? tau : 0.0));
+            break;
+        }
+        if (!locate) {
+            // optical depth ahead: draw the forced interaction depth
+            if (!inside || !(tau > 0.0)) return false;
+            pint = -expm1(-tau);
+            tau_star = -log1p(-s.u((int)c.draw0 + 4 * k) * pint);
+            continue;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) q[i] = q[i] + sint * dl[i];
+        const double mu_t = T[m * n_ebin + e];
+        const double mu_r = T[plane + m * n_ebin + e];
+        const double mu_c = T[2 * plane + m * n_ebin + e];
+        if (!(mu_r + mu_c > 0.0)) return false;
+        const double albedo = (mu_r + mu_c) / mu_t;
+        const bool rayleigh = s.u((int)c.draw0 + 4 * k + 1) < mu_r / (mu_r + mu_c);
+        double ct = 2.0 * s.u((int)c.draw0 + 4 * k + 2) - 1.0;
+        const double phi = kTwoPi * s.u((int)c.draw0 + 4 * k + 3);
+        double nd[3], dens_ratio = 4.0 * kPi;
+        if (aimed && k == K - 1) {
+            double tw[3], tl[3], ta[3], tb[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) tw[i] = c.par[5 + i] - c.pos[i];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                tl[i] = c.rot[3 * i] * tw[0] + c.rot[3 * i + 1] * tw[1] + c.rot[3 * i + 2] * tw[2];
+                ta[i] = c.rot[3 * i] * c.par[8] + c.rot[3 * i + 1] * c.par[9] + c.rot[3 * i + 2] * c.par[10];
+                tb[i] = c.rot[3 * i] * c.par[11] + c.rot[3 * i + 1] * c.par[12] + c.rot[3 * i + 2] * c.par[13];
+            }
+            const double sa = 2.0 * s.u((int)c.draw0 + 4 * k + 2) - 1.0;
+            const double sb = 2.0 * s.u((int)c.draw0 + 4 * k + 3) - 1.0;
+            double r[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) r[i] = (tl[i] + sa * ta[i] + sb * tb[i]) - q[i];
+            const double dist2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const double dist = sqrt(dist2);
+            const double nrm0 = ta[1] * tb[2] - ta[2] * tb[1], nrm1 = ta[2] * tb[0] - ta[0] * tb[2],
+                         nrm2 = ta[0] * tb[1] - ta[1] * tb[0];
+            const double area4 = sqrt(nrm0 * nrm0 + nrm1 * nrm1 + nrm2 * nrm2);
+            if (!(dist > 0.0) || !(area4 > 0.0)) return false;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) nd[i] = r[i] / dist;
+            const double cosn = fabs(nd[0] * nrm0 + nd[1] * nrm1 + nd[2] * nrm2) / area4;
+            if (!(cosn > 0.0)) return false;
+            dens_ratio = (cosn * 4.0 * area4) / dist2;
+            ct = dl[0] * nd[0] + dl[1] * nd[1] + dl[2] * nd[2];
+        } else {
+            double a0 = 0.0, a1 = 1.0;
+            if (!(fabs(dl[1]) < 0.5)) {
+                a0 = 1.0;
+                a1 = 0.0;
+            }
+            // e1 = d x a with a = (a0, a1, 0)
+            double e1[3] = {dl[1] * 0.0 - dl[2] * a1, dl[2] * a0 - dl[0] * 0.0, dl[0] * a1 - dl[1] * a0};
+            const double n1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) e1[i] = e1[i] / n1;
+            const double e2[3] = {dl[1] * e1[2] - dl[2] * e1[1], dl[2] * e1[0] - dl[0] * e1[2],
+                                  dl[0] * e1[1] - dl[1] * e1[0]};
+            const double sn = sqrt(1.0 - ct * ct);
+            double sp, cp;
+            sincos(phi, &sp, &cp);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) nd[i] = ct * dl[i] + sn * (cp * e1[i] + sp * e2[i]);
+        }
+        const double st2 = 1.0 - ct * ct;
+        double dens;
+        if (rayleigh) {
+            dens = 3.0 * (1.0 + ct * ct) / (16.0 * kPi);
+        } else {
+            const double kk = E / kMeC2Kev;
+            const double rho = 1.0 / (1.0 + kk * (1.0 - ct));
+            dens = rho * rho * (rho + 1.0 / rho - st2) / (4.0 * kPi * kn_f(kk));
+            E = rho * E;
+        }
+        w = w * (pint * albedo * (dens * dens_ratio));
+#pragma unroll
+        for (int i = 0; i < 3; ++i) dl[i] = nd[i];
+    }
+    to_lab(c, q, dl, ray);
+    return true;
+}
+
 // ---------------------------------------------------- fixed-step model ----
 // The paper's own way through the voxel sample (section 3.3): fixed steps of
 // length h, each reading the voxel that holds its end position and
