@@ -50,7 +50,8 @@ def parse():
     p.add_argument("--train-hits", type=int, default=10**8, help="learned: detector hits collected for training")
     p.add_argument("--epochs", type=int, default=5, help="learned: training epochs")
     p.add_argument("--eval-rays", type=int, default=16 * 10**8, help="learned: rays per error evaluation (16 replicas)")
-    p.add_argument("--workload", choices=("projection", "batch", "learned", "train", "stepping", "crl", "scatter"),
+    p.add_argument("--workload", choices=("projection", "batch", "learned", "train", "stepping", "crl", "scatter",
+                                          "peaks"),
                    default="projection",
                    help="projection: one 1e9-ray projection of the 256^3 phantom per step; batch: every angle "
                         "of phantoms of uneven size in one captured launch per step, beside one launch per job; "
@@ -58,7 +59,8 @@ def parse():
                         "train: proposal-network training steps; stepping: the same projection with the "
                         "fixed-step phantom model beside the exact path (speed and optical-depth error); "
                         "crl: the focusing instrument with a 16-lens compound refractive lens; scatter: the "
-                        "projection's once- and twice-scattered images beside the uncollided one")
+                        "projection's once- and twice-scattered images beside the uncollided one; peaks: the "
+                        "measured FP64 FMA, multiply-high, exp, HBM read and FP64 atomic rates")
     p.add_argument("--step", type=float, default=1.0 / 3.0, help="stepping: step length (mm)")
     p.add_argument("--batch-rays", type=int, default=10**8, help="rays per job of the batch")
     p.add_argument("--batch-angles", type=int, default=360)
@@ -691,6 +693,53 @@ def scatter_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def peaks_bench(args):
+    """Measured achievable rates beside the vendor figures: FP64 FMA issue,
+    32-bit multiply-high, FP64 exp, an HBM read stream (4 GiB), and FP64
+    atomic adds against the number of distinct target addresses."""
+    import torch
+    import paper_2410_08747_amd as mxr
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    groups = 256 * 32  # 32 work-groups of 256 lanes per CU
+
+    def timed(kind, buf, spread=1, iters=1, g=groups, reps=3):
+        best = None
+        for r in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            work = mxr.mxr_peak_launch(kind, buf.data_ptr(), buf.numel() * buf.element_size(), spread, iters, g,
+                                       stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if r > 0:  # the first launch warms up
+                t = a.elapsed_time(b) * 1e-3
+                best = t if best is None else min(best, t)
+        return work / best
+
+    sink = torch.zeros(groups * 256, dtype=torch.float64, device=dev)
+    out = {"fp64_fma_tflops": timed("fp64_fma", sink, iters=4096) / 1e12,
+           "u32_mulhi_tops": timed("u32_mulhi", sink, iters=4096) / 1e12,
+           "fp64_exp_gops": timed("fp64_exp", sink, iters=256) / 1e9}
+    big = torch.ones(1 << 29, dtype=torch.float64, device=dev)  # 4 GiB
+    out["hbm_read_gbs"] = timed("read", big, g=256 * 64) / 1e9
+    del big
+    atom = torch.zeros(1 << 21, dtype=torch.float64, device=dev)
+    out["fp64_atomic_gops_by_spread"] = {str(sp): timed("atomic_f64", atom, spread=sp, iters=64, g=256 * 16) / 1e9
+                                         for sp in (1, 130, 14400, 1 << 21)}
+    vendor = {"fp64_fma_tflops": 78.6, "hbm_read_gbs": 8000.0}
+    line = {"metric": "measured MI355X rates (FP64 FMA, u32 mul-hi, FP64 exp, HBM read, FP64 atomics)",
+            "value": out["fp64_fma_tflops"], "unit": "TFLOP/s (FP64 FMA)", "n_gpus": 1, "steps": 3, "warmup": 1,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "micro-benchmarks", "groups": groups, "parallelism": "none (1 GPU)"},
+            "measured": out, "vendor": vendor,
+            "fraction_of_vendor": {"fp64_fma": out["fp64_fma_tflops"] / vendor["fp64_fma_tflops"],
+                                   "hbm_read": out["hbm_read_gbs"] / vendor["hbm_read_gbs"]}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -714,6 +763,9 @@ def main():
         return
     if args.workload == "scatter":
         scatter_bench(args)
+        return
+    if args.workload == "peaks":
+        peaks_bench(args)
         return
     import torch
     import paper_2410_08747_amd as mxr

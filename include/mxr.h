@@ -516,6 +516,36 @@ void mxr_batch_destroy(mxr_batch *batch);
 mxr_status mxr_batch_autotune(mxr_batch *batch, double rays_fraction, const char *cache_path,
                               mxr_batch_schedule *out);
 
+/* ------------------------------------------------------------------------
+ * Micro-benchmarks: the achievable rates that bound the tracing kernels, for
+ * roofline denominators measured on the device beside the vendor figures.
+ * Not part of tracing.  One launch of groups x 256 lanes on hip_stream
+ * (asynchronous; the caller times it with events on that stream); *work
+ * receives the operations (bytes for the read) the launch performs.
+ *   MXR_PEAK_FP64_FMA  -- iters x 8 independent FP64 fma chains per lane;
+ *                         *work = flops (2 per fma).  buf: one double per
+ *                         lane (sink).
+ *   MXR_PEAK_U32_MULHI -- iters x 8 chains of 32-bit multiply-high (the
+ *                         Philox rounds' product); *work = multiplies.
+ *   MXR_PEAK_FP64_EXP  -- iters x 4 chains of FP64 exp; *work = exps.
+ *   MXR_PEAK_READ      -- a grid-stride read of the buffer beyond the first
+ *                         groups x 256 doubles (the sink), in 16-byte
+ *                         elements; *work = bytes read.
+ *   MXR_PEAK_ATOMIC_F64 -- every lane adds 1.0 iters times into buf[0 ..
+ *                         spread) (addresses hashed per lane, consecutive
+ *                         per iteration); *work = atomics.  The buffer then
+ *                         holds the counts (sum = *work).
+ * buf: device buffer of bytes bytes.  Errors: MXR_E_INVALID (null
+ * pointers, groups not in [1, 2^20], iters not in [1, 2^32], a buffer too
+ * small, spread not in [1, bytes / 8], unknown kind), MXR_E_HIP. */
+#define MXR_PEAK_FP64_FMA 0u
+#define MXR_PEAK_U32_MULHI 1u
+#define MXR_PEAK_FP64_EXP 2u
+#define MXR_PEAK_READ 3u
+#define MXR_PEAK_ATOMIC_F64 4u
+mxr_status mxr_peak_launch(uint32_t kind, void *buf, uint64_t bytes, uint64_t spread, uint64_t iters, uint32_t groups,
+                           double *work, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

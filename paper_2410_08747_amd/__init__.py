@@ -132,6 +132,9 @@ def _load() -> ctypes.CDLL:
     # one of them then finds no device.
     import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
+    lib.mxr_peak_launch.argtypes = [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
+    lib.mxr_peak_launch.restype = ctypes.c_int
     lib.mxr_abi_version.restype = ctypes.c_uint32
     lib.mxr_last_error.restype = ctypes.c_char_p
     lib.mxr_instrument_create.argtypes = [ctypes.POINTER(mxr_instrument_desc), ctypes.POINTER(ctypes.c_void_p)]
@@ -347,6 +350,18 @@ def mxr_batch_autotune(handle: int, rays_fraction: float, cache_path: Optional[s
     _check(lib.mxr_batch_autotune(handle, rays_fraction, cache_path.encode() if cache_path else None,
                                   ctypes.byref(out)))
     return out
+
+
+PEAK_KINDS = {"fp64_fma": 0, "u32_mulhi": 1, "fp64_exp": 2, "read": 3, "atomic_f64": 4}
+
+
+def mxr_peak_launch(kind: str, buf_ptr: int, nbytes: int, spread: int, iters: int, groups: int, stream=None) -> float:
+    """Launch one micro-benchmark kernel; returns the operations (bytes for
+    the read) it performs."""
+    work = ctypes.c_double(0.0)
+    _check(lib.mxr_peak_launch(PEAK_KINDS[kind], ctypes.c_void_p(buf_ptr), nbytes, spread, iters, groups,
+                               ctypes.byref(work), _stream_handle(stream)))
+    return work.value
 
 
 # ------------------------------------------------------------ marshalling --

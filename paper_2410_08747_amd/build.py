@@ -7,7 +7,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SOURCES = [os.path.join(PKG, "csrc", n) for n in ("mxr.hip", "mlp.hip", "stats.hip")]
+SOURCES = [os.path.join(PKG, "csrc", n) for n in ("mxr.hip", "mlp.hip", "stats.hip", "peaks.hip")]
 HEADERS = [os.path.join(ROOT, "include", "mxr.h"), os.path.join(PKG, "csrc", "mxr_device.h")]
 LIB = os.path.join(PKG, "libmxr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
