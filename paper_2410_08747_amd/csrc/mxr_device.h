@@ -548,10 +548,25 @@ struct AxisSet {
 // runs in order.  Events past the exit carry t = a_out and keep stepping D:
 // their voxels (read through the range-checked buffer) can only open
 // zero-length runs, which add nothing.
-template <bool EXACT, int K>
+//
+// LOCATE: also find where the running optical depth reaches tau_star.  Within
+// a material run mu is constant, so the point is checked when a run closes:
+// a_start + (tau_star - tau_before) / mu in the first attenuating run whose
+// closing depth reaches tau_star (hit.found); hit.last_end / last_m keep the
+// end and material of the last attenuating run for a tau_star that rounding
+// leaves beyond the total.  A wave leaves the walk once every lane has found
+// its point or passed its exit.
+struct WalkHit {
+    double s = 0.0, last_end = 0.0;
+    uint32_t m = 0, last_m = 0;
+    bool found = false;
+};
+
+template <bool EXACT, int K, bool LOCATE = false>
 __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet &S, int D, int A, int B,
                                               uint32_t off, double a_in, double a_out,
-                                              const double *__restrict__ mu_row) {
+                                              const double *__restrict__ mu_row, double tau_star = 0.0,
+                                              WalkHit *hit = nullptr) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)g.vol, (short)0, (int)g.nvox, 0x00020000);
     const double v = g.v;
     double PD = pick3(D, S.P[0], S.P[1], S.P[2]), PA = pick3(A, S.P[0], S.P[1], S.P[2]);
@@ -612,23 +627,58 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
             const bool change = m[j] != run_m;
             if (__builtin_amdgcn_ballot_w64(change) != 0) {
                 if (change) {
-                    tau = fma(mu_row[run_m], t[j] - a_start, tau);
+                    if constexpr (LOCATE) {
+                        const double mu = mu_row[run_m];
+                        const double closed = fma(mu, t[j] - a_start, tau);
+                        if (mu > 0.0 && t[j] > a_start) {
+                            if (!hit->found && closed >= tau_star) {
+                                hit->found = true;
+                                hit->s = a_start + (tau_star - tau) / mu;
+                                hit->m = run_m;
+                            }
+                            hit->last_end = t[j];
+                            hit->last_m = run_m;
+                        }
+                        tau = closed;
+                    } else {
+                        tau = fma(mu_row[run_m], t[j] - a_start, tau);
+                    }
                     a_start = t[j];
                     run_m = m[j];
                 }
             }
         }
         // every lane is past its exit once its last event sits at a_out
-        if (__builtin_amdgcn_ballot_w64(t[K - 1] < a_out) == 0) break;
+        if constexpr (LOCATE) {
+            if (__builtin_amdgcn_ballot_w64(t[K - 1] < a_out && !hit->found) == 0) break;
+        } else {
+            if (__builtin_amdgcn_ballot_w64(t[K - 1] < a_out) == 0) break;
+        }
     }
-    return fma(mu_row[run_m], a_out - a_start, tau);
+    if constexpr (LOCATE) {
+        const double mu = mu_row[run_m];
+        const double closed = fma(mu, a_out - a_start, tau);
+        if (mu > 0.0 && a_out > a_start) {
+            if (!hit->found && closed >= tau_star) {
+                hit->found = true;
+                hit->s = a_start + (tau_star - tau) / mu;
+                hit->m = run_m;
+            }
+            hit->last_end = a_out;
+            hit->last_m = run_m;
+        }
+        return closed;
+    } else {
+        return fma(mu_row[run_m], a_out - a_start, tau);
+    }
 }
 
 // EXACT: every plane coordinate corner + i v is reached exactly by adding v
 // (true for dyadic voxel sizes such as 1 mm); decided once per instrument.
-template <bool EXACT>
+template <bool EXACT, bool LOCATE = false>
 __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q[3], const double dl[3],
-                                             const double *__restrict__ mu_row) {
+                                             const double *__restrict__ mu_row, double tau_star = 0.0,
+                                             WalkHit *hit = nullptr) {
     double inv[3];
     double a_in = 0.0, a_out = kInf;
 #pragma unroll
@@ -708,16 +758,17 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
     else if (ay >= az) { D = 1; A = 0; B = 2; }
     else { D = 2; A = 0; B = 1; }
     const uint32_t off = (uint32_t)(idx[0] + nx * idx[1] + nxy * idx[2]);
-    return siddon_walk<EXACT, kWalkRound>(g, S, D, A, B, off, a_in, a_out, mu_row);
+    return siddon_walk<EXACT, kWalkRound, LOCATE>(g, S, D, A, B, off, a_in, a_out, mu_row, tau_star, hit);
 }
 
 // ------------------------------------------------- scattering phantom ----
 // Photons scattered exactly K times in the volume (section 3.3: the voxel
 // sample models absorption and scattering), each interaction forced: on the
 // chord ahead the total optical depth tau is taken by the exact walk, the
-// depth tau* = -log(1 - u1 (1 - e^-tau)) is located by siddon_locate (the
-// same voxel segments, summed one by one until the running depth reaches
-// tau*), and the weight takes 1 - e^-tau, the scatter albedo
+// depth tau* = -log(1 - u1 (1 - e^-tau)) is located by the same walk (in
+// the material run where the running depth reaches tau*, at
+// a_start + (tau* - tau_before) / mu), and the weight takes 1 - e^-tau,
+// the scatter albedo
 // (mu_R + mu_C) / mu_tot of the voxel's material and the angular factor;
 // Rayleigh (Thomson law, no form factor) is chosen with probability
 // mu_R / (mu_R + mu_C) (u2), Compton (Klein-Nishina, free electrons)
@@ -860,8 +911,9 @@ __device__ __forceinline__ bool siddon_locate(const PhantomGeo &g, const double 
 // interaction at the rectangle par 5..7 (centre), 8..10 and 11..13 (half
 // axes), lab frame.  T: the three-channel table (1/cm) in global memory.
 // The 2K + 1 walks (optical depth ahead, interaction point, ..., exit) run
-// as passes of one loop around a single walk, so that only one walk's
-// registers are live with the scattering state.
+// as passes of one loop: the event walk in locate mode (tau_star infinite for
+// the depth and exit passes) for the coherent chords, the voxel-by-voxel
+// walk for the chords after an isotropic scatter.
 template <bool EXACT>
 __device__ __forceinline__ bool comp_phantom_scatter(const DevComp &c, Stream &s, Ray &ray, const double *mu_lds,
                                                      uint32_t n_mat, uint32_t n_ebin) {
@@ -891,29 +943,39 @@ __device__ __forceinline__ bool comp_phantom_scatter(const DevComp &c, Stream &s
             e = (int)fmin(fmax(f, 0.0), (double)(n_ebin - 1));
             tau_star = kInf;
         }
-        double sint = 0.0, tau = 0.0;
-        uint32_t m = 0;
-        bool inside;
-        if (pass == 0) {
-            // the primary's chord: the coherent rays of a wave take the
-            // event walk of the plain phantom
-            tau = siddon_tau<EXACT>(g, q, dl, mu_lds + e * n_mat);
-            inside = true;
+        // chords along the primary or towards the target are coherent
+        // across a wave and take the event walk; chords after an isotropic
+        // scatter go voxel by voxel
+        const bool coherent = k == 0 || (k == K && aimed);
+        WalkHit hit;
+        double tau = 0.0;
+        if (coherent) {
+            tau = siddon_tau<EXACT, true>(g, q, dl, mu_lds + e * n_mat, tau_star, &hit);
         } else {
-            inside = siddon_locate(g, q, dl, mu_lds + e * n_mat, tau_star, sint, m, tau);
+            double sl = 0.0;
+            uint32_t ml = 0;
+            if (siddon_locate(g, q, dl, mu_lds + e * n_mat, tau_star, sl, ml, tau)) {
+                hit.found = sl >= 0.0 && tau_star < kInf;
+                hit.s = sl;
+                hit.m = ml;
+                hit.last_end = sl;
+                hit.last_m = ml;
+            }
         }
         if (pass == 2 * K) {  // the exit walk
             ray.E = E;
-            ray.w = w * exp(-(inside ? tau : 0.0));
+            ray.w = w * exp(-tau);
             break;
         }
         if (!locate) {
             // optical depth ahead: draw the forced interaction depth
-            if (!inside || !(tau > 0.0)) return false;
+            if (!(tau > 0.0)) return false;
             pint = -expm1(-tau);
             tau_star = -log1p(-s.u((int)c.draw0 + 4 * k) * pint);
             continue;
         }
+        const double sint = hit.found ? hit.s : hit.last_end;
+        const uint32_t m = hit.found ? hit.m : hit.last_m;
 #pragma unroll
         for (int i = 0; i < 3; ++i) q[i] = q[i] + sint * dl[i];
         const double mu_t = T[m * n_ebin + e];
