@@ -49,6 +49,7 @@ def parse():
     p.add_argument("--cpu-sample", type=int, default=4_000_000)
     p.add_argument("--train-hits", type=int, default=10**8, help="learned: detector hits collected for training")
     p.add_argument("--epochs", type=int, default=5, help="learned: training epochs")
+    p.add_argument("--alpha", type=float, default=0.1, help="learned: share of the plain source in the proposal")
     p.add_argument("--eval-rays", type=int, default=16 * 10**8, help="learned: rays per error evaluation (16 replicas)")
     p.add_argument("--workload", choices=("projection", "batch", "learned", "train", "stepping", "crl", "scatter",
                                           "peaks"),
@@ -357,7 +358,7 @@ def time_to_1pct(args):
         ti = time.perf_counter()
         out = net.forward(torch.tensor(workloads.projection_context(ang, 256)[None, :], device=dev))
         gmm = net.mixture(out, lo, hi)
-        I.set_proposal(gmm[0], alpha=0.1)
+        I.set_proposal(gmm[0], alpha=args.alpha)
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - ti
         ml, rl, tl, n_l = replicas(I, args.eval_rays)
@@ -381,7 +382,7 @@ def time_to_1pct(args):
         del I
     return {
         "replicas": R, "eval_rays": args.eval_rays, "train_hits": n_rows, "train_rays": emitted,
-        "train_angles": len(train_angles), "epochs": args.epochs, "alpha": 0.1,
+        "train_angles": len(train_angles), "epochs": args.epochs, "alpha": args.alpha,
         "learn_s": t_learn, "collect_s": t_collect, "train_s": t_train,
         "loss_first": float(ll[:10].mean()), "loss_last": float(ll[-10:].mean()),
         **results,
