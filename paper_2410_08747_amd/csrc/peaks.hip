@@ -134,7 +134,7 @@ extern "C" mxr_status mxr_peak_launch(uint32_t kind, void *buf, uint64_t bytes, 
             break;
         }
         case MXR_PEAK_ATOMIC_F64:
-            if (spread < 1 || spread * sizeof(double) > bytes)
+            if (spread < 1 || spread > bytes / sizeof(double))
                 return mxr_host::set_error(MXR_E_INVALID, "spread must be in [1, bytes / 8]");
             hipLaunchKernelGGL(k_peak_atomic, dim3(groups), dim3(kPeakBlock), 0, st, (double *)buf, spread, iters);
             *work = (double)iters * (double)lanes;
