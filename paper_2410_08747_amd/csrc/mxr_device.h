@@ -543,9 +543,15 @@ struct AxisSet {
 // B), clipped to a_out; its alpha is computed from the plane index, so it is
 // the same number the merged order of all crossings would see.  When no lane
 // of the wave has an A or B crossing next, the event is a D step for the
-// whole wave (the common case); otherwise the lanes branch.  The K voxel
-// loads of a round are issued together and then folded into the material
-// runs in order.  Events past the exit carry t = a_out and keep stepping D:
+// whole wave (the common case).  Otherwise every lane steps one axis without
+// branching: each axis's plane advances by a factor of 1 or 0 times v (an
+// exact fma), and all three alphas are recomputed from their planes, which
+// leaves the two unchanged ones bit for bit as they were.  Divergent
+// branches would execute all three updates anyway, plus the register copies
+// their joins need.  An axis the ray runs parallel to is given a plane
+// ahead of the ray and an infinite reciprocal, so its recomputed alpha stays
+// +inf.  The K voxel loads of a round are issued together and then folded
+// into the material runs in order.  Events past the exit carry t = a_out and keep stepping D:
 // their voxels (read through the range-checked buffer) can only open
 // zero-length runs, which add nothing.
 //
@@ -573,18 +579,28 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
     double PB = pick3(B, S.P[0], S.P[1], S.P[2]);
     const double qD = pick3(D, S.q[0], S.q[1], S.q[2]), qA = pick3(A, S.q[0], S.q[1], S.q[2]);
     const double qB = pick3(B, S.q[0], S.q[1], S.q[2]);
-    const double iD = pick3(D, S.inv[0], S.inv[1], S.inv[2]), iA = pick3(A, S.inv[0], S.inv[1], S.inv[2]);
-    const double iB = pick3(B, S.inv[0], S.inv[1], S.inv[2]);
+    const double iD = pick3(D, S.inv[0], S.inv[1], S.inv[2]);
+    double iA = pick3(A, S.inv[0], S.inv[1], S.inv[2]), iB = pick3(B, S.inv[0], S.inv[1], S.inv[2]);
     int kD = pick3(D, S.k[0], S.k[1], S.k[2]), kA = pick3(A, S.k[0], S.k[1], S.k[2]);
     int kB = pick3(B, S.k[0], S.k[1], S.k[2]);
     const int oD = pick3(D, S.doff[0], S.doff[1], S.doff[2]), oA = pick3(A, S.doff[0], S.doff[1], S.doff[2]);
     const int oB = pick3(B, S.doff[0], S.doff[1], S.doff[2]);
     // plane k of a mirrored axis sits at -corner + k v
-    const double cD = pick3(D, S.c[0], S.c[1], S.c[2]), cA = pick3(A, S.c[0], S.c[1], S.c[2]);
-    const double cB = pick3(B, S.c[0], S.c[1], S.c[2]);
+    const double cD = pick3(D, S.c[0], S.c[1], S.c[2]);
+    double cA = pick3(A, S.c[0], S.c[1], S.c[2]), cB = pick3(B, S.c[0], S.c[1], S.c[2]);
     double aD = (PD - qD) * iD;
     double aA = (iA == 0.0) ? kInf : (PA - qA) * iA;
     double aB = (iB == 0.0) ? kInf : (PB - qB) * iB;
+    if (iA == 0.0) {
+        PA = cA = qA + 1.0;
+        kA = 0;
+        iA = kInf;
+    }
+    if (iB == 0.0) {
+        PB = cB = qB + 1.0;
+        kB = 0;
+        iB = kInf;
+    }
 
     uint32_t run_m = load_voxel(rs, off);
     double a_start = a_in, tau = 0.0;
@@ -601,21 +617,27 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
                 off += (uint32_t)oD;
                 PD = EXACT ? PD + v : cD + (double)(++kD) * v;
                 aD = (PD - qD) * iD;
-            } else if (secA && aA <= aB) {
-                t[j] = aA;
-                off += (uint32_t)oA;
-                PA = EXACT ? PA + v : cA + (double)(++kA) * v;
-                aA = (PA - qA) * iA;
-            } else if (secB) {
-                t[j] = aB;
-                off += (uint32_t)oB;
-                PB = EXACT ? PB + v : cB + (double)(++kB) * v;
-                aB = (PB - qB) * iB;
             } else {
-                t[j] = lim;
-                off += (uint32_t)oD;
-                PD = EXACT ? PD + v : cD + (double)(++kD) * v;
+                const bool tA = secA && aA <= aB;
+                const bool tB = secB && !tA;
+                const bool tD = !(tA || tB);
+                t[j] = tA ? aA : (tB ? aB : lim);
+                off += (uint32_t)(tA ? oA : (tB ? oB : oD));
+                if constexpr (EXACT) {
+                    PD = fma(tD ? 1.0 : 0.0, v, PD);
+                    PA = fma(tA ? 1.0 : 0.0, v, PA);
+                    PB = fma(tB ? 1.0 : 0.0, v, PB);
+                } else {
+                    kD += tD;
+                    kA += tA;
+                    kB += tB;
+                    PD = cD + (double)kD * v;
+                    PA = cA + (double)kA * v;
+                    PB = cB + (double)kB * v;
+                }
                 aD = (PD - qD) * iD;
+                aA = (PA - qA) * iA;
+                aB = (PB - qB) * iB;
             }
             o[j] = off;
         }
@@ -624,28 +646,27 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
         for (int j = 0; j < K; ++j) m[j] = load_voxel(rs, o[j]);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const bool change = m[j] != run_m;
-            if (__builtin_amdgcn_ballot_w64(change) != 0) {
-                if (change) {
-                    if constexpr (LOCATE) {
-                        const double mu = mu_row[run_m];
-                        const double closed = fma(mu, t[j] - a_start, tau);
-                        if (mu > 0.0 && t[j] > a_start) {
-                            if (!hit->found && closed >= tau_star) {
-                                hit->found = true;
-                                hit->s = a_start + (tau_star - tau) / mu;
-                                hit->m = run_m;
-                            }
-                            hit->last_end = t[j];
-                            hit->last_m = run_m;
+            // a material change closes the run (a wave with no change skips
+            // the block on its empty execution mask)
+            if (m[j] != run_m) {
+                if constexpr (LOCATE) {
+                    const double mu = mu_row[run_m];
+                    const double closed = fma(mu, t[j] - a_start, tau);
+                    if (mu > 0.0 && t[j] > a_start) {
+                        if (!hit->found && closed >= tau_star) {
+                            hit->found = true;
+                            hit->s = a_start + (tau_star - tau) / mu;
+                            hit->m = run_m;
                         }
-                        tau = closed;
-                    } else {
-                        tau = fma(mu_row[run_m], t[j] - a_start, tau);
+                        hit->last_end = t[j];
+                        hit->last_m = run_m;
                     }
-                    a_start = t[j];
-                    run_m = m[j];
+                    tau = closed;
+                } else {
+                    tau = fma(mu_row[run_m], t[j] - a_start, tau);
                 }
+                a_start = t[j];
+                run_m = m[j];
             }
         }
         // every lane is past its exit once its last event sits at a_out
