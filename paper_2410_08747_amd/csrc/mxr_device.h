@@ -538,6 +538,17 @@ struct AxisSet {
     int k[3], doff[3];
 };
 
+// Minimum of two doubles that are never NaN, as the one VALU instruction
+// v_min_f64.  The ternary a < b ? a : b compiles to a compare and two
+// selects, and fmin() adds canonicalising instructions for operands the
+// compiler cannot prove canonical; the walk's alphas are finite or +inf and
+// positive, so a tie returns the same number either way.
+__device__ __forceinline__ double min_f64(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // The walk in rounds of K crossings ("events").  Each event is the nearest
 // of the next D, A and B crossings (D first on ties with the others, A before
 // B), clipped to a_out; its alpha is computed from the plane index, so it is
@@ -610,7 +621,7 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
         double t[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const double lim = aD < a_out ? aD : a_out;
+            const double lim = min_f64(aD, a_out);
             const bool secA = aA < lim, secB = aB < lim;
             if (__builtin_amdgcn_ballot_w64(secA || secB) == 0) {
                 t[j] = lim;
@@ -621,7 +632,7 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
                 const bool tA = secA && aA <= aB;
                 const bool tB = secB && !tA;
                 const bool tD = !(tA || tB);
-                t[j] = tA ? aA : (tB ? aB : lim);
+                t[j] = min_f64(lim, min_f64(aA, aB));  // the stepped axis's alpha
                 off += (uint32_t)(tA ? oA : (tB ? oB : oD));
                 if constexpr (EXACT) {
                     PD = fma(tD ? 1.0 : 0.0, v, PD);
