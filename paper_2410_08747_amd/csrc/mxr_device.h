@@ -1096,6 +1096,22 @@ __device__ __forceinline__ bool comp_phantom_scatter(const DevComp &c, Stream &s
 // loop; a voxel index is clamped per axis, so every load is in range.
 constexpr int kStepRound = 4;
 
+// clamp(x, 0, hi) for hi >= 0 as one v_med3_i32, and a * b + c on the low
+// 24 bits of a and b as one full-rate v_mad_u32_u24.  Written out because
+// the compiler emits max + min for the first and folds the second into a
+// 64-bit multiply-add.  hi and a are wave-uniform here (the phantom's
+// dimensions) and stay in scalar registers.
+__device__ __forceinline__ int clamp0_i32(int x, int hi) {
+    int r;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
+    return r;
+}
+__device__ __forceinline__ uint32_t mad_u24(int a, int b, int c) {
+    uint32_t r;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "s"(a), "v"(b), "v"(c));
+    return r;
+}
+
 __device__ __forceinline__ double step_tau(const PhantomGeo &g, const double q[3], const double dl[3], double h,
                                            int jmax, const double *__restrict__ mu_row) {
     double a_in = 0.0, a_out = kInf;
@@ -1137,10 +1153,10 @@ __device__ __forceinline__ double step_tau(const PhantomGeo &g, const double q[3
         int ix = (int)fma(dj, du[0], u0[0]);
         int iy = (int)fma(dj, du[1], u0[1]);
         int iz = (int)fma(dj, du[2], u0[2]);
-        ix = min(max(ix, 0), nx - 1);
-        iy = min(max(iy, 0), ny - 1);
-        iz = min(max(iz, 0), nz - 1);
-        return __umul24((uint32_t)nx, __umul24((uint32_t)ny, (uint32_t)iz) + (uint32_t)iy) + (uint32_t)ix;
+        ix = clamp0_i32(ix, nx - 1);
+        iy = clamp0_i32(iy, ny - 1);
+        iz = clamp0_i32(iz, nz - 1);
+        return mad_u24(nx, mad_u24(ny, iz, iy), ix);
     };
     uint32_t run_m = load_voxel(rs, voxel_of(1));
     double a_start = a_in, tau = 0.0;
@@ -1158,7 +1174,7 @@ __device__ __forceinline__ double step_tau(const PhantomGeo &g, const double q[3
             // term would and adds zero-length runs after it, so no per-step
             // j <= J test is needed
             if (m[k] != run_m) {
-                const double a = fmin(a_in + (double)(j0 + k - 1) * h, a_out);
+                const double a = min_f64(a_in + (double)(j0 + k - 1) * h, a_out);
                 tau = fma(mu_row[run_m], a - a_start, tau);
                 a_start = a;
                 run_m = m[k];
