@@ -549,6 +549,22 @@ __device__ __forceinline__ double min_f64(double a, double b) {
     return r;
 }
 
+// clamp(x, 0, hi) for hi >= 0 as one v_med3_i32, and a * b + c on the low
+// 24 bits of a and b as one full-rate v_mad_u32_u24.  Written out because
+// the compiler emits max + min for the first and folds the second into a
+// 64-bit multiply-add.  hi and a are wave-uniform here (the phantom's
+// dimensions) and stay in scalar registers.
+__device__ __forceinline__ int clamp0_i32(int x, int hi) {
+    int r;
+    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
+    return r;
+}
+__device__ __forceinline__ uint32_t mad_u24(int a, int b, int c) {
+    uint32_t r;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "s"(a), "v"(b), "v"(c));
+    return r;
+}
+
 // The walk in rounds of K crossings ("events").  Each event is the nearest
 // of the next D, A and B crossings (D first on ties with the others, A before
 // B), clipped to a_out; its alpha is computed from the plane index, so it is
@@ -896,21 +912,21 @@ __device__ __forceinline__ bool siddon_locate(const PhantomGeo &g, const double 
     const int max_steps = g.n[0] + g.n[1] + g.n[2] + 3;
     for (int step = 0; step < max_steps; ++step) {
         const int ax = (n1 < n0) ? ((n2 < n1) ? 2 : 1) : ((n2 < n0) ? 2 : 0);
-        const double nmin = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
-        const double a_next = nmin < a_out ? nmin : a_out;
+        const double nmin = min_f64(n0, min_f64(n1, n2));  // the value of axis ax
+        const double a_next = min_f64(nmin, a_out);
         const bool more = nmin < a_out;
         if (more) {
             // cross the plane: the next voxel along that axis (clamped)
             if (ax == 0) {
-                i0 = min(max(i0 + st[0], 0), g.n[0] - 1);
+                i0 = clamp0_i32(i0 + st[0], g.n[0] - 1);
                 p0 += st[0];
                 n0 = ((g.corner[0] + (double)p0 * g.v) - q[0]) * inv[0];
             } else if (ax == 1) {
-                i1 = min(max(i1 + st[1], 0), g.n[1] - 1);
+                i1 = clamp0_i32(i1 + st[1], g.n[1] - 1);
                 p1 += st[1];
                 n1 = ((g.corner[1] + (double)p1 * g.v) - q[1]) * inv[1];
             } else {
-                i2 = min(max(i2 + st[2], 0), g.n[2] - 1);
+                i2 = clamp0_i32(i2 + st[2], g.n[2] - 1);
                 p2 += st[2];
                 n2 = ((g.corner[2] + (double)p2 * g.v) - q[2]) * inv[2];
             }
@@ -1095,22 +1111,6 @@ __device__ __forceinline__ bool comp_phantom_scatter(const DevComp &c, Stream &s
 // the exact walk.  jmax (volume diagonal / h + 2, from the host) bounds every
 // loop; a voxel index is clamped per axis, so every load is in range.
 constexpr int kStepRound = 4;
-
-// clamp(x, 0, hi) for hi >= 0 as one v_med3_i32, and a * b + c on the low
-// 24 bits of a and b as one full-rate v_mad_u32_u24.  Written out because
-// the compiler emits max + min for the first and folds the second into a
-// 64-bit multiply-add.  hi and a are wave-uniform here (the phantom's
-// dimensions) and stay in scalar registers.
-__device__ __forceinline__ int clamp0_i32(int x, int hi) {
-    int r;
-    asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
-    return r;
-}
-__device__ __forceinline__ uint32_t mad_u24(int a, int b, int c) {
-    uint32_t r;
-    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "s"(a), "v"(b), "v"(c));
-    return r;
-}
 
 __device__ __forceinline__ double step_tau(const PhantomGeo &g, const double q[3], const double dl[3], double h,
                                            int jmax, const double *__restrict__ mu_row) {
