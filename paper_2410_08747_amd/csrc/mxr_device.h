@@ -365,6 +365,19 @@ __device__ __forceinline__ bool src_cone_proposal(const DevComp &c, const PropTa
     return p_phys > 0.0;
 }
 
+// tan(x): for |x| < 2^-7 the Maclaurin series x + x^3/3 + 2x^5/15 +
+// 17x^7/315 + 62x^9/2835 (the first omitted term is below 1e-23 of x there),
+// else the library tan.  Beam divergences are micro- to milliradians, so a
+// wave normally skips the library call and its argument reduction.
+__device__ __forceinline__ double tan_small(double x) {
+    if (fabs(x) < 0.0078125) {
+        const double x2 = x * x;
+        const double p = 1.0 / 3.0 + x2 * (2.0 / 15.0 + x2 * (17.0 / 315.0 + x2 * (62.0 / 2835.0)));
+        return x + x * (x2 * p);
+    }
+    return tan(x);
+}
+
 __device__ __forceinline__ void src_gaussian(const DevComp &c, Stream &s, Ray &ray) {
     double r1 = sqrt(-2.0 * log(s.u(0)));
     double s1, c1, s2, c2;
@@ -375,8 +388,8 @@ __device__ __forceinline__ void src_gaussian(const DevComp &c, Stream &s, Ray &r
     q[0] = c.par[0] * (r1 * c1);
     q[1] = c.par[1] * (r1 * s1);
     q[2] = 0.0;
-    double tx = tan(c.par[2] * (r2 * c2));
-    double ty = tan(c.par[3] * (r2 * s2));
+    double tx = tan_small(c.par[2] * (r2 * c2));
+    double ty = tan_small(c.par[3] * (r2 * s2));
     double nrm = sqrt(tx * tx + ty * ty + 1.0);
     dl[0] = tx / nrm;
     dl[1] = ty / nrm;
