@@ -46,10 +46,18 @@ def variant(name):
         slit = {"type": "slit", "pos": (0.0, 0.0, 500.0), "rot": np.eye(3), "w": 60.0, "h": 30.0}
         ins["components"].insert(1, slit)
         return ins
+    if name == "order1_parallel":
+        # a zero-divergence source: every primary ray parallel to the volume's y axis
+        ins = workloads.edct_projection(vol, tables(), angle=0.5, scatter_order=1, **small)
+        ins["components"][0] = {"type": "source_gaussian", "pos": (0.0, 0.0, 0.0), "rot": np.eye(3),
+                                "sigma_x": 10.0, "sigma_y": 5.0, "sigma_xp": 0.0, "sigma_yp": 0.0,
+                                "e0": 60.0, "rel_halfwidth": 0.5}
+        return ins
     raise KeyError(name)
 
 
-NAMES = ["order1_aimed", "order2_aimed", "order1_isotropic", "order3_aimed_voxel0.8", "order1_generic"]
+NAMES = ["order1_aimed", "order2_aimed", "order1_isotropic", "order3_aimed_voxel0.8", "order1_generic",
+         "order1_parallel"]
 
 
 @pytest.mark.parametrize("name", NAMES)

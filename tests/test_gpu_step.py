@@ -18,7 +18,7 @@ import pytest
 import oracle
 import workloads
 from test_gpu_batch import same_tally
-from test_gpu_parity import announce, compare_bins, compare_rays, cpu, mxr, odd_edct
+from test_gpu_parity import announce, compare_bins, compare_rays, cpu, mxr, odd_edct, parallel_beam
 
 pytestmark = pytest.mark.gpu
 
@@ -53,10 +53,16 @@ def stepped(name):
         slit = {"type": "slit", "pos": (0.0, 0.0, 500.0), "rot": np.eye(3), "w": 60.0, "h": 30.0}
         ins["components"].insert(1, slit)
         return ins
+    if name == "parallel_third":
+        # every ray parallel to the y axis of the volume and, at angle 0, to x
+        return with_step(parallel_beam(0.0), 1.0 / 3.0)
+    if name == "parallel_0.5_third":
+        return with_step(parallel_beam(0.5), 1.0 / 3.0)
     raise KeyError(name)
 
 
-NAMES = ["edct_64_third", "edct_64_coarse", "odd_45deg_third", "odd_voxel0.8_third", "slit_generic"]
+NAMES = ["edct_64_third", "edct_64_coarse", "odd_45deg_third", "odd_voxel0.8_third", "slit_generic",
+         "parallel_third", "parallel_0.5_third"]
 
 
 @pytest.mark.parametrize("name", NAMES)
