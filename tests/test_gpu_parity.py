@@ -218,36 +218,41 @@ def test_chunked_runs_equal_one_run(torch_cuda, small_edct):
     assert np.max(np.abs(g[nz] - o[nz]) / o[nz]) <= REL_BIN
 
 
-def parallel_beam(angle, voxel=1.0):
+def parallel_beam(angle, voxel=1.0, sigma=(10.0, 5.0)):
     """The small projection lit by a Gaussian source of zero divergence:
     every ray runs exactly along z, so in the phantom's frame (rotated about
-    y) the y axis is parallel to every ray, and at angle 0 the x axis too."""
+    y) the y axis is parallel to every ray, and at angle 0 the x axis too.
+    With zero width every ray starts on the axis, which lies in voxel faces
+    of the 64^3 volume (its planes sit at whole millimetres from -32)."""
     vol = workloads.make_phantom(64, seed=1)
     ins = workloads.edct_projection(vol, workloads.make_mu_tables(1), angle=angle, strata=16, nx=32, ny=16, ne=16)
     ins["components"][0] = {"type": "source_gaussian", "pos": (0.0, 0.0, 0.0), "rot": np.eye(3),
-                            "sigma_x": 10.0, "sigma_y": 5.0, "sigma_xp": 0.0, "sigma_yp": 0.0,
+                            "sigma_x": sigma[0], "sigma_y": sigma[1], "sigma_xp": 0.0, "sigma_yp": 0.0,
                             "e0": 60.0, "rel_halfwidth": 0.5}
     ins["components"][1]["voxel"] = voxel
     return ins
 
 
-@pytest.mark.parametrize("angle,voxel", [(0.0, 1.0), (0.5, 1.0), (math.pi / 2, 1.0), (0.3, 0.8)])
-def test_axis_parallel_rays(torch_cuda, angle, voxel):
+@pytest.mark.parametrize("angle,voxel,sigma", [(0.0, 1.0, (10.0, 5.0)), (0.5, 1.0, (10.0, 5.0)),
+                                               (math.pi / 2, 1.0, (10.0, 5.0)), (0.3, 0.8, (10.0, 5.0)),
+                                               (0.0, 1.0, (0.0, 0.0)), (0.5, 1.0, (0.0, 0.0))])
+def test_axis_parallel_rays(torch_cuda, angle, voxel, sigma):
     """Rays parallel to one or two axes of the volume (the walk keeps such an
-    axis's alpha at +inf); per ray and per bin against the oracle."""
-    ins = parallel_beam(angle, voxel)
+    axis's alpha at +inf), and with zero beam width rays that run inside
+    voxel faces; per ray and per bin against the oracle."""
+    ins = parallel_beam(angle, voxel, sigma)
     n = 60001
-    announce("axis-parallel rays", "angle", angle, "voxel", voxel, "n", n)
+    announce("axis-parallel rays", "angle", angle, "voxel", voxel, "sigma", sigma, "n", n)
     I = mxr().Instrument(ins)
     ids = np.arange(n, dtype=np.uint64)
     g = I.trace_rays(ids, seed=4, n_total=n)
     torch_cuda.cuda.synchronize()
     o = oracle.trace_rays(ins, ids, seed=4, n_total=n)
     assert int(np.sum(o["bin"] >= 0)) > n // 4
-    compare_rays(g, o, f"parallel beam, angle {angle}, voxel {voxel}")
+    compare_rays(g, o, f"parallel beam, angle {angle}, voxel {voxel}, width {sigma}")
     t = I.run(n, seed=5)
     torch_cuda.cuda.synchronize()
-    compare_bins(t[0], oracle.run(ins, n, seed=5)[0], f"parallel beam bins, angle {angle}, voxel {voxel}")
+    compare_bins(t[0], oracle.run(ins, n, seed=5)[0], f"parallel beam bins, angle {angle}, voxel {voxel}, width {sigma}")
 
 
 def test_edge_cases(torch_cuda, small_edct):
