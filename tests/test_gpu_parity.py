@@ -255,6 +255,24 @@ def test_axis_parallel_rays(torch_cuda, angle, voxel, sigma):
     compare_bins(t[0], oracle.run(ins, n, seed=5)[0], f"parallel beam bins, angle {angle}, voxel {voxel}, width {sigma}")
 
 
+def test_largest_run_size(torch_cuda):
+    """The largest run the 4096^2-cell stratification admits: n_total x cells
+    = 2^64 - 2^24, so the cell arithmetic of the last rays reaches the top of
+    the 64-bit range on both sides; one ray more is refused."""
+    m = mxr()
+    vol = workloads.make_phantom(64, seed=1)
+    ins = workloads.edct_projection(vol, workloads.make_mu_tables(1), angle=0.4, strata=4096)
+    nt = (1 << 40) - 1
+    ids = np.array([0, 1, nt // 3, nt // 2] + list(range(nt - 64, nt)), dtype=np.uint64)
+    announce("largest run size", nt)
+    I = m.Instrument(ins)
+    g = I.trace_rays(ids, seed=3, n_total=nt)
+    torch_cuda.cuda.synchronize()
+    compare_rays(g, oracle.trace_rays(ins, ids, seed=3, n_total=nt), "n_total 2^40 - 1")
+    with pytest.raises(m.MxrError):
+        I.trace_rays(ids[:1], seed=3, n_total=(1 << 40) + 5)
+
+
 def test_edge_cases(torch_cuda, small_edct):
     m = mxr()
     I = m.Instrument(small_edct)
