@@ -202,6 +202,26 @@ def test_full_size_sampled_ranges(torch_cuda, full_edct, first, n):
     compare_bins(t[0], o[0], f"edct_256 rays [{first}, {first + n})")
 
 
+def test_largest_phantom_sampled(torch_cuda):
+    """A 512^3 phantom (128 MiB, the largest of the batched workload) at an
+    oblique angle: sampled rays of a 1e9-ray run and a ray range, per ray and
+    per bin."""
+    vol = workloads.make_phantom(512, seed=2)
+    ins = workloads.edct_projection(vol, workloads.make_mu_tables(1), angle=1.0, strata=4096)
+    n_total = 10**9
+    ids = np.unique(np.concatenate([np.random.default_rng(5).integers(0, n_total, 4000),
+                                    np.arange(0, 32), np.arange(n_total - 32, n_total)]))
+    announce("512^3 sampled rays", ids.size)
+    I = mxr().Instrument(ins)
+    g = I.trace_rays(ids.astype(np.uint64), seed=6, n_total=n_total)
+    torch_cuda.cuda.synchronize()
+    compare_rays(g, oracle.trace_rays(ins, ids, seed=6, n_total=n_total), "512^3 sampled")
+    first, n = 600_000_000, 40000
+    t = I.run(n, seed=6, first_ray=first, n_total=n_total)
+    torch_cuda.cuda.synchronize()
+    compare_bins(t[0], oracle.run(ins, n, seed=6, first=first, n_total=n_total)[0], "512^3 ray range")
+
+
 def test_chunked_runs_equal_one_run(torch_cuda, small_edct):
     n = 400000
     announce("chunking", "n", n)
