@@ -3,8 +3,9 @@
 Per ray (mxr_trace_rays vs the oracle's per-ray trace, the same Philox
 streams): identical status, absorbing component and tally bin; position,
 direction, energy and weight within 1e-12 relative (floors: 1 mm, 1, 1 keV,
-1).  Per bin (mxr_run vs the oracle's run): identical counts; sums of w and
-w^2 within 1e-9 relative, zero bins zero on both sides -- every summand is
+and 1e-300 for the weight, which is compared relative to itself).  Per bin
+(mxr_run vs the oracle's run): identical counts; sums of w and w^2 within
+1e-9 relative, zero bins zero on both sides -- every summand is
 non-negative, so atomic reordering moves a sum by at most (n - 1) 2^-53.
 
 The full-size projection (256^3 phantom, 256 x 64 x 128 detector, 1e9 rays)
@@ -23,6 +24,11 @@ pytestmark = pytest.mark.gpu
 
 REL_RAY = 1e-12
 REL_BIN = 1e-9
+# Weights are non-negative and mostly well below 1 (the median detected
+# weight of the projection is ~0.07, a few percent are below 1e-6), so the
+# weight is compared relative to itself; the floor only keeps subnormal
+# weights (optical depths above ~708) from demanding more bits than they hold.
+W_FLOOR = 1e-300
 
 
 def mxr():
@@ -52,7 +58,7 @@ def compare_rays(gpu, ora, label, w_rel=None):
     assert np.array_equal(cpu(gpu["bin"]), ora["bin"]), f"{label}: bin differs"
     pairs = [("x", ora["r"][:, 0], 1.0), ("y", ora["r"][:, 1], 1.0), ("z", ora["r"][:, 2], 1.0),
              ("dx", ora["d"][:, 0], 1.0), ("dy", ora["d"][:, 1], 1.0), ("dz", ora["d"][:, 2], 1.0),
-             ("E", ora["E"], 1.0), ("w", ora["w"], 1.0)]
+             ("E", ora["E"], 1.0), ("w", ora["w"], W_FLOOR)]
     for name, ref, floor in pairs:
         got = cpu(gpu[name])
         err = np.abs(got - ref) / np.maximum(np.abs(ref), floor)

@@ -92,7 +92,7 @@ def compare_proposal_rays(ins, gmm, alpha, n_total, ids, g, o, seed, job, label,
     w0 = W_g * (s0["w"][live] / W_o)
     c = oracle.trace_after_source(ins, ids[live], seed, n_total, s0["r"][live], gd[live], gE[live], w0,
                                   purpose=purpose, job=job)
-    err = np.abs(gw[live] - c["w"]) / np.maximum(np.abs(c["w"]), 1.0)
+    err = np.abs(gw[live] - c["w"]) / np.maximum(np.abs(c["w"]), 1e-300)
     k = int(np.argmax(err))
     assert err.max() <= 1e-12, f"{label}: w ray {np.flatnonzero(live)[k]}: gpu {gw[live][k]!r} oracle {c['w'][k]!r}"
     assert np.array_equal(c["bin"], cpu(g["bin"])[live])

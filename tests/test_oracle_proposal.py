@@ -1,7 +1,9 @@
 """Pins of the learned-proposal oracle against what mathematics fixes:
 library quantiles and truncated normals, densities that integrate to one,
 the importance-sampling identity E_q[p/q] = 1, unbiased detector images,
-finite differences of the loss, closed forms of the network and head.
+finite differences of the loss, closed forms of the network and head, the
+network's layers against torch's linear and SiLU layers at random weights,
+and Adam against torch's optimizer over several steps.
 """
 import math
 
@@ -251,6 +253,58 @@ def test_gradient_matches_finite_differences():
             tm[i] -= h
             fd = (P.loss(tp, C, Y, omega, lo, hi) - P.loss(tm, C, Y, omega, lo, hi)) / (2 * h)
             assert abs(fd - g[i]) <= 1e-6 * max(abs(fd), 1e-3), (name, idx, fd, g[i])
+
+
+def test_forward_matches_torch_layers():
+    """The hidden path at random non-zero weights against torch's own
+    linear and SiLU layers in float64.  The parameters are unpacked here from
+    the packing the C ABI documents (W1 6 x 128 row-major, b1, W2 128 x 128,
+    b2, W3 128 x 56, b3), so a wrong layer order, activation or packing in
+    the oracle fails."""
+    import torch
+    rng = np.random.default_rng(11)
+    theta = rng.normal(scale=0.4, size=P.N_PARAMS)
+    C = rng.normal(scale=1.5, size=(33, 6))
+    sizes = [(6, 128), (128,), (128, 128), (128,), (128, 56), (56,)]
+    parts, k = [], 0
+    for shp in sizes:
+        n = int(np.prod(shp))
+        parts.append(torch.from_numpy(theta[k:k + n].reshape(shp).copy()))
+        k += n
+    assert k == P.N_PARAMS
+    W1, b1, W2, b2, W3, b3 = parts
+    F = torch.nn.functional
+    x = torch.from_numpy(C)
+    z1 = F.linear(x, W1.T.contiguous(), b1)
+    z2 = F.linear(F.silu(z1), W2.T.contiguous(), b2)
+    o = F.linear(F.silu(z2), W3.T.contiguous(), b3)
+    f = P.forward(theta, C)
+    for name, ref in (("z1", z1), ("z2", z2), ("o", o)):
+        ref = ref.numpy()
+        assert np.max(np.abs(f[name] - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref))), name
+    assert np.max(np.abs(f["h1"] - F.silu(z1).numpy())) <= 1e-13 * max(1.0, float(z1.abs().max()))
+    # the hidden layers matter at these weights: the output is far from b3
+    assert np.max(np.abs(f["o"] - theta[-56:])) > 1.0
+
+
+def test_adam_matches_torch_optimizer():
+    """Twelve Adam steps with gradients that change size and sign, against
+    torch.optim.Adam in float64 (same lr, betas, eps); a wrong bias
+    correction (1 - b2 for 1 - b2^t, say) or moment update fails at step 2."""
+    import torch
+    rng = np.random.default_rng(5)
+    n = 257
+    theta = rng.normal(size=n)
+    m, v = np.zeros(n), np.zeros(n)
+    p = torch.nn.Parameter(torch.from_numpy(theta.copy()))
+    opt = torch.optim.Adam([p], lr=2e-3, betas=(0.85, 0.995), eps=1e-7)
+    for step in range(1, 13):
+        g = rng.normal(size=n) * 10.0 ** rng.integers(-4, 3, n)
+        theta, m, v = P.adam(theta, m, v, g, step, lr=2e-3, b1=0.85, b2=0.995, eps=1e-7)
+        p.grad = torch.from_numpy(g.copy())
+        opt.step()
+        ref = p.detach().numpy()
+        assert np.max(np.abs(theta - ref)) <= 1e-13, step
 
 
 def test_adam_first_step_is_sign_step():

@@ -5,7 +5,9 @@ order; section 3.3: the voxel sample models absorption and scattering).
   quadrature of the differential cross section, and its Thomson limit 4/3;
 * the forced interaction depth in a homogeneous cube follows the truncated
   exponential on the chord (KS), the chord from an independent ray/box
-  intersection;
+  intersection; across three layers of different attenuation and albedo,
+  the point follows the layered depth's distribution function (KS) and every
+  ray's weight equals the product of slab-geometry factors;
 * the weight of a single scatter, divided by the factors the geometry fixes
   (1 - e^-mu L, the albedo, e^-mu L_exit with L_exit from the independent
   intersection), is the angular factor; weighted by it, the scattering
@@ -113,6 +115,80 @@ def test_interaction_depth_truncated_exponential():
     assert len(rows) > 15000
     m = mu_t / 10.0
     u = [(1 - math.exp(-m * s)) / (1 - math.exp(-m * L)) for _, L, s, _, _ in rows]
+    assert stats.kstest(u, "uniform").pvalue > 1e-3
+
+
+# layers along z of the cube: voxel planes k in [0, 4), [4, 8), [8, 12)
+LAYERS = ((1, 0.6, 0.30), (2, 3.0, 0.60), (3, 1.2, 0.96))  # material, mu_total, mu_Rayleigh (1/cm)
+
+
+def layered_instrument():
+    ins = cube_instrument(1.0, 0.0, 0.0)
+    ph = ins["components"][1]
+    vol = np.zeros((N, N, N), np.uint8)
+    tab = np.zeros((3, 4, 4))
+    tab[0, 0] = 1.0  # material 0 unused
+    for k, (m, mt, mr) in enumerate(LAYERS):
+        vol[4 * k:4 * k + 4] = m
+        tab[0, m], tab[1, m] = mt, mr  # Rayleigh only: Thomson angles, energy kept
+    ph["volume"], ph["mu_table"] = vol, tab
+    return ins
+
+
+def layered_tau(p, d, length):
+    """Optical depth of the segment p + t d, t in [0, length], through the
+    z layers (z of the cube from 94 to 106 mm), by interval overlap."""
+    tau = 0.0
+    for k, (_, mt, _) in enumerate(LAYERS):
+        z0, z1 = 94.0 + 4 * k, 98.0 + 4 * k
+        if d[2] == 0.0:
+            ln = length if z0 <= p[2] < z1 else 0.0
+        else:
+            t0, t1 = sorted(((z0 - p[2]) / d[2], (z1 - p[2]) / d[2]))
+            ln = max(0.0, min(t1, length) - max(t0, 0.0))
+        tau += mt * ln / 10.0
+    return tau
+
+
+def test_forced_interaction_across_material_layers():
+    """Rays crossing three z layers of different attenuation and albedo
+    (Rayleigh only).  The forced interaction point s on the chord has the
+    distribution function (1 - e^-tau(s)) / (1 - e^-tau(L)), with tau(s) the
+    piecewise-linear depth through the layers (KS on that transform); and
+    each ray's weight over its source weight equals (1 - e^-tau(L)) times
+    the albedo of the layer holding the point, the Thomson factor
+    3/4 (1 + cos^2) of isotropic draws and e^-tau_exit along the new
+    direction -- every factor from slab geometry written here, not from the
+    voxel walk, so a walk that switches material in the wrong place, keeps
+    the first material, or takes the albedo from elsewhere fails."""
+    ins = layered_instrument()
+    n = 20000
+    ids = np.arange(n)
+    src = oracle.trace_rays({"components": ins["components"][:1]}, ids, seed=7, n_total=n)
+    out = oracle.trace_rays(ins, ids, seed=7, n_total=n)
+    h = N / 2.0
+    u, seen = [], set()
+    for i in range(n):
+        assert out["status"][i] == oracle.STATUS_EXITED
+        q0 = src["r"][i] - np.array([0.0, 0.0, 100.0])
+        d0 = src["d"][i]
+        a_in, a_out = box_interval(q0, d0, h)
+        L = a_out - a_in
+        entry = src["r"][i] + a_in * d0
+        tau_L = layered_tau(entry, d0, L)
+        p = out["r"][i]
+        s = float(np.dot(p - entry, d0))
+        u.append((1 - math.exp(-layered_tau(entry, d0, s))) / (1 - math.exp(-tau_L)))
+        d1 = out["d"][i]
+        _, l_exit = box_interval(p - np.array([0.0, 0.0, 100.0]), d1, h)
+        k = min(int((p[2] - 94.0) // 4), 2)
+        seen.add(k)
+        albedo = LAYERS[k][2] / LAYERS[k][1]
+        ct = float(np.dot(d0, d1))
+        want = (1 - math.exp(-tau_L)) * albedo * 0.75 * (1 + ct * ct) * math.exp(-layered_tau(p, d1, l_exit))
+        got = out["w"][i] / src["w"][i]
+        assert abs(got - want) <= 1e-9 * want, (i, got, want, k)
+    assert seen == {0, 1, 2}
     assert stats.kstest(u, "uniform").pvalue > 1e-3
 
 
