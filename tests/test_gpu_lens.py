@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads
-from test_gpu_parity import announce, compare_bins, compare_rays, cpu, mxr
+from test_gpu_parity import announce, compare_bins, compare_rays, retracer, cpu, mxr
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +63,7 @@ def test_per_ray_parity(torch_cuda, name):
     through = np.sum((o["dead_at"] < 0) | (o["dead_at"] > lens_k))
     print(f"{name}: {through} rays through the lens", flush=True)
     assert through > 1000
-    compare_rays(g, o, name)
+    compare_rays(g, o, name, retrace=retracer(ins, ids, 7, n))
 
 
 @pytest.mark.parametrize("name", NAMES)
@@ -96,7 +96,7 @@ def test_full_size_sampled_rays(torch_cuda):
     g = mxr().Instrument(ins).trace_rays(ids.astype(np.uint64), seed=1, n_total=n_total)
     torch_cuda.cuda.synchronize()
     o = oracle.trace_rays(ins, ids, seed=1, n_total=n_total)
-    compare_rays(g, o, "crl full-size")
+    compare_rays(g, o, "crl full-size", retrace=retracer(ins, ids, 1, n_total))
 
 
 @pytest.mark.parametrize("first,n", [(0, 1000000), (10**9 - 524288, 524288)])

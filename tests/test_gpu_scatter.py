@@ -70,7 +70,7 @@ def test_per_ray_parity(torch_cuda, name):
     torch_cuda.cuda.synchronize()
     o = oracle.trace_rays(ins, ids, seed=7, n_total=n)
     print(f"{name}: {int(np.sum(o['bin'] >= 0))} rays tallied", flush=True)
-    compare_rays(g, o, name)
+    compare_rays(g, o, name, scatter=True)
 
 
 @pytest.mark.parametrize("name", NAMES)
@@ -106,7 +106,7 @@ def test_full_size_sampled_rays(torch_cuda, full_scatter):
     g = mxr().Instrument(full_scatter).trace_rays(ids.astype(np.uint64), seed=1, n_total=n_total)
     torch_cuda.cuda.synchronize()
     o = oracle.trace_rays(full_scatter, ids, seed=1, n_total=n_total)
-    compare_rays(g, o, "scatter 256 full-size")
+    compare_rays(g, o, "scatter 256 full-size", scatter=True)
 
 
 @pytest.mark.parametrize("first,n", [(0, 50000), (10**9 - 40000, 40000)])

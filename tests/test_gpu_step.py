@@ -18,7 +18,7 @@ import pytest
 import oracle
 import workloads
 from test_gpu_batch import same_tally
-from test_gpu_parity import announce, compare_bins, compare_rays, cpu, mxr, odd_edct, parallel_beam
+from test_gpu_parity import announce, compare_bins, compare_rays, retracer, cpu, mxr, odd_edct, parallel_beam
 
 pytestmark = pytest.mark.gpu
 
@@ -74,7 +74,7 @@ def test_per_ray_parity(torch_cuda, name):
     g = mxr().Instrument(ins).trace_rays(ids, seed=7, n_total=n)
     torch_cuda.cuda.synchronize()
     o = oracle.trace_rays(ins, ids, seed=7, n_total=n)
-    compare_rays(g, o, name)
+    compare_rays(g, o, name, retrace=retracer(ins, ids, 7, n))
 
 
 @pytest.mark.parametrize("name", NAMES)
@@ -110,7 +110,7 @@ def test_full_size_sampled_rays(torch_cuda, full_step):
     g = mxr().Instrument(full_step).trace_rays(ids.astype(np.uint64), seed=1, n_total=n_total)
     torch_cuda.cuda.synchronize()
     o = oracle.trace_rays(full_step, ids, seed=1, n_total=n_total)
-    compare_rays(g, o, "step edct_256 full-size")
+    compare_rays(g, o, "step edct_256 full-size", retrace=retracer(full_step, ids, 1, n_total))
 
 
 @pytest.mark.parametrize("first,n", [(0, 100000), (10**9 - 65536, 65536)])
