@@ -301,7 +301,7 @@ def time_to_1pct(args):
     cap = int(args.train_hits)
     hits = None
     starts, emitted = [], 0
-    omega_parts = []
+    images = []
     for a_i, ang in enumerate(train_angles):
         ins, I = instrument(ang)
         if hits is None:
@@ -318,27 +318,27 @@ def time_to_1pct(args):
         end = int(hits["count"].item())
         assert end <= cap, "training rows overflowed the buffer"
         emitted += pilot + main
-        part = {"w": hits["w"][start:end], "bin": hits["bin"][start:end]}
-        omega_parts.append(mxr.train_weights(part, end - start, coll[0]["sum_w"]))
+        images.append(coll[0]["sum_w"])
         starts.append(start)
         del I, coll
     n_rows = int(hits["count"].item())
-    omega = torch.cat(omega_parts)
     torch.cuda.synchronize()
     t_collect = time.perf_counter() - t0
-    lo, hi = mxr.source_box(workloads.edct_projection(vol, mu, angle=0.0, strata=STRATA)["components"][0])
+    # training weights per angle from that angle's image, then Adam: one library call
     net = mxr.ProposalNet(workloads.init_mlp_params(1), batch=65536, device=dev)
     steps = args.epochs * ((n_rows + 65535) // 65536)
     loss_log = torch.zeros(steps, dtype=torch.float64, device=dev)
-    net.train(hits["ctx"][:n_rows], hits["y"][:n_rows], omega, lo, hi, epochs=args.epochs, lr=1e-3, seed=1,
-              loss_log=loss_log, stream=stream)
+    _, I0 = instrument(0.0)
+    net.train_from_runs(I0, hits, starts + [n_rows], images, epochs=args.epochs, lr=1e-3, seed=1,
+                        loss_log=loss_log, stream=stream)
     torch.cuda.synchronize()
+    del I0
     t_train = time.perf_counter() - t0 - t_collect
     t_learn = time.perf_counter() - t0  # inference (one forward per projection) is timed below
     ll = loss_log.cpu().numpy()
     log(f"collected {n_rows:.2e} hits at {len(train_angles)} angles from {emitted:.2e} rays in {t_collect:.2f} s; "
         f"trained {steps} steps in {t_train:.2f} s; loss {ll[:10].mean():.4f} -> {ll[-10:].mean():.4f}")
-    del hits, omega, omega_parts
+    del hits, images
 
     results = {}
     for name, ang in (("angle_0", 0.0), ("angle_0.3_unseen", 0.3)):
@@ -356,9 +356,7 @@ def time_to_1pct(args):
         T_p = metrics.time_to_1pct(tp / n_p, n_p, q_p)
         torch.cuda.synchronize()
         ti = time.perf_counter()
-        out = net.forward(torch.tensor(workloads.projection_context(ang, 256)[None, :], device=dev))
-        gmm = net.mixture(out, lo, hi)
-        I.set_proposal(gmm[0], alpha=args.alpha)
+        I.apply_proposal(net, workloads.projection_context(ang, 256), alpha=args.alpha, stream=stream)
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - ti
         ml, rl, tl, n_l = replicas(I, args.eval_rays)

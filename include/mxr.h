@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define MXR_ABI_VERSION 1u
+#define MXR_ABI_VERSION 2u
 #define MXR_MAX_COMPONENTS 16u
 #define MXR_MAX_DETECTORS 4u
 
@@ -234,7 +234,7 @@ void mxr_instrument_destroy(mxr_instrument *ins);
  * [4k+2] weight removed by attenuation at k, [4k+3] weight tallied at k;
  * [4K] weight leaving the instrument.  Errors: MXR_E_INVALID (null handle
  * or tallies, tally count or size mismatch, first_ray + n_rays > n_total,
- * n_total * G^2 >= 2^64), MXR_E_STATE (another device current), MXR_E_HIP. */
+ * n_total G^2 + G^2 - 1 >= 2^64), MXR_E_STATE (another device current), MXR_E_HIP. */
 mxr_status mxr_run(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays, uint64_t n_total, uint64_t seed,
                    uint32_t purpose, uint32_t job, const mxr_tally *tallies, uint32_t n_tallies, double *ledger,
                    void *hip_stream);
@@ -283,6 +283,13 @@ mxr_status mxr_trace_rays(mxr_instrument *ins, const uint64_t *ray_ids, uint64_t
  * first component is not a cone-beam source), MXR_E_STATE, MXR_E_NOMEM,
  * MXR_E_HIP. */
 mxr_status mxr_proposal_set(mxr_instrument *ins, const double *gmm, double alpha);
+
+/* The box of the proposal coordinates of the instrument's cone-beam source
+ * (host arrays of 3): lo = (-tan a, -tan a, E min), hi = (tan a, tan a,
+ * E max), a the cone half-angle; the mixture head and the training loss
+ * below take it.  Errors: MXR_E_INVALID (null pointers), MXR_E_UNSUPPORTED
+ * (the first component is not a cone-beam source). */
+mxr_status mxr_proposal_box(const mxr_instrument *ins, double lo[3], double hi[3]);
 
 /* Rows of training data: one per ray that reaches the monitor.  All arrays
  * are DEVICE arrays of `capacity` rows; *count (device) is advanced by the
@@ -422,6 +429,47 @@ mxr_status mxr_mlp_train(const float *ctx, const double *y, const double *omega,
                          const mxr_train_cfg *cfg, const double lo[3], const double hi[3], float *master, uint16_t *w,
                          float *m, float *v, float *grad, void *ws, uint64_t ws_bytes, double *loss_log,
                          void *hip_stream);
+
+/* Training rows gathered by one or more collecting runs (mxr_collect), as
+ * DEVICE arrays of n_rows entries; rows [run_first[r], run_first[r + 1])
+ * came from run r, whose monitor image (sum_w, DEVICE, n_bins doubles) is
+ * run_image[r].  run_first and run_image are HOST arrays of n_runs + 1 and
+ * n_runs entries; run_first[0] = 0 and run_first[n_runs] = n_rows. */
+typedef struct {
+    const float *ctx;
+    const double *y;
+    const double *w;
+    const int64_t *bin;
+    uint64_t n_rows;
+    uint32_t n_runs;
+    const uint64_t *run_first;
+    const double *const *run_image;
+    uint64_t n_bins;
+    double floor_frac; /* of mxr_train_weights */
+} mxr_train_rows;
+
+/* The learned proposal from collected rows in one call: the training
+ * weights of each run's rows from that run's image (mxr_train_weights,
+ * written to omega: DEVICE, n_rows doubles), then Adam training of the
+ * network (mxr_mlp_train) in the box of the instrument's source
+ * (mxr_proposal_box).  master, w, m, v, grad, ws, ws_bytes and loss_log as
+ * in mxr_mlp_train (ws also serves the weight statistics before the
+ * training steps).  Asynchronous on hip_stream.  Errors: MXR_E_INVALID
+ * (null arrays, run table not covering the rows, n_runs = 0),
+ * MXR_E_UNSUPPORTED (the source is not a cone-beam source, 2^32 rows or
+ * more), MXR_E_HIP. */
+mxr_status mxr_proposal_train(const mxr_instrument *ins, const mxr_train_rows *rows, const mxr_train_cfg *cfg,
+                              float *master, uint16_t *w, float *m, float *v, float *grad, double *omega, void *ws,
+                              uint64_t ws_bytes, double *loss_log, void *hip_stream);
+
+/* Sets the instrument's proposal from the network: one forward at the
+ * host `context` (6 floats) under the bfloat16 parameters w (DEVICE), the
+ * mixture in the source's box, then mxr_proposal_set(ins, ., alpha).  ws:
+ * DEVICE, at least mxr_mlp_workspace_bytes(1) + 1024 bytes.  Synchronises
+ * the device (as mxr_proposal_set).  Errors: as mxr_mlp_forward and
+ * mxr_proposal_set. */
+mxr_status mxr_proposal_apply(mxr_instrument *ins, const uint16_t *w, const float context[6], double alpha, void *ws,
+                              uint64_t ws_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Per-bin error of a detector image by batch means.

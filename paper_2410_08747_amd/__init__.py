@@ -18,7 +18,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmxr.so")
 
-MXR_ABI_VERSION = 1
+MXR_ABI_VERSION = 2
 MAX_COMPONENTS = 16
 
 TYPE_CODES = {
@@ -110,6 +110,21 @@ class mxr_train_cfg(ctypes.Structure):
                 ("first_step", ctypes.c_uint32)]
 
 
+class mxr_train_rows(ctypes.Structure):
+    _fields_ = [
+        ("ctx", ctypes.c_void_p),
+        ("y", ctypes.c_void_p),
+        ("w", ctypes.c_void_p),
+        ("bin", ctypes.c_void_p),
+        ("n_rows", ctypes.c_uint64),
+        ("n_runs", ctypes.c_uint32),
+        ("run_first", ctypes.POINTER(ctypes.c_uint64)),
+        ("run_image", ctypes.POINTER(ctypes.c_void_p)),
+        ("n_bins", ctypes.c_uint64),
+        ("floor_frac", ctypes.c_double),
+    ]
+
+
 class mxr_hits(ctypes.Structure):
     _fields_ = [
         ("ctx", ctypes.c_void_p),
@@ -180,6 +195,13 @@ def _load() -> ctypes.CDLL:
     lib.mxr_train_weights.restype = ctypes.c_int
     lib.mxr_mlp_train.argtypes = [P, P, P, U64, ctypes.POINTER(mxr_train_cfg), D3, D3, P, P, P, P, P, P, U64, P, P]
     lib.mxr_mlp_train.restype = ctypes.c_int
+    lib.mxr_proposal_box.argtypes = [P, D3, D3]
+    lib.mxr_proposal_box.restype = ctypes.c_int
+    lib.mxr_proposal_train.argtypes = [P, ctypes.POINTER(mxr_train_rows), ctypes.POINTER(mxr_train_cfg), P, P, P, P,
+                                       P, P, P, U64, P, P]
+    lib.mxr_proposal_train.restype = ctypes.c_int
+    lib.mxr_proposal_apply.argtypes = [P, P, ctypes.POINTER(ctypes.c_float), ctypes.c_double, P, U64, P]
+    lib.mxr_proposal_apply.restype = ctypes.c_int
     lib.mxr_batch_means.argtypes = [P, ctypes.c_uint32, U64, U64, P, P, P]
     lib.mxr_batch_means.restype = ctypes.c_int
     lib.mxr_batch_create.argtypes = [ctypes.POINTER(mxr_batch_job), ctypes.c_uint32,
@@ -303,6 +325,23 @@ def mxr_mlp_train(ctx, y, omega, n_rows, cfg: mxr_train_cfg, lo, hi, master, w, 
                   stream=None) -> None:
     _check(lib.mxr_mlp_train(ctx, y, omega, n_rows, ctypes.byref(cfg), _d3(lo), _d3(hi), master, w, m, v, grad, ws,
                              ws_bytes, loss_log, _stream_handle(stream)))
+
+
+def mxr_proposal_box(handle: int):
+    lo, hi = (ctypes.c_double * 3)(), (ctypes.c_double * 3)()
+    _check(lib.mxr_proposal_box(handle, lo, hi))
+    return tuple(lo), tuple(hi)
+
+
+def mxr_proposal_train(handle: int, rows: mxr_train_rows, cfg: mxr_train_cfg, master, w, m, v, grad, omega, ws,
+                       ws_bytes, loss_log, stream=None) -> None:
+    _check(lib.mxr_proposal_train(handle, ctypes.byref(rows), ctypes.byref(cfg), master, w, m, v, grad, omega, ws,
+                                  ws_bytes, loss_log, _stream_handle(stream)))
+
+
+def mxr_proposal_apply(handle: int, w, context, alpha: float, ws, ws_bytes, stream=None) -> None:
+    c = (ctypes.c_float * 6)(*[float(x) for x in context])
+    _check(lib.mxr_proposal_apply(handle, w, c, alpha, ws, ws_bytes, _stream_handle(stream)))
 
 
 def mxr_batch_means(sums_ptr, R, n_bins, rays_per_replica, mean_ptr, rel_ptr, stream=None) -> None:
@@ -525,6 +564,15 @@ class Instrument:
         g = gmm.reshape(56).to(dtype=__import__("torch").float64).contiguous()
         mxr_proposal_set(self.handle, g.data_ptr(), alpha)
 
+    def proposal_box(self):
+        """(lo, hi) of the cone-beam source's proposal coordinates (u, v, E)."""
+        return mxr_proposal_box(self.handle)
+
+    def apply_proposal(self, net, context, alpha: float = 0.1, stream=None) -> None:
+        """Draw the cone-beam source from the network ``net``'s mixture at
+        ``context`` (one forward, the library's own box)."""
+        mxr_proposal_apply(self.handle, net.w.data_ptr(), context, alpha, net.ws.data_ptr(), net.ws_bytes, stream)
+
     def new_hits(self, capacity: int):
         """Device buffers for ``capacity`` collected rows and a zeroed counter."""
         import torch
@@ -621,13 +669,6 @@ class Batch:
             pass
 
 
-def source_box(source: Dict):
-    """(lo, hi) of the proposal box of a cone-beam source dict."""
-    import math
-    t = math.tan(source["half_angle"])
-    return (-t, -t, float(source["emin"])), (t, t, float(source["emax"]))
-
-
 class ProposalNet:
     """The proposal network's device state: float32 master parameters, their
     bfloat16 working copy, Adam moments, a gradient buffer and a workspace
@@ -646,7 +687,8 @@ class ProposalNet:
         self.grad = torch.zeros(MLP_PARAMS, dtype=torch.float32, device=self.device)
         self.loss = torch.zeros(1, dtype=torch.float64, device=self.device)
         self.batch = batch
-        self.ws_bytes = mxr_mlp_workspace_bytes(batch)
+        # the network's workspace, with room for mxr_proposal_apply's tail
+        self.ws_bytes = max(mxr_mlp_workspace_bytes(batch), mxr_mlp_workspace_bytes(1) + 1024)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.step = 0
         mxr_mlp_to_bf16(self.master.data_ptr(), MLP_PARAMS, self.w.data_ptr())
@@ -696,6 +738,28 @@ class ProposalNet:
                       self.grad.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
                       loss_log.data_ptr() if loss_log is not None else None, stream)
         self.step += epochs * ((n + min(self.batch, n) - 1) // min(self.batch, n))
+
+
+    def train_from_runs(self, ins, hits, run_first, run_images, epochs: int, lr=1e-3, beta1=0.9, beta2=0.999,
+                        eps=1e-8, seed: int = 1, floor_frac: float = 1e-3, loss_log=None, stream=None):
+        """mxr_proposal_train: the training weights of the collected rows
+        ``hits`` (rows [run_first[r], run_first[r + 1]) from the run whose
+        monitor image is run_images[r]) and Adam training in the box of the
+        instrument ``ins``'s source.  Returns the weights (device tensor)."""
+        import torch
+        n = int(run_first[-1])
+        omega = torch.empty(n, dtype=torch.float64, device=self.device)
+        first = (ctypes.c_uint64 * len(run_first))(*[int(x) for x in run_first])
+        images = (ctypes.c_void_p * len(run_images))(*[t.data_ptr() for t in run_images])
+        rows = mxr_train_rows(hits["ctx"].data_ptr(), hits["y"].data_ptr(), hits["w"].data_ptr(),
+                              hits["bin"].data_ptr(), n, len(run_images), first, images, run_images[0].numel(),
+                              floor_frac)
+        cfg = mxr_train_cfg(lr, beta1, beta2, eps, self.batch, epochs, seed, self.step)
+        mxr_proposal_train(ins.handle, rows, cfg, self.master.data_ptr(), self.w.data_ptr(), self.m.data_ptr(),
+                           self.v.data_ptr(), self.grad.data_ptr(), omega.data_ptr(), self.ws.data_ptr(),
+                           self.ws_bytes, loss_log.data_ptr() if loss_log is not None else None, stream)
+        self.step += epochs * ((n + min(self.batch, n) - 1) // min(self.batch, n))
+        return omega
 
 
 def train_weights(hits, count: int, sum_w, floor_frac: float = 1e-3, stream=None):

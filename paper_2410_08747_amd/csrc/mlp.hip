@@ -855,4 +855,60 @@ mxr_status mxr_mlp_train(const float *ctx, const double *y, const double *omega,
     return MXR_OK;
 }
 
+mxr_status mxr_proposal_train(const mxr_instrument *ins, const mxr_train_rows *rows, const mxr_train_cfg *cfg,
+                              float *master, uint16_t *w, float *m, float *v, float *grad, double *omega, void *ws,
+                              uint64_t ws_bytes, double *loss_log, void *hip_stream) {
+    if (!rows || !cfg) return fail(MXR_E_INVALID, "null rows or configuration");
+    double lo[3], hi[3];
+    mxr_status s = mxr_proposal_box(ins, lo, hi);
+    if (s != MXR_OK) return s;
+    const mxr_train_rows &R = *rows;
+    if (R.n_rows == 0) return fail(MXR_E_INVALID, "no training rows");
+    if (R.n_runs == 0 || !R.run_first || !R.run_image) return fail(MXR_E_INVALID, "no run table");
+    if (R.run_first[0] != 0 || R.run_first[R.n_runs] != R.n_rows)
+        return fail(MXR_E_INVALID, "the run table must cover rows [0, n_rows)");
+    if ((s = check_device_ptrs({R.ctx, R.y, R.w, R.bin, omega, ws})) != MXR_OK) return s;
+    if (ws_bytes < (2 * kSumBlocks + 1) * sizeof(double))
+        return fail(MXR_E_INVALID, "workspace of %llu bytes is too small", (unsigned long long)ws_bytes);
+    for (uint32_t r = 0; r < R.n_runs; ++r) {
+        const uint64_t a = R.run_first[r], b = R.run_first[r + 1];
+        if (b < a || b > R.n_rows) return fail(MXR_E_INVALID, "run %u: rows [%llu, %llu) out of order", r,
+                                               (unsigned long long)a, (unsigned long long)b);
+        if (b == a) continue;
+        if (!R.run_image[r]) return fail(MXR_E_INVALID, "run %u: null image", r);
+        // the weight statistics use the start of the workspace; the training
+        // below overwrites it only after these kernels (same stream)
+        if ((s = mxr_train_weights(R.w + a, R.bin + a, b - a, R.run_image[r], R.n_bins, R.floor_frac, omega + a,
+                                   (double *)ws, hip_stream)) != MXR_OK)
+            return s;
+    }
+    return mxr_mlp_train(R.ctx, R.y, omega, R.n_rows, cfg, lo, hi, master, w, m, v, grad, ws, ws_bytes, loss_log,
+                         hip_stream);
+}
+
+mxr_status mxr_proposal_apply(mxr_instrument *ins, const uint16_t *w, const float context[6], double alpha, void *ws,
+                              uint64_t ws_bytes, void *hip_stream) {
+    double lo[3], hi[3];
+    mxr_status s = mxr_proposal_box(ins, lo, hi);
+    if (s != MXR_OK) return s;
+    if (!w || !context || !ws) return fail(MXR_E_INVALID, "null parameters, context or workspace");
+    const uint64_t net_bytes = layout_for(1).bytes;
+    if (ws_bytes < net_bytes + 1024)
+        return fail(MXR_E_INVALID, "workspace of %llu bytes, %llu needed", (unsigned long long)ws_bytes,
+                    (unsigned long long)(net_bytes + 1024));
+    // after the network's workspace: the context (6 floats), the outputs
+    // (56 floats) and the mixture (56 doubles)
+    char *tail = (char *)ws + net_bytes;
+    float *ctx = (float *)tail, *out = (float *)(tail + 64);
+    double *gmm = (double *)(tail + 512);
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipError_t e = hipMemcpyAsync(ctx, context, kIn * sizeof(float), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return fail(MXR_E_HIP, "copy of the context: %s", hipGetErrorString(e));
+    if ((s = mxr_mlp_forward(w, ctx, 1, out, ws, net_bytes, hip_stream)) != MXR_OK) return s;
+    if ((s = mxr_mlp_mixture(out, 1, lo, hi, gmm, hip_stream)) != MXR_OK) return s;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(MXR_E_HIP, "network forward: %s", hipGetErrorString(e));
+    return mxr_proposal_set(ins, gmm, alpha);
+}
+
 }  // extern "C"

@@ -240,9 +240,12 @@ template <class C>
 struct WavesHint {
     static constexpr int value = 1;
 };
+#ifndef MXR_PROJ_WAVES
+#define MXR_PROJ_WAVES 8
+#endif
 template <>
 struct WavesHint<Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR>> {
-    static constexpr int value = 8;
+    static constexpr int value = MXR_PROJ_WAVES;
 };
 template <>
 struct WavesHint<Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, kDetectorCollect>> {
@@ -1039,6 +1042,17 @@ static mxr_status derive(const mxr_component_desc &s, DevComp &c, int k, uint32_
     return MXR_OK;
 }
 
+// Box of the proposal coordinates y = (u, v, E) of a cone-beam source:
+// u = dx/dz and v = dy/dz reach tan(half-angle) on the cone's rim, and the
+// energy is drawn on [E min, E max].
+static void proposal_box(const DevComp &c, double lo[3], double hi[3]) {
+    const double t = std::tan(c.par[0]);
+    lo[0] = lo[1] = -t;
+    hi[0] = hi[1] = t;
+    lo[2] = c.par[1];
+    hi[2] = c.par[2];
+}
+
 extern "C" {
 
 uint32_t mxr_abi_version(void) { return MXR_ABI_VERSION; }
@@ -1224,7 +1238,9 @@ static mxr_status common_args(mxr_instrument *ins, uint64_t n_total, uint64_t se
     while (G > 1 && G * G > n_total) G -= 1;
     a.G = G;
     a.G2 = G * G;
-    if (a.G2 > 1 && n_total > (~0ull) / a.G2) return fail(MXR_E_INVALID, "n_total * strata^2 must stay below 2^64");
+    // the last cell's bound (cell + 1) n_total + G^2 - 1 must not wrap
+    if (a.G2 > 1 && n_total > (~0ull - (a.G2 - 1)) / a.G2)
+        return fail(MXR_E_INVALID, "n_total * strata^2 + strata^2 - 1 must stay below 2^64");
     a.prop = ins->prop_on ? ins->prop_dev : nullptr;
     if (ins->prop_on) {
         // branch ranges of this run: plain share round(alpha n), then the
@@ -1324,6 +1340,13 @@ mxr_status mxr_collect(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays,
     return launch(ins, a, n_rays, false, false, (hipStream_t)hip_stream);
 }
 
+mxr_status mxr_proposal_box(const mxr_instrument *ins, double lo[3], double hi[3]) {
+    if (!ins || !lo || !hi) return fail(MXR_E_INVALID, "null instrument or box");
+    if (ins->host.c[0].type != MXR_SRC_CONE_BEAM) return fail(MXR_E_UNSUPPORTED, "a proposal needs a cone-beam source");
+    proposal_box(ins->host.c[0], lo, hi);
+    return MXR_OK;
+}
+
 mxr_status mxr_proposal_set(mxr_instrument *ins, const double *gmm, double alpha) {
     if (!ins) return fail(MXR_E_INVALID, "null instrument");
     int cur = -1;
@@ -1343,8 +1366,9 @@ mxr_status mxr_proposal_set(mxr_instrument *ins, const double *gmm, double alpha
     const DevComp &c = d.c[0];
     PropTable P;
     std::memset(&P, 0, sizeof P);
-    const double t = std::tan(c.par[0]);
-    const double lo[3] = {-t, -t, c.par[1]}, hi[3] = {t, t, c.par[2]};
+    double lo[3], hi[3];
+    proposal_box(c, lo, hi);
+    const double t = hi[0];
     double run = 0.0;
     for (int k = 0; k < 8; ++k) {
         const double *gk = g + 7 * k;
@@ -1622,7 +1646,8 @@ mxr_status mxr_batch_create(const mxr_batch_job *jobs, uint32_t n_jobs, const mx
         b.word3 = j.job;
         uint64_t G = ins->strata ? ins->strata : 1;
         while (G > 1 && G * G > j.n_rays) G -= 1;
-        if (G * G > 1 && j.n_rays > (~0ull) / (G * G)) return fail(MXR_E_INVALID, "job %u: n_rays * strata^2 must stay below 2^64", k);
+        if (G * G > 1 && j.n_rays > (~0ull - (G * G - 1)) / (G * G))
+            return fail(MXR_E_INVALID, "job %u: n_rays * strata^2 + strata^2 - 1 must stay below 2^64", k);
         b.G = G;
         b.G2 = G * G;
         for (uint32_t d = 0; d < ins->n_det; ++d) {

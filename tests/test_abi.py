@@ -27,8 +27,13 @@ def lib():
 
 def test_header_declares_the_api():
     names = declared_functions()
+    # the boundary of the hot path: tracing, the learned proposal (set, box,
+    # train from collected rows, apply from the network), the batch and the
+    # launch-shape tuners
     for want in ("mxr_abi_version", "mxr_last_error", "mxr_instrument_create", "mxr_instrument_destroy",
-                 "mxr_run", "mxr_trace_rays"):
+                 "mxr_run", "mxr_trace_rays", "mxr_collect", "mxr_proposal_set", "mxr_proposal_box",
+                 "mxr_proposal_train", "mxr_proposal_apply", "mxr_batch_create", "mxr_batch_run",
+                 "mxr_batch_autotune", "mxr_batch_means"):
         assert want in names
 
 
@@ -44,7 +49,7 @@ def test_library_exports_every_declared_symbol(lib):
 def test_calls_that_need_no_device(lib):
     lib.mxr_abi_version.restype = ctypes.c_uint32
     lib.mxr_last_error.restype = ctypes.c_char_p
-    assert lib.mxr_abi_version() == 1
+    assert lib.mxr_abi_version() == 2
     assert lib.mxr_last_error() is not None
     # validation fails before any device call
     out = ctypes.c_void_p()
@@ -69,7 +74,7 @@ def test_binding_struct_layout(lib):
 #include <stdio.h>
 #include <stddef.h>
 #include "mxr.h"
-int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mxr_component_desc), sizeof(mxr_tally), sizeof(mxr_ray_soa), offsetof(mxr_component_desc, data), sizeof(mxr_batch_job), offsetof(mxr_batch_job, tallies), sizeof(mxr_batch_schedule), sizeof(mxr_hits));return 0;}
+int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mxr_component_desc), sizeof(mxr_tally), sizeof(mxr_ray_soa), offsetof(mxr_component_desc, data), sizeof(mxr_batch_job), offsetof(mxr_batch_job, tallies), sizeof(mxr_batch_schedule), sizeof(mxr_hits), sizeof(mxr_train_rows), offsetof(mxr_train_rows, floor_frac));return 0;}
 '''
     import tempfile
     with tempfile.TemporaryDirectory() as d:
@@ -84,3 +89,5 @@ int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mxr_component_
     assert sizes[5] == m.mxr_batch_job.tallies.offset
     assert sizes[6] == ctypes.sizeof(m.mxr_batch_schedule) == 16
     assert sizes[7] == ctypes.sizeof(m.mxr_hits) == 72
+    assert sizes[8] == ctypes.sizeof(m.mxr_train_rows) == 80
+    assert sizes[9] == m.mxr_train_rows.floor_frac.offset
