@@ -393,6 +393,19 @@ mxr_status mxr_mlp_to_bf16(const float *x, uint64_t n, uint16_t *y, void *hip_st
 mxr_status mxr_mlp_forward(const uint16_t *w, const float *ctx, uint64_t n, float *out, void *ws, uint64_t ws_bytes,
                            void *hip_stream);
 
+/* mxr_mlp_forward for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): no workspace
+ * argument and no allocation; the layer values live in a static device array
+ * of 8 MiB that the library holds on each device it runs on until the
+ * process ends (its address is looked up once per device, on the first
+ * call).  At most MXR_MLP_NOALLOC_ROWS rows per call.  Calls on one device
+ * share that array: calls that overlap on one device (on different streams,
+ * or from several host threads) race and must not be issued.  No part of the
+ * array needs clearing between calls.  Errors: MXR_E_INVALID (null arrays,
+ * n above the limit), MXR_E_HIP. */
+#define MXR_MLP_NOALLOC_ROWS 4096u
+mxr_status mxr_mlp_forward_noalloc(const uint16_t *w, const float *ctx, uint64_t n, float *out, void *hip_stream);
+
 /* Mixture tables for mxr_proposal_set from outputs: gmm (n x 56 f64, per
  * row 8 x (pi, mu[3], sigma[3])), with the source's box lo / hi (host, 3
  * doubles each: -tan a, -tan a, emin / tan a, tan a, emax). */

@@ -100,6 +100,7 @@ class mxr_batch_schedule(ctypes.Structure):
 
 
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 6, 128, 56, 24632
+MLP_NOALLOC_ROWS = 4096
 WS_REGIONS = ("X", "Z1", "H1", "Z2", "H2", "O", "DO", "DOH", "DZ2", "DZ2H", "DZ1", "DZ1H", "PARTIAL", "Y", "W",
               "ROWLOSS", "SCALARS", "WT", "COLS")
 
@@ -184,6 +185,8 @@ def _load() -> ctypes.CDLL:
     lib.mxr_mlp_to_bf16.restype = ctypes.c_int
     lib.mxr_mlp_forward.argtypes = [P, P, U64, P, P, U64, P]
     lib.mxr_mlp_forward.restype = ctypes.c_int
+    lib.mxr_mlp_forward_noalloc.argtypes = [P, P, U64, P, P]
+    lib.mxr_mlp_forward_noalloc.restype = ctypes.c_int
     lib.mxr_mlp_mixture.argtypes = [P, U64, D3, D3, P, P]
     lib.mxr_mlp_mixture.restype = ctypes.c_int
     lib.mxr_mlp_loss_grad.argtypes = [P, P, P, P, U64, D3, D3, P, P, P, U64, P]
@@ -301,6 +304,10 @@ def mxr_mlp_to_bf16(x_ptr: int, n: int, y_ptr: int, stream=None) -> None:
 
 def mxr_mlp_forward(w_ptr, ctx_ptr, n, out_ptr, ws_ptr, ws_bytes, stream=None) -> None:
     _check(lib.mxr_mlp_forward(w_ptr, ctx_ptr, n, out_ptr, ws_ptr, ws_bytes, _stream_handle(stream)))
+
+
+def mxr_mlp_forward_noalloc(w_ptr, ctx_ptr, n, out_ptr, stream=None) -> None:
+    _check(lib.mxr_mlp_forward_noalloc(w_ptr, ctx_ptr, n, out_ptr, _stream_handle(stream)))
 
 
 def mxr_mlp_mixture(out_ptr, n, lo, hi, gmm_ptr, stream=None) -> None:

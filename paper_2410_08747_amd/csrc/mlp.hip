@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "mxr.h"
@@ -561,6 +562,56 @@ Layout layout_for(uint64_t n) {
     return L;
 }
 
+// Layout of a forward pass alone: the context, the layer values, the
+// outputs and the transposed weights; the training regions are empty.
+Layout layout_forward(uint64_t n) {
+    uint64_t sizes[MXR_MLP_WS_REGIONS] = {0};
+    sizes[MXR_MLP_WS_X] = n * kIn * 2;
+    sizes[MXR_MLP_WS_Z1] = n * kHid * 4;
+    sizes[MXR_MLP_WS_H1] = n * kHid * 2;
+    sizes[MXR_MLP_WS_Z2] = n * kHid * 4;
+    sizes[MXR_MLP_WS_H2] = n * kHid * 2;
+    sizes[MXR_MLP_WS_O] = n * kOut * 4;
+    sizes[MXR_MLP_WS_WT] = kParams * 2;
+    Layout L;
+    uint64_t o = 0;
+    for (int i = 0; i < MXR_MLP_WS_REGIONS; ++i) {
+        L.off[i] = o;
+        o += (sizes[i] + 255) / 256 * 256;
+    }
+    L.bytes = o;
+    return L;
+}
+
+// Scratch of mxr_mlp_forward_noalloc: the layer values of up to
+// kScratchRows rows, in a device array the library holds on every device it
+// runs on until the process ends.  Host code reaches it only through the
+// address hipGetSymbolAddress gives on that device.
+constexpr uint64_t kScratchRows = MXR_MLP_NOALLOC_ROWS;
+constexpr uint64_t kScratchBytes = 8ull << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device.
+mxr_status scratch_address(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(MXR_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MXR_E_UNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(MXR_E_HIP, "address of the static scratch: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MXR_OK;
+}
+
 template <class T>
 T *at(void *ws, const Layout &L, int region) {
     return (T *)((char *)ws + L.off[region]);
@@ -724,6 +775,29 @@ mxr_status mxr_mlp_forward(const uint16_t *w, const float *ctx, uint64_t n, floa
     if (s != MXR_OK) return s;
     const Layout L = layout_for(n);
     if (ws_bytes < L.bytes) return fail(MXR_E_INVALID, "workspace of %llu bytes, %llu needed", (unsigned long long)ws_bytes, (unsigned long long)L.bytes);
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(n)), dim3(kThreads), 0, st, ctx, (const double *)nullptr,
+                       (const double *)nullptr, n, (uint64_t)1, (uint64_t)0, (uint64_t)0, n,
+                       at<uint16_t>(ws, L, MXR_MLP_WS_X), (double *)nullptr, (double *)nullptr);
+    if ((s = launch_check("gather")) != MXR_OK) return s;
+    if ((s = forward_ws(w, n, ws, L, st)) != MXR_OK) return s;
+    hipError_t e = hipMemcpyAsync(out, at<float>(ws, L, MXR_MLP_WS_O), n * kOut * sizeof(float),
+                                  hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return fail(MXR_E_HIP, "copy of the outputs: %s", hipGetErrorString(e));
+    return MXR_OK;
+}
+
+mxr_status mxr_mlp_forward_noalloc(const uint16_t *w, const float *ctx, uint64_t n, float *out, void *hip_stream) {
+    if (n == 0) return MXR_OK;
+    mxr_status s = check_device_ptrs({w, ctx, out});
+    if (s != MXR_OK) return s;
+    if (n > kScratchRows)
+        return fail(MXR_E_INVALID, "%llu rows: the allocation-free forward takes at most %llu rows per call",
+                    (unsigned long long)n, (unsigned long long)kScratchRows);
+    const Layout L = layout_forward(n);
+    if (L.bytes > kScratchBytes) return fail(MXR_E_INVALID, "the forward's layer values exceed the static scratch");
+    void *ws = nullptr;
+    if ((s = scratch_address(&ws)) != MXR_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
     hipLaunchKernelGGL(k_gather, dim3(blocks_for(n)), dim3(kThreads), 0, st, ctx, (const double *)nullptr,
                        (const double *)nullptr, n, (uint64_t)1, (uint64_t)0, (uint64_t)0, n,
