@@ -226,6 +226,24 @@ mxr_status mxr_instrument_create(const mxr_instrument_desc *desc, mxr_instrument
  * NULL is accepted. */
 void mxr_instrument_destroy(mxr_instrument *ins);
 
+/* Launch shape of an instrument's plain runs (mxr_run without a ledger or a
+ * proposal).  It changes how rays are mapped onto the device, never which
+ * rays are traced or their results (per bin up to the order of the atomic
+ * additions).
+ *   occupancy  waves per SIMD the run kernel is compiled for: 0 the chain's
+ *              own, or 4, 6, 8 (fixed chains only; others ignore it)
+ *   compact    1: chains with a crop right after the source run the
+ *              survivor-compacting kernel; 0: one ray per lane
+ *   rounds     compacting kernel: 64-ray rounds per wave, 1..64 (0 = 64)
+ *   xcd_order  0: the i-th of the eight XCDs traces the i-th eighth of the
+ *              ray range; 1: work-groups take ray tiles in launch order */
+typedef struct {
+    uint32_t occupancy;
+    uint32_t compact;
+    uint32_t rounds;
+    uint32_t xcd_order;
+} mxr_launch_shape;
+
 /* Traces rays [first_ray, first_ray + n_rays) of an n_total-ray run and
  * adds their histograms into tallies[0 .. n_tallies) (one per monitor, in
  * instrument order, n_bins = nx*ny*ne each).  ledger (nullable, device,
@@ -245,6 +263,31 @@ mxr_status mxr_run(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays, uin
 mxr_status mxr_trace_rays(mxr_instrument *ins, const uint64_t *ray_ids, uint64_t n, uint64_t n_total,
                           uint64_t seed, uint32_t purpose, uint32_t job, const mxr_ray_soa *out,
                           void *hip_stream);
+
+/* Current launch shape of the instrument's plain runs. */
+mxr_status mxr_get_launch_shape(const mxr_instrument *ins, mxr_launch_shape *out);
+
+/* Sets the launch shape (validated: occupancy in {0, 4, 6, 8}, compact in
+ * {0, 1}, rounds <= 64, xcd_order in {0, 1}).  Errors: MXR_E_INVALID. */
+mxr_status mxr_set_launch_shape(mxr_instrument *ins, const mxr_launch_shape *shape);
+
+/* Autotuner of an instrument's plain runs (paper, section 2.2: the
+ * simulation is parallel over rays, so the mapping of rays onto the device
+ * is free; the kernels' occupancy and ray order are the levers measured
+ * here): times each candidate shape -- occupancy 0/4/6/8 for fixed chains,
+ * both XCD ray orders, and for chains with a crop after the source the
+ * compacting kernel at 64 or 16 rounds or none -- on rays [0, n) of an
+ * n_total-ray run, n = max(1, rays_fraction n_total), after one untimed run
+ * each; keeps the fastest and records it under a key of the instrument
+ * (component chain, exactness of the phantom's planes, phantom and monitor
+ * sizes, the run size's power of two) in the text file cache_path
+ * (nullable), which later calls consult before timing anything.  The chosen
+ * shape is set on the instrument and returned in out (nullable).  The
+ * timing runs ADD into tallies: zero them before the production run.
+ * Synchronous.  Errors: as mxr_run, MXR_E_INVALID for rays_fraction outside
+ * (0, 1]. */
+mxr_status mxr_autotune_instrument(mxr_instrument *ins, uint64_t n_total, double rays_fraction, const mxr_tally *tallies,
+                                   uint32_t n_tallies, const char *cache_path, mxr_launch_shape *out);
 
 /* ------------------------------------------------------------------------
  * Importance sampling of the cone-beam source by a learned proposal.

@@ -105,6 +105,11 @@ WS_REGIONS = ("X", "Z1", "H1", "Z2", "H2", "O", "DO", "DOH", "DZ2", "DZ2H", "DZ1
               "ROWLOSS", "SCALARS", "WT", "COLS")
 
 
+class mxr_launch_shape(ctypes.Structure):
+    _fields_ = [("occupancy", ctypes.c_uint32), ("compact", ctypes.c_uint32), ("rounds", ctypes.c_uint32),
+                ("xcd_order", ctypes.c_uint32)]
+
+
 class mxr_train_cfg(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("batch", ctypes.c_uint32), ("epochs", ctypes.c_uint32), ("seed", ctypes.c_uint64),
@@ -198,6 +203,13 @@ def _load() -> ctypes.CDLL:
     lib.mxr_train_weights.restype = ctypes.c_int
     lib.mxr_mlp_train.argtypes = [P, P, P, U64, ctypes.POINTER(mxr_train_cfg), D3, D3, P, P, P, P, P, P, U64, P, P]
     lib.mxr_mlp_train.restype = ctypes.c_int
+    lib.mxr_get_launch_shape.argtypes = [P, ctypes.POINTER(mxr_launch_shape)]
+    lib.mxr_get_launch_shape.restype = ctypes.c_int
+    lib.mxr_set_launch_shape.argtypes = [P, ctypes.POINTER(mxr_launch_shape)]
+    lib.mxr_set_launch_shape.restype = ctypes.c_int
+    lib.mxr_autotune_instrument.argtypes = [P, U64, ctypes.c_double, ctypes.POINTER(mxr_tally), ctypes.c_uint32,
+                                            ctypes.c_char_p, ctypes.POINTER(mxr_launch_shape)]
+    lib.mxr_autotune_instrument.restype = ctypes.c_int
     lib.mxr_proposal_box.argtypes = [P, D3, D3]
     lib.mxr_proposal_box.restype = ctypes.c_int
     lib.mxr_proposal_train.argtypes = [P, ctypes.POINTER(mxr_train_rows), ctypes.POINTER(mxr_train_cfg), P, P, P, P,
@@ -332,6 +344,25 @@ def mxr_mlp_train(ctx, y, omega, n_rows, cfg: mxr_train_cfg, lo, hi, master, w, 
                   stream=None) -> None:
     _check(lib.mxr_mlp_train(ctx, y, omega, n_rows, ctypes.byref(cfg), _d3(lo), _d3(hi), master, w, m, v, grad, ws,
                              ws_bytes, loss_log, _stream_handle(stream)))
+
+
+def mxr_get_launch_shape(handle: int) -> mxr_launch_shape:
+    out = mxr_launch_shape()
+    _check(lib.mxr_get_launch_shape(handle, ctypes.byref(out)))
+    return out
+
+
+def mxr_set_launch_shape(handle: int, shape: mxr_launch_shape) -> None:
+    _check(lib.mxr_set_launch_shape(handle, ctypes.byref(shape)))
+
+
+def mxr_autotune_instrument(handle: int, n_total: int, rays_fraction: float, tallies: Sequence[mxr_tally],
+                            cache_path: Optional[str] = None) -> mxr_launch_shape:
+    arr = (mxr_tally * max(1, len(tallies)))(*tallies)
+    out = mxr_launch_shape()
+    _check(lib.mxr_autotune_instrument(handle, n_total, rays_fraction, arr, len(tallies),
+                                       cache_path.encode() if cache_path else None, ctypes.byref(out)))
+    return out
 
 
 def mxr_proposal_box(handle: int):
@@ -570,6 +601,24 @@ class Instrument:
         assert gmm.dtype.is_floating_point and gmm.numel() == 56 and gmm.is_cuda
         g = gmm.reshape(56).to(dtype=__import__("torch").float64).contiguous()
         mxr_proposal_set(self.handle, g.data_ptr(), alpha)
+
+    @property
+    def launch_shape(self):
+        """(occupancy, compact, rounds, xcd_order) of plain runs."""
+        s = mxr_get_launch_shape(self.handle)
+        return (s.occupancy, s.compact, s.rounds, s.xcd_order)
+
+    @launch_shape.setter
+    def launch_shape(self, value) -> None:
+        mxr_set_launch_shape(self.handle, mxr_launch_shape(*[int(v) for v in value]))
+
+    def autotune(self, n_total: int, rays_fraction: float, tallies=None, cache_path: Optional[str] = None):
+        """mxr_autotune_instrument; timing runs add into ``tallies`` (new ones
+        if None).  Returns the chosen shape."""
+        if tallies is None:
+            tallies = self.new_tallies()
+        s = mxr_autotune_instrument(self.handle, n_total, rays_fraction, self.tally_structs(tallies), cache_path)
+        return (s.occupancy, s.compact, s.rounds, s.xcd_order)
 
     def proposal_box(self):
         """(lo, hi) of the cone-beam source's proposal coordinates (u, v, E)."""

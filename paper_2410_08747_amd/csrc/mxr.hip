@@ -313,8 +313,8 @@ __device__ __forceinline__ bool run_chain(Chain<Ts...>, const DevInstr *ins, Ray
 // work-group b is remapped to the b/8-th slot of the (b mod 8)-th eighth of
 // the ray range: each XCD traces a contiguous block of ray ids, which the
 // stratified source sends through neighbouring voxels and pixels.
-template <class C, bool LEDGER, bool TRACE, bool EXACT>
-__global__ __launch_bounds__(kBlock, WavesHint<C>::value) void k_trace(const DevInstr *__restrict__ ins, RunArgs a) {
+template <class C, bool LEDGER, bool TRACE, bool EXACT, int WAVES = WavesHint<C>::value>
+__global__ __launch_bounds__(kBlock, WAVES) void k_trace(const DevInstr *__restrict__ ins, RunArgs a) {
     extern __shared__ double smem[];
     const uint32_t n_mat = ins->n_mat, n_ebin = ins->n_ebin;
     double *mu_lds = smem;
@@ -335,7 +335,8 @@ __global__ __launch_bounds__(kBlock, WavesHint<C>::value) void k_trace(const Dev
     }
     __syncthreads();
 
-    const uint64_t logical = (uint64_t)(blockIdx.x & 7u) * a.blocks_per_xcd + (blockIdx.x >> 3);
+    const uint64_t logical = a.xcd_order ? (uint64_t)blockIdx.x
+                                         : (uint64_t)(blockIdx.x & 7u) * a.blocks_per_xcd + (blockIdx.x >> 3);
     const uint64_t i = logical * kBlock + threadIdx.x;
     if (i < a.n) {
         const uint64_t ray_id = TRACE ? a.ids[i] : a.first + i;
@@ -476,7 +477,8 @@ __global__ __launch_bounds__(kBlock, WavesHint<C>::value) void k_trace_compact(c
     L.tl_nb = tl_nb;
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     uint64_t *Q = queue[wave];
-    const uint64_t logical = (uint64_t)(blockIdx.x & 7u) * a.blocks_per_xcd + (blockIdx.x >> 3);
+    const uint64_t logical = a.xcd_order ? (uint64_t)blockIdx.x
+                                         : (uint64_t)(blockIdx.x & 7u) * a.blocks_per_xcd + (blockIdx.x >> 3);
     const uint64_t per_wave = 64ull * a.compact_rounds;
     const uint64_t wbase = (logical * (kBlock / 64) + wave) * per_wave;
     const uint64_t wend = wbase + per_wave < a.n ? wbase + per_wave : a.n;
@@ -721,7 +723,31 @@ struct KernelSet {
         if (trace) return ledger ? k_trace<C, true, true, EXACT> : k_trace<C, false, true, EXACT>;
         return ledger ? k_trace<C, true, false, EXACT> : k_trace<C, false, false, EXACT>;
     }
+    // the plain run kernel compiled for another occupancy (waves per SIMD;
+    // 0: the chain's own)
+    static KernelFn plain(uint32_t waves) {
+        switch (waves) {
+            case 4: return k_trace<C, false, false, EXACT, 4>;
+            case 6: return k_trace<C, false, false, EXACT, 6>;
+            case 8: return k_trace<C, false, false, EXACT, 8>;
+            default: return k_trace<C, false, false, EXACT>;
+        }
+    }
 };
+
+// plain run kernel of a fixed chain at an occupancy, or nullptr (generic chain)
+KernelFn pick_plain(int recipe, bool exact, uint32_t waves) {
+    switch (recipe) {
+        case kRecipeBasic: return KernelSet<ChainBasic, true>::plain(waves);
+        case kRecipeEdct: return exact ? KernelSet<ChainEdct, true>::plain(waves) : KernelSet<ChainEdct, false>::plain(waves);
+        case kRecipeBeamline: return KernelSet<ChainBeamline, true>::plain(waves);
+        case kRecipeEdctStep: return KernelSet<ChainEdctStep, true>::plain(waves);
+        case kRecipeCrl: return KernelSet<ChainCrl, true>::plain(waves);
+        case kRecipeEdctScatter:
+            return exact ? KernelSet<ChainEdctScatter, true>::plain(waves) : KernelSet<ChainEdctScatter, false>::plain(waves);
+        default: return nullptr;
+    }
+}
 
 enum RunMode { kModePlain = 0, kModeProposal, kModeCollect, kModeProposalCollect };
 
@@ -850,6 +876,7 @@ mxr_status set_error(mxr_status st, const char *msg) {
 }  // namespace mxr_host
 
 struct mxr_instrument {
+    mxr_launch_shape shape{0, 1, 0, 0};  // plain runs' launch shape (see mxr_set_launch_shape)
     int device;
     DevInstr host;
     DevInstr *dev;
@@ -1172,8 +1199,13 @@ static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, b
     const bool exact = ins->host.phantom < 0 || ins->host.c[ins->host.phantom].aux[4] != 0.0;
     const int mode = base.hits.count ? (base.prop ? kModeProposalCollect : kModeCollect)
                                      : (base.prop ? kModeProposal : kModePlain);
+    const bool plain = !ledger && !trace && mode == kModePlain;
     KernelFn k = pick_kernel(ins->recipe, ledger, trace, exact, mode);
-    KernelFn kc = (!ledger && !trace && mode == kModePlain) ? pick_compact(ins->recipe) : nullptr;
+    if (plain && ins->shape.occupancy) {
+        KernelFn ko = pick_plain(ins->recipe, exact, ins->shape.occupancy);
+        if (ko) k = ko;
+    }
+    KernelFn kc = (plain && ins->shape.compact) ? pick_compact(ins->recipe) : nullptr;
     size_t shmem = 0;
     if (ins->host.phantom >= 0) shmem += (size_t)ins->host.n_mat * ins->host.n_ebin * sizeof(double);
     if (ledger) shmem += (size_t)(4 * ins->host.ncomp + 1) * sizeof(double);
@@ -1205,8 +1237,11 @@ static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, b
             a.first = base.first + done;
         }
         // compacting kernel: as many rounds as keep >= 4 work-groups per CU
+        // (at most the shape's rounds, when it sets them)
         a.compact_rounds = (uint32_t)std::max<uint64_t>(
-            1, std::min<uint64_t>(kCompactRounds, m / ((uint64_t)kBlock * 4 * ins->n_cu)));
+            1, std::min<uint64_t>(ins->shape.rounds ? ins->shape.rounds : kCompactRounds,
+                                  m / ((uint64_t)kBlock * 4 * ins->n_cu)));
+        a.xcd_order = plain ? ins->shape.xcd_order : 0u;
         const uint64_t rays_per_group = kc ? (uint64_t)kBlock * a.compact_rounds : (uint64_t)kBlock;
         const uint64_t groups = (m + rays_per_group - 1) / rays_per_group;
         a.blocks_per_xcd = (uint32_t)((groups + 7) / 8);
@@ -1416,6 +1451,128 @@ mxr_status mxr_proposal_set(mxr_instrument *ins, const double *gmm, double alpha
     if (e != hipSuccess) return hip_fail(e, "upload of the proposal table");
     ins->prop_host = P;
     ins->prop_on = true;
+    return MXR_OK;
+}
+
+mxr_status mxr_get_launch_shape(const mxr_instrument *ins, mxr_launch_shape *out) {
+    if (!ins || !out) return fail(MXR_E_INVALID, "null instrument or shape");
+    *out = ins->shape;
+    return MXR_OK;
+}
+
+mxr_status mxr_set_launch_shape(mxr_instrument *ins, const mxr_launch_shape *shape) {
+    if (!ins || !shape) return fail(MXR_E_INVALID, "null instrument or shape");
+    const mxr_launch_shape &s = *shape;
+    if (!(s.occupancy == 0 || s.occupancy == 4 || s.occupancy == 6 || s.occupancy == 8) || s.compact > 1 ||
+        s.rounds > kCompactRounds || s.xcd_order > 1)
+        return fail(MXR_E_INVALID, "launch shape out of range (occupancy %u, compact %u, rounds %u, xcd order %u)",
+                    s.occupancy, s.compact, s.rounds, s.xcd_order);
+    ins->shape = s;
+    return MXR_OK;
+}
+
+// Tuning-cache key of an instrument's plain runs of about n_total rays.
+static std::string instrument_key(const mxr_instrument *ins, uint64_t n_total) {
+    const DevInstr &d = ins->host;
+    std::string k = "instrument recipe " + std::to_string(ins->recipe) + " chain";
+    for (uint32_t c = 0; c < d.ncomp; ++c) {
+        k += " " + std::to_string(d.c[c].type) + "/" + std::to_string(d.c[c].flags);
+        if (d.c[c].type == MXR_PHANTOM || d.c[c].type == MXR_DETECTOR)
+            k += ":" + std::to_string(d.c[c].dims[0]) + "x" + std::to_string(d.c[c].dims[1]) + "x" +
+                 std::to_string(d.c[c].dims[2]);
+    }
+    const bool exact = d.phantom < 0 || d.c[d.phantom].aux[4] != 0.0;
+    int lg = 0;
+    while (lg < 63 && (1ull << (lg + 1)) <= n_total) ++lg;
+    return k + " exact " + std::to_string(exact ? 1 : 0) + " log2n " + std::to_string(lg);
+}
+
+mxr_status mxr_autotune_instrument(mxr_instrument *ins, uint64_t n_total, double rays_fraction, const mxr_tally *tallies,
+                                   uint32_t n_tallies, const char *cache_path, mxr_launch_shape *out) {
+    if (!ins) return fail(MXR_E_INVALID, "null instrument");
+    if (!(rays_fraction > 0.0 && rays_fraction <= 1.0)) return fail(MXR_E_INVALID, "rays_fraction must be in (0, 1]");
+    if (n_total < 1) return fail(MXR_E_INVALID, "n_total must be positive");
+    const std::string key = instrument_key(ins, n_total);
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char line[1024];
+            bool found = false;
+            mxr_launch_shape hit{};
+            while (std::fgets(line, sizeof line, f)) {
+                char *tab = std::strchr(line, '\t');
+                if (!tab) continue;
+                *tab = 0;
+                mxr_launch_shape sh{};
+                if (key == line &&
+                    std::sscanf(tab + 1, "%u %u %u %u", &sh.occupancy, &sh.compact, &sh.rounds, &sh.xcd_order) == 4) {
+                    hit = sh;
+                    found = true;
+                }
+            }
+            std::fclose(f);
+            if (found && mxr_set_launch_shape(ins, &hit) == MXR_OK) {
+                if (out) *out = ins->shape;
+                return MXR_OK;
+            }
+        }
+    }
+    const bool fixed = pick_plain(ins->recipe, true, 0) != nullptr;
+    const bool compactable = pick_compact(ins->recipe) != nullptr;
+    std::vector<mxr_launch_shape> cand;
+    for (uint32_t occ : {0u, 4u, 6u, 8u}) {
+        if (occ && !fixed) continue;
+        for (uint32_t xo : {0u, 1u}) {
+            if (compactable) {
+                cand.push_back({occ, 1, 0, xo});
+                cand.push_back({occ, 1, 16, xo});
+            }
+            cand.push_back({occ, 0, 0, xo});
+        }
+    }
+    const uint64_t n = std::max<uint64_t>(1, (uint64_t)((double)n_total * rays_fraction));
+    const mxr_launch_shape saved = ins->shape;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipStreamCreate(&st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    mxr_status status = e == hipSuccess ? MXR_OK : hip_fail(e, "autotune stream and events");
+    float best_ms = 0.f;
+    mxr_launch_shape best = saved;
+    for (size_t c = 0; status == MXR_OK && c < cand.size(); ++c) {
+        ins->shape = cand[c];
+        float ms = 0.f;
+        for (int rep = 0; status == MXR_OK && rep < 2; ++rep) {  // the first run warms up
+            e = hipEventRecord(e0, st);
+            if (e == hipSuccess)
+                status = mxr_run(ins, 0, n, n_total, 1, 0, 0, tallies, n_tallies, nullptr, st);
+            if (status == MXR_OK) {
+                e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) status = hip_fail(e, "autotune timing");
+            }
+        }
+        if (status == MXR_OK && (best_ms == 0.f || ms < best_ms)) {
+            best_ms = ms;
+            best = cand[c];
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    if (status != MXR_OK) {
+        ins->shape = saved;
+        return status;
+    }
+    ins->shape = best;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "%s\t%u %u %u %u\n", key.c_str(), best.occupancy, best.compact, best.rounds, best.xcd_order);
+            std::fclose(f);
+        }
+    }
+    if (out) *out = best;
     return MXR_OK;
 }
 

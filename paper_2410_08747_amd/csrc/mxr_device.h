@@ -93,6 +93,7 @@ struct RunArgs {
     uint32_t word3;  // purpose << 24 | job
     uint32_t blocks_per_xcd;
     uint32_t compact_rounds;  // compacting kernel: 64-ray rounds per wave
+    uint32_t xcd_order;       // 0: XCD x traces the x-th eighth of the range; 1: work-groups in launch order
     TallyPtrs tally;
     double *ledger;
     const uint64_t *ids;  // trace mode: ray ids

@@ -33,7 +33,8 @@ def test_header_declares_the_api():
     for want in ("mxr_abi_version", "mxr_last_error", "mxr_instrument_create", "mxr_instrument_destroy",
                  "mxr_run", "mxr_trace_rays", "mxr_collect", "mxr_proposal_set", "mxr_proposal_box",
                  "mxr_proposal_train", "mxr_proposal_apply", "mxr_batch_create", "mxr_batch_run",
-                 "mxr_batch_autotune", "mxr_batch_means"):
+                 "mxr_batch_autotune", "mxr_batch_means", "mxr_autotune_instrument", "mxr_set_launch_shape",
+                 "mxr_get_launch_shape"):
         assert want in names
 
 
@@ -74,7 +75,7 @@ def test_binding_struct_layout(lib):
 #include <stdio.h>
 #include <stddef.h>
 #include "mxr.h"
-int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mxr_component_desc), sizeof(mxr_tally), sizeof(mxr_ray_soa), offsetof(mxr_component_desc, data), sizeof(mxr_batch_job), offsetof(mxr_batch_job, tallies), sizeof(mxr_batch_schedule), sizeof(mxr_hits), sizeof(mxr_train_rows), offsetof(mxr_train_rows, floor_frac));return 0;}
+int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mxr_component_desc), sizeof(mxr_tally), sizeof(mxr_ray_soa), offsetof(mxr_component_desc, data), sizeof(mxr_batch_job), offsetof(mxr_batch_job, tallies), sizeof(mxr_batch_schedule), sizeof(mxr_hits), sizeof(mxr_train_rows), offsetof(mxr_train_rows, floor_frac), sizeof(mxr_launch_shape));return 0;}
 '''
     import tempfile
     with tempfile.TemporaryDirectory() as d:
@@ -91,3 +92,4 @@ int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mxr_co
     assert sizes[7] == ctypes.sizeof(m.mxr_hits) == 72
     assert sizes[8] == ctypes.sizeof(m.mxr_train_rows) == 80
     assert sizes[9] == m.mxr_train_rows.floor_frac.offset
+    assert sizes[10] == ctypes.sizeof(m.mxr_launch_shape) == 16
