@@ -23,7 +23,7 @@ def test_workloads_listed():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
                        timeout=120, cwd=ROOT)
     assert r.returncode == 0
-    for w in ("projection", "batch", "learned", "train", "stepping", "crl", "scatter", "peaks"):
+    for w in ("projection", "batch", "learned", "train", "stepping", "crl", "scatter", "peaks", "basic", "beamline"):
         assert w in r.stdout
 
 
