@@ -65,10 +65,19 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
+// Hardware exponential, logarithm and reciprocal (v_exp_f32, v_log_f32,
+// v_rcp_f32: about an ulp each; the argument scaling adds a few ulp): the
+// activations they feed are rounded to bfloat16, and the head's float32 loss
+// gradient is checked to 3e-4 of a row's scale, so the ten-instruction IEEE
+// division and the full-range expf / logf buy nothing here.
+__device__ __forceinline__ float fexp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ float flog(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ float silu(float z) { return z * frcp(1.0f + fexp(-z)); }
 
 __device__ __forceinline__ float silu_grad(float z) {
-    const float s = 1.0f / (1.0f + expf(-z));
+    const float s = frcp(1.0f + fexp(-z));
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -337,7 +346,7 @@ struct HeadArgs {
     float *colpart;  // per wave (8 rows) column sums of dO, 56 per wave
 };
 
-__device__ __forceinline__ float phi_pdf(float z) { return 0.3989422804014327f * expf(-0.5f * z * z); }
+__device__ __forceinline__ float phi_pdf(float z) { return 0.3989422804014327f * fexp(-0.5f * z * z); }
 
 // mass of a standard normal in [za, zb], from the side that does not cancel
 __device__ __forceinline__ float box_mass(float za, float zb) {
@@ -359,56 +368,69 @@ __device__ __forceinline__ float group8_sum(float v) {
     return v + __shfl_xor(v, 4, 64);
 }
 
+// The head and loss gradient of one row, component k = this lane's index in
+// its group of eight (the eight lanes of a row are consecutive and take part
+// together).  o: the row's 56 outputs; y: its target; a: its loss weight
+// omega_i / sum omega.  g: dL/do of component k's seven outputs, scaled by a;
+// loss: a (-log q) of the row (every lane of the group).
+__device__ __forceinline__ void head_row(const float *o_row, const double *y_row, float a, const float lo[3],
+                                         const float hi[3], int k, float g[7], float &loss) {
+    const float *o = o_row + 7 * k;
+    const float lg = o[0];
+    const float mx = group8_max(lg);
+    const float lse_logit = mx + flog(group8_sum(fexp(lg - mx)));
+    const float pi = fexp(lg - lse_logit);
+    float c = lg - lse_logit, zk = 1.f;
+    float t[3], sg[3], z[3], za[3], zb[3], F[3], raw_s[3];
+    for (int d = 0; d < 3; ++d) {
+        const float cen = 0.5f * (lo[d] + hi[d]), half = 0.5f * (hi[d] - lo[d]);
+        t[d] = tanhf(o[1 + d]);
+        const float mu = cen + half * t[d];
+        raw_s[d] = o[4 + d];
+        const float sp = raw_s[d] > 20.f ? raw_s[d] : log1pf(fexp(raw_s[d]));
+        sg[d] = half * (1e-3f + sp);
+        const float is = frcp(sg[d]);
+        z[d] = ((float)y_row[d] - mu) * is;
+        za[d] = (lo[d] - mu) * is;
+        zb[d] = (hi[d] - mu) * is;
+        F[d] = box_mass(za[d], zb[d]);
+        c += -0.5f * z[d] * z[d] - flog(sg[d]) - 0.91893853f;
+        zk *= F[d];
+    }
+    const float cmax = group8_max(c);
+    const float lse = cmax + flog(group8_sum(fexp(c - cmax)));
+    const float S = group8_sum(pi * zk);
+    loss = a * (flog(S) - lse);
+    const float r = fexp(c - lse);
+    const float s = pi * zk * frcp(S);
+    g[0] = a * (s - r);
+    for (int d = 0; d < 3; ++d) {
+        const float half = 0.5f * (hi[d] - lo[d]);
+        const float pa = phi_pdf(za[d]), pb = phi_pdf(zb[d]);
+        const float is = frcp(sg[d]), iF = frcp(F[d]);
+        const float dF_mu = -(pb - pa) * is;
+        const float dF_sg = -(zb[d] * pb - za[d] * pa) * is;
+        const float g_mu = -r * z[d] * is + s * dF_mu * iF;
+        const float g_sg = -r * (z[d] * z[d] - 1.f) * is + s * dF_sg * iF;
+        g[1 + d] = a * (g_mu * half * (1.f - t[d] * t[d]));
+        g[4 + d] = a * (g_sg * half * frcp(1.f + fexp(-raw_s[d])));
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_head_loss_grad(HeadArgs h) {
     const uint64_t gt = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
     const uint64_t gi = gt >> 3;
     const int k = (int)(gt & 7);
     const bool live = gi < h.n;
     const uint64_t i = live ? gi : 0;  // groups past the end compute row 0 with weight 0
-    const float *o = h.O + i * kOut + 7 * k;
     const float a = live ? (float)(h.W[i] / *h.wsum) : 0.f;
-    const float lg = o[0];
-    const float mx = group8_max(lg);
-    const float lse_logit = mx + logf(group8_sum(expf(lg - mx)));
-    const float pi = expf(lg - lse_logit);
-    float c = lg - lse_logit, zk = 1.f;
-    float t[3], sg[3], z[3], za[3], zb[3], F[3], raw_s[3];
-    for (int d = 0; d < 3; ++d) {
-        const float cen = 0.5f * (h.lo[d] + h.hi[d]), half = 0.5f * (h.hi[d] - h.lo[d]);
-        t[d] = tanhf(o[1 + d]);
-        const float mu = cen + half * t[d];
-        raw_s[d] = o[4 + d];
-        const float sp = raw_s[d] > 20.f ? raw_s[d] : log1pf(expf(raw_s[d]));
-        sg[d] = half * (1e-3f + sp);
-        z[d] = ((float)h.Y[i * 3 + d] - mu) / sg[d];
-        za[d] = (h.lo[d] - mu) / sg[d];
-        zb[d] = (h.hi[d] - mu) / sg[d];
-        F[d] = box_mass(za[d], zb[d]);
-        c += -0.5f * z[d] * z[d] - logf(sg[d]) - 0.91893853f;
-        zk *= F[d];
-    }
-    const float cmax = group8_max(c);
-    const float lse = cmax + logf(group8_sum(expf(c - cmax)));
-    const float S = group8_sum(pi * zk);
-    if (live && k == 0) h.row_loss[i] = (double)(a * (logf(S) - lse));
-    const float r = expf(c - lse);
-    const float s = pi * zk / S;
-    float g[7];
-    g[0] = s - r;
-    for (int d = 0; d < 3; ++d) {
-        const float half = 0.5f * (h.hi[d] - h.lo[d]);
-        const float pa = phi_pdf(za[d]), pb = phi_pdf(zb[d]);
-        const float dF_mu = -(pb - pa) / sg[d];
-        const float dF_sg = -(zb[d] * pb - za[d] * pa) / sg[d];
-        const float g_mu = -r * z[d] / sg[d] + s * dF_mu / F[d];
-        const float g_sg = -r * (z[d] * z[d] - 1.f) / sg[d] + s * dF_sg / F[d];
-        g[1 + d] = g_mu * half * (1.f - t[d] * t[d]);
-        g[4 + d] = g_sg * half / (1.f + expf(-raw_s[d]));
-    }
+    float g[7], loss;
+    head_row(h.O + i * kOut, h.Y + i * 3, a, h.lo, h.hi, k, g, loss);
+    if (live && k == 0) h.row_loss[i] = (double)loss;
     const uint64_t wave = gt >> 6;  // 8 rows per wave
     const bool writer = (threadIdx.x & 63) < 8 && (wave << 3) < h.n;
     for (int j = 0; j < 7; ++j) {
-        const float v = a * g[j];
+        const float v = g[j];
         if (live) {
             h.dO[i * kOut + 7 * k + j] = v;
             h.dOh[i * kOut + 7 * k + j] = f32_to_bf16(v);
@@ -477,6 +499,339 @@ __global__ void k_to_bf16(const float *x, uint64_t n, uint16_t *y) {
     if (i < n) y[i] = f32_to_bf16(x[i]);
 }
 
+// ----------------------------------------------- fused training step --
+// One launch computes a whole Adam step's gradient: work-group g takes the
+// 32-row strips g, g + G, g + 2G, ... of the batch and, per strip, gathers
+// its rows, runs the three layers forward, the head and its loss gradient,
+// and the backward products, with the bfloat16 weights staged once in LDS
+// and every layer value of the strip in LDS (nothing but the rows goes to
+// or comes from memory).  The weight gradients accumulate across the
+// group's strips in the MFMA accumulators; the group then writes one
+// partial gradient, and k_fused_reduce_adam sums the G partials in order
+// (deterministic) and takes the Adam step.  The products, operands and
+// roundings are those of the layer-by-layer path (bf16 operands, f32
+// accumulation, f32 pre-activations, bf16 copies of activations and
+// gradients), only the order of the float32 sums differs.
+constexpr int kStripRows = 32;
+constexpr int kFusedGroups = 256;
+
+struct FusedArgs {
+    const float *ctx;
+    const double *y, *omega;
+    uint64_t n_data, a, b, first, cnt;  // batch row i = data row (a (first + i) mod n_data + b) mod n_data
+    const double *wsum;                 // sum of the batch's omega
+    const uint16_t *w;                  // bfloat16 parameters
+    float lo[3], hi[3];
+    float *part;                        // gridDim.x x kParams partial gradients
+    double *loss_part;                  // gridDim.x partial losses
+};
+
+__device__ __forceinline__ v4s frag_c(const uint16_t *p) { return *(const v4s *)p; }
+__device__ __forceinline__ v4s frag_s(const uint16_t *p, int stride) {
+    v4s r;
+    r[0] = (short)p[0];
+    r[1] = (short)p[stride];
+    r[2] = (short)p[2 * stride];
+    r[3] = (short)p[3 * stride];
+    return r;
+}
+__device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+constexpr int kFusedThreads = 512;  // eight waves: two per SIMD
+
+__global__ __launch_bounds__(kFusedThreads, 1) void k_train_fused(FusedArgs f) {
+    constexpr int R = kStripRows, H = kHid, O64 = 64, X16 = 16;
+    __shared__ __attribute__((aligned(16))) uint16_t sW1t[H * X16];  // W1 transposed (out x in), in >= 6 zero
+    __shared__ __attribute__((aligned(16))) uint16_t sW2[H * H];     // W2 (in x out)
+    __shared__ __attribute__((aligned(16))) uint16_t sW3[H * O64];   // W3 (in x out), out >= 56 zero
+    __shared__ __attribute__((aligned(16))) float sB1[H], sB2[H], sB3[O64];
+    __shared__ __attribute__((aligned(16))) uint16_t sX[R * X16];
+    __shared__ __attribute__((aligned(16))) double sY[R * 3];
+    __shared__ __attribute__((aligned(16))) float sA[R];
+    __shared__ __attribute__((aligned(16))) float sZ1[R * H];  // pre-activations of layer 1
+    __shared__ __attribute__((aligned(16))) uint16_t sH1[R * H];
+    __shared__ __attribute__((aligned(16))) float sZ2[R * H];  // layer 2; then dZ1 (bf16) in its first half
+    __shared__ __attribute__((aligned(16))) uint16_t sH2[R * H];
+    __shared__ __attribute__((aligned(16))) float sO[R * O64];  // outputs; then dZ2 (bf16 R x H) in the same bytes
+    __shared__ __attribute__((aligned(16))) uint16_t sdO[R * O64];
+    __shared__ __attribute__((aligned(16))) uint64_t sSrc[R];
+    __shared__ __attribute__((aligned(16))) float sRed[4 * 64];
+    __shared__ __attribute__((aligned(16))) double sLoss[kFusedThreads];
+    uint16_t *sdZ2 = (uint16_t *)sO;
+    uint16_t *sdZ1 = (uint16_t *)sZ2;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, q = lane >> 4;
+    // weights and biases, once
+    for (int i = tid; i < H * X16; i += kFusedThreads) {
+        const int n = i / X16, k = i % X16;
+        sW1t[i] = k < kIn ? f.w[kW1 + k * H + n] : (uint16_t)0;
+    }
+    for (int i = tid; i < H * H; i += kFusedThreads) sW2[i] = f.w[kW2 + i];
+    for (int i = tid; i < H * O64; i += kFusedThreads) {
+        const int k = i / O64, n = i % O64;
+        sW3[i] = n < kOut ? f.w[kW3 + k * kOut + n] : (uint16_t)0;
+    }
+    for (int i = tid; i < H; i += kFusedThreads) {
+        sB1[i] = bf16_to_f32(f.w[kB1 + i]);
+        sB2[i] = bf16_to_f32(f.w[kB2 + i]);
+    }
+    for (int i = tid; i < O64; i += kFusedThreads) sB3[i] = i < kOut ? bf16_to_f32(f.w[kB3 + i]) : 0.f;
+    for (int i = tid; i < R * O64; i += kFusedThreads) sdO[i] = 0;  // columns >= 56 stay zero
+    const double wsum = *f.wsum;
+    // wave w owns column tile w of the row-strip products and row tile w of
+    // the weight-gradient products
+    v4f acc1 = {0.f, 0.f, 0.f, 0.f}, acc2[8], acc3[4];
+    for (int t = 0; t < 8; ++t) acc2[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 4; ++t) acc3[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    float db1 = 0.f, db2 = 0.f, db3[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    double loss_acc = 0.0;
+    const uint64_t n_strips = (f.cnt + R - 1) / R;
+    const int nt = wave;
+    __syncthreads();
+
+    for (uint64_t strip = blockIdx.x; strip < n_strips; strip += gridDim.x) {
+        // rows of the strip (rows past the batch repeat its first row with
+        // weight 0): their data rows, then one element per thread
+        if (tid < R) {
+            const uint64_t i = strip * R + tid;
+            const bool live = i < f.cnt;
+            sSrc[tid] = ((f.a * (f.first + (live ? i : 0))) % f.n_data + f.b) % f.n_data;
+        }
+        __syncthreads();
+        for (int e = tid; e < R * 10; e += kFusedThreads) {
+            const int row = e / 10, item = e % 10;
+            const uint64_t src = sSrc[row];
+            if (item < kIn) sX[row * X16 + item] = f32_to_bf16(f.ctx[src * kIn + item]);
+            else if (item < kIn + 3) sY[row * 3 + item - kIn] = f.y[src * 3 + item - kIn];
+            else sA[row] = (strip * R + row < f.cnt) ? (float)(f.omega[src] / wsum) : 0.f;
+        }
+        for (int e = tid; e < R * (X16 - kIn); e += kFusedThreads)
+            sX[(e / (X16 - kIn)) * X16 + kIn + e % (X16 - kIn)] = 0;
+        __syncthreads();
+        // layer 1: Z1 = X W1 + b1 (K = 6, padded to 16)
+        {
+            const v4s b = frag_c(sW1t + (nt * 16 + r) * X16 + 4 * q);
+            v4f c[2];
+            for (int mt = 0; mt < 2; ++mt)
+                c[mt] = mfma16(frag_c(sX + (mt * 16 + r) * X16 + 4 * q), b, v4f{0.f, 0.f, 0.f, 0.f});
+            for (int mt = 0; mt < 2; ++mt)
+                for (int j = 0; j < 4; ++j) {
+                    const int m = mt * 16 + 4 * q + j, n = nt * 16 + r;
+                    const float z = c[mt][j] + sB1[n];
+                    sZ1[m * H + n] = z;
+                    sH1[m * H + n] = f32_to_bf16(silu(z));
+                }
+        }
+        __syncthreads();
+        // layer 2: Z2 = H1 W2 + b2 (the two row tiles' chains interleaved)
+        {
+            v4f c[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int k0 = 0; k0 < H; k0 += 16) {
+                const v4s b = frag_s(sW2 + (k0 + 4 * q) * H + nt * 16 + r, H);
+                c[0] = mfma16(frag_c(sH1 + r * H + k0 + 4 * q), b, c[0]);
+                c[1] = mfma16(frag_c(sH1 + (16 + r) * H + k0 + 4 * q), b, c[1]);
+            }
+            for (int mt = 0; mt < 2; ++mt)
+                for (int j = 0; j < 4; ++j) {
+                    const int m = mt * 16 + 4 * q + j, n = nt * 16 + r;
+                    const float z = c[mt][j] + sB2[n];
+                    sZ2[m * H + n] = z;
+                    sH2[m * H + n] = f32_to_bf16(silu(z));
+                }
+        }
+        __syncthreads();
+        // layer 3: O = H2 W3 + b3 (outputs 56..63 are zero): 8 tiles, one per wave
+        {
+            const int mt = wave >> 2, ot = wave & 3;
+            v4f c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k0 = 0; k0 < H; k0 += 16)
+                c = mfma16(frag_c(sH2 + (mt * 16 + r) * H + k0 + 4 * q),
+                           frag_s(sW3 + (k0 + 4 * q) * O64 + ot * 16 + r, O64), c);
+            for (int j = 0; j < 4; ++j) {
+                const int m = mt * 16 + 4 * q + j, n = ot * 16 + r;
+                sO[m * O64 + n] = c[j] + sB3[n];
+            }
+        }
+        __syncthreads();
+        // head: eight lanes per row (lane k = component k), waves 0-3
+        if (tid < R * 8) {
+            const int i = tid >> 3, k = tid & 7;
+            float g[7], loss;
+            head_row(sO + i * O64, sY + i * 3, sA[i], f.lo, f.hi, k, g, loss);
+            if (k == 0) loss_acc += (double)loss;
+            for (int j = 0; j < 7; ++j) {
+                sdO[i * O64 + 7 * k + j] = f32_to_bf16(g[j]);
+                // this wave's 8 rows of the column: lanes k, k + 8, ..., k + 56
+                float cs = g[j];
+                cs += __shfl_xor(cs, 8, 64);
+                cs += __shfl_xor(cs, 16, 64);
+                cs += __shfl_xor(cs, 32, 64);
+                db3[j] += cs;
+            }
+        }
+        __syncthreads();
+        // dZ2 = (dO W3^T) * silu'(Z2), its column sums (bias 2)
+        {
+            v4f c[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int k0 = 0; k0 < O64; k0 += 16) {
+                const v4s b = frag_c(sW3 + (nt * 16 + r) * O64 + k0 + 4 * q);
+                c[0] = mfma16(frag_c(sdO + r * O64 + k0 + 4 * q), b, c[0]);
+                c[1] = mfma16(frag_c(sdO + (16 + r) * O64 + k0 + 4 * q), b, c[1]);
+            }
+            float cs = 0.f;
+            for (int mt = 0; mt < 2; ++mt)
+                for (int j = 0; j < 4; ++j) {
+                    const int m = mt * 16 + 4 * q + j, n = nt * 16 + r;
+                    const float dz = c[mt][j] * silu_grad(sZ2[m * H + n]);
+                    cs += dz;
+                    sdZ2[m * H + n] = f32_to_bf16(dz);
+                }
+            cs += __shfl_xor(cs, 16, 64);
+            cs += __shfl_xor(cs, 32, 64);
+            db2 += cs;
+        }
+        __syncthreads();
+        // dW3 += H2^T dO (in x out over the strip's rows): row tile = wave
+        {
+            const int mt = wave;
+#pragma unroll
+            for (int k0 = 0; k0 < R; k0 += 16) {
+                const v4s a = frag_s(sH2 + (k0 + 4 * q) * H + mt * 16 + r, H);
+#pragma unroll
+                for (int ot = 0; ot < 4; ++ot)
+                    acc3[ot] = mfma16(a, frag_s(sdO + (k0 + 4 * q) * O64 + ot * 16 + r, O64), acc3[ot]);
+            }
+        }
+        // dZ1 = (dZ2 W2^T) * silu'(Z1), its column sums (bias 1); Z2 is no
+        // longer read, its bytes take dZ1
+        {
+            v4f c[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int k0 = 0; k0 < H; k0 += 16) {
+                const v4s b = frag_c(sW2 + (nt * 16 + r) * H + k0 + 4 * q);
+                c[0] = mfma16(frag_c(sdZ2 + r * H + k0 + 4 * q), b, c[0]);
+                c[1] = mfma16(frag_c(sdZ2 + (16 + r) * H + k0 + 4 * q), b, c[1]);
+            }
+            float cs = 0.f;
+            for (int mt = 0; mt < 2; ++mt)
+                for (int j = 0; j < 4; ++j) {
+                    const int m = mt * 16 + 4 * q + j, n = nt * 16 + r;
+                    const float dz = c[mt][j] * silu_grad(sZ1[m * H + n]);
+                    cs += dz;
+                    sdZ1[m * H + n] = f32_to_bf16(dz);
+                }
+            cs += __shfl_xor(cs, 16, 64);
+            cs += __shfl_xor(cs, 32, 64);
+            db1 += cs;
+        }
+        __syncthreads();
+        // dW2 += H1^T dZ2 (row tile = wave), dW1 += X^T dZ1 (column tile = wave)
+        {
+            const int mt = wave;
+#pragma unroll
+            for (int k0 = 0; k0 < R; k0 += 16) {
+                const v4s a = frag_s(sH1 + (k0 + 4 * q) * H + mt * 16 + r, H);
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    acc2[t] = mfma16(a, frag_s(sdZ2 + (k0 + 4 * q) * H + t * 16 + r, H), acc2[t]);
+                acc1 = mfma16(frag_s(sX + (k0 + 4 * q) * X16 + r, X16),
+                              frag_s(sdZ1 + (k0 + 4 * q) * H + nt * 16 + r, H), acc1);
+            }
+        }
+        __syncthreads();
+    }
+
+    // the group's partial gradient, in the parameter layout
+    float *P = f.part + (uint64_t)blockIdx.x * kParams;
+    {
+        const int mt = wave;
+        for (int t = 0; t < 8; ++t)
+            for (int j = 0; j < 4; ++j) P[kW2 + (mt * 16 + 4 * q + j) * H + t * 16 + r] = acc2[t][j];
+        for (int ot = 0; ot < 4; ++ot)
+            for (int j = 0; j < 4; ++j) {
+                const int n = ot * 16 + r;
+                if (n < kOut) P[kW3 + (mt * 16 + 4 * q + j) * kOut + n] = acc3[ot][j];
+            }
+        for (int j = 0; j < 4; ++j) {
+            const int m = 4 * q + j;
+            if (m < kIn) P[kW1 + m * H + nt * 16 + r] = acc1[j];
+        }
+        if (q == 0) {
+            P[kB1 + nt * 16 + r] = db1;
+            P[kB2 + nt * 16 + r] = db2;
+        }
+    }
+    // bias 3: lanes 0..7 of waves 0-3 hold their waves' column sums
+    if (wave < 4 && lane < 8)
+        for (int j = 0; j < 7; ++j) sRed[wave * 64 + 7 * lane + j] = db3[j];
+    sLoss[tid] = loss_acc;
+    __syncthreads();
+    if (tid < kOut) P[kB3 + tid] = ((sRed[tid] + sRed[64 + tid]) + sRed[128 + tid]) + sRed[192 + tid];
+    if (tid == 0) {
+        double s = 0.0;
+        for (int i = 0; i < kFusedThreads; ++i) s += sLoss[i];
+        f.loss_part[blockIdx.x] = s;
+    }
+}
+
+// Sum of the batch's omega over the shuffled rows (the gathered order of the
+// layer-by-layer path; each work-group sums its stride into one partial).
+__global__ void k_batch_wsum(const double *omega, uint64_t n_data, uint64_t a, uint64_t b, uint64_t first,
+                             uint64_t cnt, double *partial) {
+    __shared__ double red[kThreads];
+    double s = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < cnt; i += (uint64_t)gridDim.x * kThreads)
+        s += omega[((a * (first + i)) % n_data + b) % n_data];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// gradient = the groups' partials summed in a fixed order (eight threads
+// per parameter each sum every eighth group, then their eight sums in
+// order), then one Adam step; the loss (nullable) = the partial losses
+// summed in order
+constexpr int kReduceParams = 32;  // parameters per work-group of 256 threads
+
+__global__ __launch_bounds__(256) void k_fused_reduce_adam(const float *part, int groups, float *grad, float *theta,
+                                                           uint16_t *wb, float *m, float *v, float lr, float b1,
+                                                           float b2, float eps, float c1, float c2,
+                                                           const double *loss_part, double *loss) {
+    __shared__ float red[8][kReduceParams];
+    const int sub = threadIdx.x >> 5, c = threadIdx.x & 31;
+    const uint64_t p = (uint64_t)blockIdx.x * kReduceParams + c;
+    if (loss && blockIdx.x == 0 && threadIdx.x == 0) {
+        double s = 0.0;
+        for (int g = 0; g < groups; ++g) s += loss_part[g];
+        *loss = s;
+    }
+    float acc = 0.f;
+    if (p < kParams)
+        for (int g = sub; g < groups; g += 8) acc += part[(uint64_t)g * kParams + p];
+    red[sub][c] = acc;
+    __syncthreads();
+    if (sub != 0 || p >= kParams) return;
+    float gi = 0.f;
+    for (int u = 0; u < 8; ++u) gi += red[u][c];
+    grad[p] = gi;
+    const float mi = b1 * m[p] + (1.f - b1) * gi;
+    const float vi = b2 * v[p] + (1.f - b2) * gi * gi;
+    m[p] = mi;
+    v[p] = vi;
+    const float t = theta[p] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    theta[p] = t;
+    wb[p] = f32_to_bf16(t);
+}
+
 // Training weights omega_i = w_i / max(I_b, floor), I_b = sum_w[b] / n_emitted
 // the bin's estimated intensity, floor = floor_frac * (mean I over bins with
 // hits): every live bin gets equal total weight, the proposal that makes the
@@ -536,6 +891,8 @@ struct Layout {
 };
 
 uint64_t splits_for(uint64_t n) { return std::max<uint64_t>(1, (n + kSplitRows - 1) / kSplitRows); }
+constexpr uint64_t kFusedGroupsMax = 256;  // the fused step's work-groups (kFusedGroups)
+static_assert(kFusedGroupsMax == (uint64_t)kFusedGroups, "partial region of the fused step");
 
 Layout layout_for(uint64_t n) {
     const uint64_t sizes[MXR_MLP_WS_REGIONS] = {
@@ -546,7 +903,7 @@ Layout layout_for(uint64_t n) {
         n * kOut * 4, n * kOut * 2,     // dO, dO (bf16)
         n * kHid * 4, n * kHid * 2,     // dZ2, dZ2 (bf16)
         n * kHid * 4, n * kHid * 2,     // dZ1, dZ1 (bf16)
-        splits_for(n) * kParams * 4,    // split partials of the gradient
+        std::max<uint64_t>(splits_for(n), kFusedGroupsMax) * kParams * 4,  // split / group partials of the gradient
         n * 3 * 8, n * 8, n * 8,        // gathered targets, weights, per-row loss
         (kSumBlocks + 2) * 8,           // reduction scratch + sum of weights + loss
         kParams * 2,                    // W^T copies (bf16), same offsets as W
@@ -913,17 +1270,45 @@ mxr_status mxr_mlp_train(const float *ctx, const double *y, const double *omega,
         }
         for (uint64_t k = 0; k < steps_per_epoch; ++k) {
             const uint64_t first = k * B, cnt = std::min<uint64_t>(B, n_rows - first);
-            hipLaunchKernelGGL(k_gather, dim3(blocks_for(cnt)), dim3(kThreads), 0, st, ctx, y, omega, n_rows, a, b,
-                               first, cnt, at<uint16_t>(ws, L, MXR_MLP_WS_X), at<double>(ws, L, MXR_MLP_WS_Y),
-                               at<double>(ws, L, MXR_MLP_WS_W));
-            if ((s = launch_check("gather")) != MXR_OK) return s;
             double *lp = loss_log ? loss_log + (uint64_t)e * steps_per_epoch + k : nullptr;
-            const Layout Lc = layout_for(B);  // the batch's layout also serves a shorter last batch
-            if ((s = loss_grad_ws(w, cnt, flo, fhi, grad, lp, ws, Lc, st)) != MXR_OK) return s;
             ++step;
-            if ((s = mxr_adam_step(master, w, grad, m, v, kParams, step, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps,
-                                   hip_stream)) != MXR_OK)
-                return s;
+            if (!(cfg->lr > 0.f) || !(cfg->beta1 >= 0.f && cfg->beta1 < 1.f) ||
+                !(cfg->beta2 >= 0.f && cfg->beta2 < 1.f) || !(cfg->eps >= 0.f))
+                return fail(MXR_E_INVALID, "bad Adam hyper-parameters");
+            // one fused launch per step: the batch's weight sum, the
+            // gradient partials of every strip, their ordered sum and Adam
+            double *red = at<double>(ws, L, MXR_MLP_WS_SCALARS), *wsum = red + kSumBlocks;
+            hipLaunchKernelGGL(k_batch_wsum, dim3(kSumBlocks), dim3(kThreads), 0, st, omega, n_rows, a, b, first, cnt,
+                               red);
+            hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(kThreads), 0, st, (const double *)red, (uint64_t)kSumBlocks,
+                               wsum);
+            FusedArgs fa;
+            fa.ctx = ctx;
+            fa.y = y;
+            fa.omega = omega;
+            fa.n_data = n_rows;
+            fa.a = a;
+            fa.b = b;
+            fa.first = first;
+            fa.cnt = cnt;
+            fa.wsum = wsum;
+            fa.w = w;
+            for (int d = 0; d < 3; ++d) {
+                fa.lo[d] = flo[d];
+                fa.hi[d] = fhi[d];
+            }
+            fa.part = at<float>(ws, L, MXR_MLP_WS_PARTIAL);
+            fa.loss_part = at<double>(ws, L, MXR_MLP_WS_ROWLOSS);
+            const uint64_t strips = (cnt + kStripRows - 1) / kStripRows;
+            const int groups = (int)std::min<uint64_t>(kFusedGroups, strips);
+            hipLaunchKernelGGL(k_train_fused, dim3(groups), dim3(kFusedThreads), 0, st, fa);
+            const float c1 = (float)(1.0 / (1.0 - std::pow((double)cfg->beta1, (double)step)));
+            const float c2 = (float)(1.0 / (1.0 - std::pow((double)cfg->beta2, (double)step)));
+            hipLaunchKernelGGL(k_fused_reduce_adam, dim3((unsigned)((kParams + kReduceParams - 1) / kReduceParams)),
+                               dim3(256), 0, st,
+                               (const float *)fa.part, groups, grad, master, w, m, v, cfg->lr, cfg->beta1, cfg->beta2,
+                               cfg->eps, c1, c2, (const double *)fa.loss_part, lp);
+            if ((s = launch_check("fused training step")) != MXR_OK) return s;
         }
     }
     return MXR_OK;

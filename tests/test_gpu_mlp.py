@@ -261,3 +261,43 @@ def test_training_lowers_the_loss(torch_cuda):
     assert after < before - 1.0, (before, after)
     assert lg[-5:].mean() < lg[:5].mean()
     assert net.step == steps
+
+
+@pytest.mark.parametrize("n", [4096, 65536, 1000, 45])
+def test_fused_step_gradient_equals_the_layered_gradient(torch_cuda, n):
+    """One training step over a whole batch (epochs = 1, batch = n): the
+    fused step's gradient (left in the gradient buffer) against the
+    layer-by-layer gradient of mxr_mlp_loss_grad on the same rows and
+    weights.  The operands and roundings are the same, only the order of the
+    float32 sums differs (strips of 32 rows summed per work-group, then the
+    groups in order, against 1024-row splits), so the two agree to float32
+    summation noise; the step's loss agrees as well.  Batches that are not a
+    multiple of the 32-row strip leave a partial strip."""
+    m = mxr()
+    import torch
+    announce("fused step vs layered gradient", n)
+    rng = np.random.default_rng(21 + n)
+    lo, hi = box()
+    y = np.stack([rng.uniform(lo[d], hi[d], n) for d in range(3)], 1)
+    ctx = rng.normal(size=(n, 6)).astype(np.float32)
+    omega = rng.uniform(0.1, 2.0, n)
+    p0 = P.init_params(3).astype(np.float32) + rng.normal(0, 0.05, 24632).astype(np.float32)
+    tc, ty, tw = (torch.tensor(a, device="cuda") for a in (ctx, y, omega))
+    ref = m.ProposalNet(p0, batch=n)
+    loss_ref, grad_ref = ref.loss_grad(tc, ty, tw, lo, hi)
+    g_ref = grad_ref.clone()
+    fused = m.ProposalNet(p0, batch=n)
+    log = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fused.train(tc, ty, tw, lo, hi, epochs=1, lr=1e-3, seed=9, loss_log=log)
+    torch.cuda.synchronize()
+    g = fused.grad.double().cpu().numpy()
+    r = g_ref.double().cpu().numpy()
+    rel = np.linalg.norm(g - r) / np.linalg.norm(r)
+    cos = float(g @ r / (np.linalg.norm(g) * np.linalg.norm(r)))
+    print(f"n={n}: gradient rel. difference {rel:.2e}, cosine {cos:.8f}; loss {float(log[0]):.6f} vs "
+          f"{float(loss_ref.item()):.6f}", flush=True)
+    assert rel < 2e-3 and cos > 0.99999
+    assert abs(float(log[0]) - float(loss_ref.item())) <= 1e-5 * max(1.0, abs(float(loss_ref.item())))
+    # the Adam step of the fused path from the same gradient: master - lr sign-ish step
+    assert torch.isfinite(fused.master).all()
+    assert fused.step == 1
