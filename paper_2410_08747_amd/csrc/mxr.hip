@@ -272,9 +272,12 @@ template <class C>
 struct BatchWavesHint {
     static constexpr int value = 1;
 };
+#ifndef MXR_BATCH_WAVES
+#define MXR_BATCH_WAVES 8
+#endif
 template <>
 struct BatchWavesHint<Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR>> {
-    static constexpr int value = 4;
+    static constexpr int value = MXR_BATCH_WAVES;
 };
 
 template <bool LEDGER, bool TRACE, bool EXACT, int T, int... Rest>
@@ -573,7 +576,11 @@ __global__ __launch_bounds__(kBlock, BatchWavesHint<C>::value) void k_batch(cons
     for (uint64_t iter = 0; iter <= n_tiles; ++iter) {
         if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1ull);
         __syncthreads();
-        const uint64_t tile = s_tile;
+        // the popped tile is the same for every lane: make that explicit so
+        // the job lookup and the job's arguments stay scalar
+        const uint64_t t_lds = s_tile;
+        const uint64_t tile = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(t_lds >> 32)) << 32) |
+                              (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)t_lds);
         __syncthreads();
         if (tile >= n_tiles) break;
         // job of this tile: the last job whose first tile is <= tile
