@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--rays", type=int, default=N_RAYS)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-learned", action="store_true", help="skip the time-to-1%% measurement (plain vs learned)")
-    p.add_argument("--cpu-sample", type=int, default=4_000_000)
+    p.add_argument("--cpu-sample", type=int, default=16_000_000)
     p.add_argument("--train-hits", type=int, default=10**8, help="learned: detector hits collected for training")
     p.add_argument("--epochs", type=int, default=5, help="learned: training epochs")
     p.add_argument("--alpha", type=float, default=0.1, help="learned: share of the plain source in the proposal")
@@ -124,34 +124,48 @@ def cpu_model() -> str:
 
 
 def cpu_baseline(instr, n_sample: int, n_total: int, repeats: int = 5):
-    """The oracle on the host cores, on 16 equal ray ranges spread evenly over
-    the run (the stratified source orders rays by direction, so a contiguous
-    prefix would only sample the edge of the cone): the median of ``repeats``
+    """The oracle on the host cores, on rays spread evenly over the run (the
+    stratified source orders rays by direction, so a contiguous prefix would
+    only sample one edge of the cone): each repeat traces rays
+    r, r + s, r + 2s, ... of the n_total-ray run with the oracle's per-ray
+    tracer (every ray's full path through every component, detector bin
+    included; only the three histogram additions of a run are left out, and
+    with them a run's fixed cost of allocating and summing 2M-bin histograms,
+    which a 1e9-ray run amortises).  Reported: the median of ``repeats``
     timings on all the cores of one GPU's host share (at most 16 threads, each
-    range split over them), and the median of ``repeats`` single-thread
-    timings on a sample 16x smaller (the paper's baseline is one CPU thread,
-    wall clock, repeated runs)."""
+    tracing every 16th ray of the sample in a single-thread oracle call, all
+    at once), and the median of ``repeats`` single-thread timings on a sample
+    16x smaller (the paper's baseline is one CPU thread, wall clock, repeated
+    runs)."""
     import oracle
+    from concurrent.futures import ThreadPoolExecutor
     nproc = os.cpu_count() or 1
     threads = min(nproc, 16)
-    chunks = 16
 
-    def timed(n, th):
-        per = max(1, n // chunks)
+    def ids(m, r):
+        return (np.uint64(r) + np.arange(m, dtype=np.uint64) * np.uint64(n_total // m))
+
+    def timed(m, r, pool):
+        sample = ids(m, r)
         t0 = time.perf_counter()
-        for c in range(chunks):
-            oracle.run(instr, per, seed=1, first=(n_total // chunks) * c, n_total=n_total, threads=th)
-        return per * chunks, time.perf_counter() - t0
+        if pool is None:
+            oracle.trace_rays(instr, sample, 1, n_total)
+        else:
+            list(pool.map(lambda t: oracle.trace_rays(instr, sample[t::threads], 1, n_total), range(threads)))
+        return m, time.perf_counter() - t0
 
-    all_core = [timed(n_sample // repeats, threads) for _ in range(repeats)]
-    one = [timed(max(chunks, n_sample // (16 * repeats)), 1) for _ in range(repeats)]
+    m_all = max(threads, n_sample // repeats)
+    m_one = max(1, n_sample // (16 * repeats))
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        all_core = [timed(m_all, r, pool) for r in range(repeats)]
+    one = [timed(m_one, r, None) for r in range(repeats)]
     rate = lambda runs: float(np.median([d / t for d, t in runs]))
-    done = sum(d for d, _ in all_core)
     return {"value": rate(all_core), "unit": "rays/s", "cores": threads, "kind": "oracle",
-            "sample": f"{repeats} repeats of {chunks} ranges of {all_core[0][0] // chunks} rays spread over the "
-                      f"{n_total:.0e}-ray run ({done} rays, {threads} host threads, median of the repeats)",
+            "sample": f"{repeats} repeats of {m_all} rays evenly spaced over the {n_total:.0e}-ray run "
+                      f"(oracle per-ray tracer, every {threads}th ray per host thread, {threads} threads at once; "
+                      f"median of the repeats)",
             "single_thread": {"value": rate(one), "unit": "rays/s", "cores": 1,
-                              "sample": f"{repeats} repeats of {one[0][0]} rays, median"},
+                              "sample": f"{repeats} repeats of {m_one} rays evenly spaced over the run, median"},
             "nproc": nproc, "cpu_model": cpu_model(), "repeats": repeats}
 
 
