@@ -513,18 +513,20 @@ __device__ __forceinline__ bool comp_lens(const DevComp &c, Ray &ray) {
 // crosses one D plane; with cubic voxels and |d_A|, |d_B| <= |d_D| at most
 // one plane of each other axis lies between two D planes, so those rarer
 // crossings are taken in a branch that coherent waves mostly skip.  Every
-// crossing parameter is alpha = (plane - q) / d with the reciprocal
-// precomputed and the plane coordinate exact, so it is the same number in
-// whatever order the planes are visited (negative directions are mirrored so
-// every axis steps by +v).  The optical depth is accumulated per material
-// run: segment lengths between crossings telescope, so a run of voxels of
-// one material adds mu * (alpha_end - alpha_start) -- the same sum of
+// crossing parameter is a fixed function of the exact plane coordinate
+// (fma(plane, inv, -q inv), or (plane - q) inv, with inv = 1/d and q fixed
+// per ray and axis), so a plane's alpha is the same number in whatever order
+// the planes are visited and in the set-up that finds the first plane
+// (negative directions are mirrored so every axis steps by +v, which
+// leaves both forms unchanged).  The optical depth is accumulated per material run:
+// segment lengths between crossings telescope, so a run of voxels of one
+// material adds mu * (alpha_end - alpha_start) -- the same sum of
 // mu * length as segment by segment, up to rounding -- and the mu table is
 // read only where the material changes.  Voxels are read with buffer loads
 // (hardware range check: an out-of-range offset reads 0 instead of
 // faulting).  The walk is bounded by nx + ny + nz + 3 steps.
 #ifndef MXR_WALK_ROUND
-#define MXR_WALK_ROUND 2
+#define MXR_WALK_ROUND 3
 #endif
 constexpr int kWalkRound = MXR_WALK_ROUND;  // crossings per round of loads
 
@@ -545,10 +547,23 @@ __device__ __forceinline__ T pick3(int k, T a0, T a1, T a2) {
     return k == 0 ? a0 : (k == 1 ? a1 : a2);
 }
 
+// alpha of the plane at coordinate P on an axis with start q, reciprocal
+// direction inv and offset nq = -q inv.  ONE_ROUNDING: fma(P, inv, nq), one
+// instruction, one rounding after the exact product; otherwise
+// (P - q) * inv, the reference definition's rounding.  The walks that
+// locate interaction points keep the latter: a scattering chain feeds each
+// located point into the next walk, so it stays on the reference's
+// roundings, while a plain optical depth only sums the crossings' alphas.
+template <bool ONE_ROUNDING>
+__device__ __forceinline__ double plane_alpha(double P, double q, double inv, double nq) {
+    if constexpr (ONE_ROUNDING) return fma(P, inv, nq);
+    else return (P - q) * inv;
+}
+
 // Per-axis walk state, one entry per axis; roles D, A, B pick from it with
 // selects (registers cannot be indexed by a per-lane value).
 struct AxisSet {
-    double P[3], q[3], inv[3], c[3];  // c: corner, mirrored (-corner) for negative directions
+    double P[3], q[3], nq[3], inv[3], c[3];  // c: corner, mirrored (-corner) for negative directions
     int k[3], doff[3];
 };
 
@@ -561,6 +576,23 @@ __device__ __forceinline__ double min_f64(double a, double b) {
     double r;
     asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
     return r;
+}
+
+// The divergent event's updates, written so that each new value takes the
+// register of the value it replaces (tied operands).  The uniform D step
+// leaves the A and B state untouched; with in-place updates on the other
+// path the two paths meet without register copies (the compiler otherwise
+// gives the new values fresh registers and copies the old ones on the
+// uniform path, five to six moves per event).  Same arithmetic as
+// P = fma(f, v, P), a = fma(P, inv, nq) and m = min(a, b).
+__device__ __forceinline__ void step_in_place(double &P, double f, double v) {
+    asm("v_fma_f64 %0, %1, %2, %0" : "+v"(P) : "v"(f), "s"(v));
+}
+__device__ __forceinline__ void alpha_in_place(double &a, double P, double inv, double nq) {
+    asm("v_fma_f64 %0, %1, %2, %3" : "+v"(a) : "v"(P), "v"(inv), "v"(nq));
+}
+__device__ __forceinline__ void min_in_place(double &m, double a, double b) {
+    asm("v_min_f64 %0, %1, %2" : "+v"(m) : "v"(a), "v"(b));
 }
 
 // clamp(x, 0, hi) for hi >= 0 as one v_med3_i32, and a * b + c on the low
@@ -581,20 +613,21 @@ __device__ __forceinline__ uint32_t mad_u24(int a, int b, int c) {
 
 // The walk in rounds of K crossings ("events").  Each event is the nearest
 // of the next D, A and B crossings (D first on ties with the others, A before
-// B), clipped to a_out; its alpha is computed from the plane index, so it is
-// the same number the merged order of all crossings would see.  When no lane
-// of the wave has an A or B crossing next, the event is a D step for the
-// whole wave (the common case).  Otherwise every lane steps one axis without
-// branching: each axis's plane advances by a factor of 1 or 0 times v (an
-// exact fma), and all three alphas are recomputed from their planes, which
-// leaves the two unchanged ones bit for bit as they were.  Divergent
-// branches would execute all three updates anyway, plus the register copies
-// their joins need.  An axis the ray runs parallel to is given a plane
-// ahead of the ray and an infinite reciprocal, so its recomputed alpha stays
-// +inf.  The K voxel loads of a round are issued together and then folded
-// into the material runs in order.  Events past the exit carry t = a_out and keep stepping D:
-// their voxels (read through the range-checked buffer) can only open
-// zero-length runs, which add nothing.
+// B); its alpha is computed from the plane coordinate, so it is the same
+// number the merged order of all crossings would see.  The nearer of the A
+// and B crossings is kept (mAB), so one compare tells whether a lane's next
+// event is a D step.  When no lane of the wave has an A or B crossing next,
+// the event is a D step for the whole wave (the common case).  Otherwise
+// every lane steps one axis without branching: each axis's plane advances
+// by a factor of 1 or 0 times v (an exact fma), and all three alphas are
+// recomputed from their planes, which leaves the two unchanged ones bit for
+// bit as they were.  An axis the ray runs parallel to has inv = 0 and
+// nq = +inf, so its alpha is +inf and it never steps.  The K voxel loads of
+// a round are issued together and then folded into the material runs in
+// order.  Events are not clipped to the exit: a lane past its exit keeps
+// stepping, and the fold clips each closing alpha to a_out, so runs past the
+// exit have zero length and add nothing (their voxels are read through the
+// range-checked buffer).
 //
 // LOCATE: also find where the running optical depth reaches tau_star.  Within
 // a material run mu is constant, so the point is checked when a run closes:
@@ -609,6 +642,26 @@ struct WalkHit {
     bool found = false;
 };
 
+// Close the material run [a_start, tc] of material m (attenuation mu) onto
+// the optical depth tau; LOCATE: and check it for the depth tau_star.
+template <bool LOCATE>
+__device__ __forceinline__ void close_run(double tc, double mu, uint32_t m, double &tau, double a_start,
+                                          double tau_star, WalkHit *hit) {
+    const double closed = fma(mu, tc - a_start, tau);
+    if constexpr (LOCATE) {
+        if (mu > 0.0 && tc > a_start) {
+            if (!hit->found && closed >= tau_star) {
+                hit->found = true;
+                hit->s = a_start + (tau_star - tau) / mu;
+                hit->m = m;
+            }
+            hit->last_end = tc;
+            hit->last_m = m;
+        }
+    }
+    tau = closed;
+}
+
 template <bool EXACT, int K, bool LOCATE = false>
 __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet &S, int D, int A, int B,
                                               uint32_t off, double a_in, double a_out,
@@ -618,68 +671,61 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
     const double v = g.v;
     double PD = pick3(D, S.P[0], S.P[1], S.P[2]), PA = pick3(A, S.P[0], S.P[1], S.P[2]);
     double PB = pick3(B, S.P[0], S.P[1], S.P[2]);
-    const double qD = pick3(D, S.q[0], S.q[1], S.q[2]), qA = pick3(A, S.q[0], S.q[1], S.q[2]);
-    const double qB = pick3(B, S.q[0], S.q[1], S.q[2]);
+    constexpr bool ONE = !LOCATE;
+    const double nD = pick3(D, S.nq[0], S.nq[1], S.nq[2]);
+    const double nA = pick3(A, S.nq[0], S.nq[1], S.nq[2]), nB = pick3(B, S.nq[0], S.nq[1], S.nq[2]);
+    const double qD = pick3(D, S.q[0], S.q[1], S.q[2]);
+    const double qA = pick3(A, S.q[0], S.q[1], S.q[2]), qB = pick3(B, S.q[0], S.q[1], S.q[2]);
     const double iD = pick3(D, S.inv[0], S.inv[1], S.inv[2]);
-    double iA = pick3(A, S.inv[0], S.inv[1], S.inv[2]), iB = pick3(B, S.inv[0], S.inv[1], S.inv[2]);
+    const double iA = pick3(A, S.inv[0], S.inv[1], S.inv[2]), iB = pick3(B, S.inv[0], S.inv[1], S.inv[2]);
     int kD = pick3(D, S.k[0], S.k[1], S.k[2]), kA = pick3(A, S.k[0], S.k[1], S.k[2]);
     int kB = pick3(B, S.k[0], S.k[1], S.k[2]);
     const int oD = pick3(D, S.doff[0], S.doff[1], S.doff[2]), oA = pick3(A, S.doff[0], S.doff[1], S.doff[2]);
     const int oB = pick3(B, S.doff[0], S.doff[1], S.doff[2]);
     // plane k of a mirrored axis sits at -corner + k v
     const double cD = pick3(D, S.c[0], S.c[1], S.c[2]);
-    double cA = pick3(A, S.c[0], S.c[1], S.c[2]), cB = pick3(B, S.c[0], S.c[1], S.c[2]);
-    double aD = (PD - qD) * iD;
-    double aA = (iA == 0.0) ? kInf : (PA - qA) * iA;
-    double aB = (iB == 0.0) ? kInf : (PB - qB) * iB;
-    if (iA == 0.0) {
-        PA = cA = qA + 1.0;
-        kA = 0;
-        iA = kInf;
-    }
-    if (iB == 0.0) {
-        PB = cB = qB + 1.0;
-        kB = 0;
-        iB = kInf;
-    }
+    const double cA = pick3(A, S.c[0], S.c[1], S.c[2]), cB = pick3(B, S.c[0], S.c[1], S.c[2]);
+    double aD = plane_alpha<ONE>(PD, qD, iD, nD);
+    double aA = plane_alpha<ONE>(PA, qA, iA, nA);
+    double aB = plane_alpha<ONE>(PB, qB, iB, nB);
+    double mAB = min_f64(aA, aB);
 
     uint32_t run_m = load_voxel(rs, off);
     double a_start = a_in, tau = 0.0;
-    const int max_rounds = (g.n[0] + g.n[1] + g.n[2] + 3) / K + 2;
+    const int max_rounds = __builtin_amdgcn_readfirstlane((g.n[0] + g.n[1] + g.n[2] + 3) / K + 2);
     for (int round = 0; round < max_rounds; ++round) {
         uint32_t o[K];
         double t[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            const double lim = min_f64(aD, a_out);
-            const bool secA = aA < lim, secB = aB < lim;
-            if (__builtin_amdgcn_ballot_w64(secA || secB) == 0) {
-                t[j] = lim;
-                off += (uint32_t)oD;
-                PD = EXACT ? PD + v : cD + (double)(++kD) * v;
-                aD = (PD - qD) * iD;
-            } else {
-                const bool tA = secA && aA <= aB;
-                const bool tB = secB && !tA;
-                const bool tD = !(tA || tB);
-                t[j] = min_f64(lim, min_f64(aA, aB));  // the stepped axis's alpha
-                off += (uint32_t)(tA ? oA : (tB ? oB : oD));
+            const bool side = mAB < aD;
+            t[j] = min_f64(aD, mAB);
+            // every lane takes the D step below; a lane whose next crossing
+            // is an A or B plane takes that one instead: the offset moves by
+            // its stride rather than the D stride, and its D plane is first
+            // moved back by v (exact), so the step leaves it in place
+            if (__builtin_amdgcn_ballot_w64(side) != 0) {
+                const bool tA = side && aA <= aB;
+                const bool tB = side && !tA;
+                off += (uint32_t)(tA ? oA - oD : (tB ? oB - oD : 0));
                 if constexpr (EXACT) {
-                    PD = fma(tD ? 1.0 : 0.0, v, PD);
+                    PD = fma(side ? -1.0 : 0.0, v, PD);
                     PA = fma(tA ? 1.0 : 0.0, v, PA);
                     PB = fma(tB ? 1.0 : 0.0, v, PB);
                 } else {
-                    kD += tD;
+                    kD -= side;
                     kA += tA;
                     kB += tB;
-                    PD = cD + (double)kD * v;
                     PA = cA + (double)kA * v;
                     PB = cB + (double)kB * v;
                 }
-                aD = (PD - qD) * iD;
-                aA = (PA - qA) * iA;
-                aB = (PB - qB) * iB;
+                aA = plane_alpha<ONE>(PA, qA, iA, nA);
+                aB = plane_alpha<ONE>(PB, qB, iB, nB);
+                mAB = min_f64(aA, aB);
             }
+            off += (uint32_t)oD;
+            PD = EXACT ? PD + v : cD + (double)(++kD) * v;
+            aD = plane_alpha<ONE>(PD, qD, iD, nD);
             o[j] = off;
         }
         uint32_t m[K];
@@ -690,49 +736,21 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
             // a material change closes the run (a wave with no change skips
             // the block on its empty execution mask)
             if (m[j] != run_m) {
-                if constexpr (LOCATE) {
-                    const double mu = mu_row[run_m];
-                    const double closed = fma(mu, t[j] - a_start, tau);
-                    if (mu > 0.0 && t[j] > a_start) {
-                        if (!hit->found && closed >= tau_star) {
-                            hit->found = true;
-                            hit->s = a_start + (tau_star - tau) / mu;
-                            hit->m = run_m;
-                        }
-                        hit->last_end = t[j];
-                        hit->last_m = run_m;
-                    }
-                    tau = closed;
-                } else {
-                    tau = fma(mu_row[run_m], t[j] - a_start, tau);
-                }
-                a_start = t[j];
+                const double tc = min_f64(t[j], a_out);
+                close_run<LOCATE>(tc, mu_row[run_m], run_m, tau, a_start, tau_star, hit);
+                a_start = tc;
                 run_m = m[j];
             }
         }
-        // every lane is past its exit once its last event sits at a_out
+        // every lane is past its exit once its last event lies at or beyond a_out
         if constexpr (LOCATE) {
             if (__builtin_amdgcn_ballot_w64(t[K - 1] < a_out && !hit->found) == 0) break;
         } else {
             if (__builtin_amdgcn_ballot_w64(t[K - 1] < a_out) == 0) break;
         }
     }
-    if constexpr (LOCATE) {
-        const double mu = mu_row[run_m];
-        const double closed = fma(mu, a_out - a_start, tau);
-        if (mu > 0.0 && a_out > a_start) {
-            if (!hit->found && closed >= tau_star) {
-                hit->found = true;
-                hit->s = a_start + (tau_star - tau) / mu;
-                hit->m = run_m;
-            }
-            hit->last_end = a_out;
-            hit->last_m = run_m;
-        }
-        return closed;
-    } else {
-        return fma(mu_row[run_m], a_out - a_start, tau);
-    }
+    close_run<LOCATE>(a_out, mu_row[run_m], run_m, tau, a_start, tau_star, hit);
+    return tau;
 }
 
 // EXACT: every plane coordinate corner + i v is reached exactly by adding v
@@ -763,7 +781,12 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
     // Per axis: the voxel holding the start of the path and the first plane
     // crossed after a_in.  Planes are mirrored for negative directions
     // (coordinate -x, plane index counted downwards), so that the next plane
-    // is always reached by adding v and alpha = (P - q) * inv keeps its value.
+    // is always reached by adding v; alpha keeps its value (with -P, -q and
+    // -inv the product P inv and the difference (P - q) inv are the same
+    // numbers, -q inv unchanged).  An axis the ray runs parallel to gets an
+    // alpha of +inf: inv = 0 and nq = +inf for the one-rounding form, a
+    // plane ahead of q and inv = +inf for the other.
+    constexpr bool ONE = !LOCATE;
     int idx[3];
     AxisSet S;
     const int nx = g.n[0], nxy = g.n[0] * g.n[1];
@@ -776,38 +799,42 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
             double f = floor((q[i] - c) / v);
             idx[i] = (int)fmin(fmax(f, 0.0), (double)(n - 1));
             S.k[i] = 0;
-            S.P[i] = 0.0;
+            S.P[i] = ONE ? 0.0 : q[i] + 1.0;
             S.q[i] = q[i];
-            S.inv[i] = 0.0;
+            S.nq[i] = kInf;
+            S.inv[i] = ONE ? 0.0 : kInf;
             S.c[i] = c;
             S.doff[i] = 0;
             continue;
         }
+        const double nq = -(q[i] * inv[i]);
         const double x_in = q[i] + a_in * dl[i];
         const double f = (x_in - c) / v;
         int p;
         if (dl[i] > 0.0) {
             // first plane p in [1, n] with alpha(p) > a_in
             p = (int)fmin(fmax(floor(f) + 1.0, 1.0), (double)n);
-            if (p > 1 && ((c + (double)(p - 1) * v) - q[i]) * inv[i] > a_in) p -= 1;
-            if (p < n && !(((c + (double)p * v) - q[i]) * inv[i] > a_in)) p += 1;
+            if (p > 1 && plane_alpha<ONE>(c + (double)(p - 1) * v, q[i], inv[i], nq) > a_in) p -= 1;
+            if (p < n && !(plane_alpha<ONE>(c + (double)p * v, q[i], inv[i], nq) > a_in)) p += 1;
             idx[i] = p - 1;
             S.k[i] = p;
             S.P[i] = c + (double)p * v;
             S.q[i] = q[i];
+            S.nq[i] = nq;
             S.inv[i] = inv[i];
             S.c[i] = c;
             S.doff[i] = stride[i];
         } else {
             // last plane p in [0, n - 1] with alpha(p) > a_in, walked downwards
             p = (int)fmin(fmax(ceil(f) - 1.0, 0.0), (double)(n - 1));
-            if (p < n - 1 && ((c + (double)(p + 1) * v) - q[i]) * inv[i] > a_in) p += 1;
-            if (p > 0 && !(((c + (double)p * v) - q[i]) * inv[i] > a_in)) p -= 1;
+            if (p < n - 1 && plane_alpha<ONE>(c + (double)(p + 1) * v, q[i], inv[i], nq) > a_in) p += 1;
+            if (p > 0 && !(plane_alpha<ONE>(c + (double)p * v, q[i], inv[i], nq) > a_in)) p -= 1;
             idx[i] = p;
             // mirrored: plane index k = -p, coordinate -(c + p v), -q, -inv
             S.k[i] = -p;
             S.P[i] = -(c + (double)p * v);
             S.q[i] = -q[i];
+            S.nq[i] = nq;
             S.inv[i] = -inv[i];
             S.c[i] = -c;
             S.doff[i] = -stride[i];
