@@ -929,6 +929,10 @@ static mxr_status derive(const mxr_component_desc &s, DevComp &c, int k, uint32_
             c.aux[1] = p[2] - p[1];
             c.aux[2] = p[3] * std::log(p[2] / p[1]) - (p[2] - p[1]);
             c.aux[3] = p[9] * std::sqrt(2.0 * M_PI);
+            c.aux[4] = 1.0 / p[9];
+            c.aux[5] = 1.0 / c.aux[3];
+            c.aux[6] = p[4] / c.aux[2];
+            c.aux[7] = 1.0 / c.aux[1];
             break;
         case MXR_SRC_GAUSSIAN:
             if (!(p[0] >= 0 && p[1] >= 0 && p[2] >= 0 && p[3] >= 0 && p[4] > 0 && p[5] >= 0 && p[5] < 1))
@@ -1262,6 +1266,23 @@ static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, b
     return MXR_OK;
 }
 
+
+// Divisors of n rays stratified over G x G cells (the device's strat_cell).
+static StratDiv strat_div(uint64_t n, uint64_t G) {
+    StratDiv d{};
+    d.n = n;
+    d.G = (uint32_t)G;
+    d.G2 = G * G;
+    d.c0 = n / d.G2;
+    d.r = n % d.G2;
+    d.rn = n ? 1.0 / (double)n : 0.0;
+    d.rG = 1.0 / (double)G;
+    d.rG2 = 1.0 / (double)d.G2;
+    const double per = (double)n / (double)d.G2;
+    d.f0 = d.c0 ? per / (double)d.c0 : 0.0;
+    d.f1 = per / (double)(d.c0 + 1);
+    return d;
+}
 static mxr_status common_args(mxr_instrument *ins, uint64_t n_total, uint64_t seed, uint32_t purpose, uint32_t job,
                               RunArgs &a) {
     if (!ins) return fail(MXR_E_INVALID, "null instrument");
@@ -1283,6 +1304,7 @@ static mxr_status common_args(mxr_instrument *ins, uint64_t n_total, uint64_t se
     // the last cell's bound (cell + 1) n_total + G^2 - 1 must not wrap
     if (a.G2 > 1 && n_total > (~0ull - (a.G2 - 1)) / a.G2)
         return fail(MXR_E_INVALID, "n_total * strata^2 + strata^2 - 1 must stay below 2^64");
+    a.sd = strat_div(n_total, G);
     a.prop = ins->prop_on ? ins->prop_dev : nullptr;
     if (ins->prop_on) {
         // branch ranges of this run: plain share round(alpha n), then the
@@ -1304,7 +1326,7 @@ static mxr_status common_args(mxr_instrument *ins, uint64_t n_total, uint64_t se
             const uint64_t cnt = a.pb[b] - (b ? a.pb[b - 1] : 0);
             uint64_t g = gmax;
             while (g > 1 && g * g > cnt) g -= 1;
-            a.pG[b] = (uint32_t)g;
+            a.psd[b] = strat_div(cnt, g);
             a.pc[b] = (double)cnt / (double)n_total;
         }
     }
@@ -1814,6 +1836,7 @@ mxr_status mxr_batch_create(const mxr_batch_job *jobs, uint32_t n_jobs, const mx
             return fail(MXR_E_INVALID, "job %u: n_rays * strata^2 + strata^2 - 1 must stay below 2^64", k);
         b.G = G;
         b.G2 = G * G;
+        b.sd = strat_div(j.n_rays, G);
         for (uint32_t d = 0; d < ins->n_det; ++d) {
             const mxr_tally &t = j.tallies[d];
             if (!t.count || !t.sum_w || !t.sum_w2) return fail(MXR_E_INVALID, "job %u: tally %u has a null array", k, d);
@@ -1982,6 +2005,7 @@ mxr_status mxr_batch_autotune(mxr_batch *b, double rays_fraction, const char *ca
         while (G > 1 && G * G > j.args.n_total) G -= 1;
         j.args.G = G;
         j.args.G2 = G * G;
+        j.args.sd = strat_div(j.args.n_total, G);
     }
     mxr_status lay = batch_layout(b);
     if (lay != MXR_OK) {

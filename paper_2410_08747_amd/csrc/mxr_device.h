@@ -86,10 +86,23 @@ struct HitSink {
     float c[6];                  // context of this run
 };
 
+// Divisors of a stratified range of n rays over G x G cells, prepared on the
+// host: ray i of the range lies in cell floor(i G^2 / n), and a cell holds
+// c0 = floor(n / G^2) or c0 + 1 rays (r = n mod G^2 of the cells hold one
+// more), so the cell factor (n / G^2) / count takes one of the two values f0
+// and f1, each the same division the factor is defined by.  rn, rG and rG2
+// are 1/n, 1/G and 1/G^2 rounded, for the quotient estimates.
+struct StratDiv {
+    uint64_t n, G2, c0, r;
+    uint32_t G, pad;
+    double rn, rG, rG2, f0, f1;
+};
+
 struct RunArgs {
     const DevInstr *ins;
     uint64_t first, n, n_total, seed;
     uint64_t G, G2;  // strata per side used, and its square
+    StratDiv sd;     // the same strata's divisors
     uint32_t word3;  // purpose << 24 | job
     uint32_t blocks_per_xcd;
     uint32_t compact_rounds;  // compacting kernel: 64-ray rounds per wave
@@ -101,9 +114,9 @@ struct RunArgs {
     const PropTable *prop;  // proposal of the cone-beam source, or null
     // proposal runs: branch b (plain, then components 0..7) takes ray ids
     // [pb[b], pb[b+1]) (pb[0] = 0 is implicit: pb here holds the 9 upper
-    // bounds), stratified over pG[b]^2 cells; pc[b] = its share of the rays
+    // bounds), stratified over psd[b].G^2 cells; pc[b] = its share of the rays
     uint64_t pb[9];
-    uint32_t pG[9];
+    StratDiv psd[9];
     double pc[9];
     HitSink hits;  // hit-collecting runs
 };
@@ -218,12 +231,56 @@ __device__ __forceinline__ void src_rect_cone(const DevComp &c, Stream &s, Ray &
     to_lab(c, q, dl, ray);
 }
 
+// Tube spectrum (section 3.4's source: Kramers continuum plus two Gaussian
+// lines), per keV and normalised; the constant divisors come as host-side
+// reciprocals and quotients: aux[4] = 1/sigma, aux[5] = 1/(sigma sqrt(2 pi)),
+// aux[6] = continuum weight / continuum integral.
 __device__ __forceinline__ double spectrum(const DevComp &c, double E) {
-    double z1 = (E - c.par[5]) / c.par[9];
-    double z2 = (E - c.par[7]) / c.par[9];
-    double g1 = exp(-0.5 * z1 * z1) / c.aux[3];
-    double g2 = exp(-0.5 * z2 * z2) / c.aux[3];
-    return c.par[4] * ((c.par[3] - E) / E) / c.aux[2] + c.par[6] * g1 + c.par[8] * g2;
+    double z1 = (E - c.par[5]) * c.aux[4];
+    double z2 = (E - c.par[7]) * c.aux[4];
+    double g1 = exp(-0.5 * z1 * z1) * c.aux[5];
+    double g2 = exp(-0.5 * z2 * z2) * c.aux[5];
+    return c.aux[6] * ((c.par[3] - E) / E) + c.par[6] * g1 + c.par[8] * g2;
+}
+
+// floor(x / d) from the rounded estimate x * rd (rd = 1/d rounded), for a
+// quotient below 2^32 and at most q_max with q_max d < 2^64: the estimate's
+// relative error is a few 2^-53, so it lies within 1 of the quotient, and
+// one product decides a step down or up.
+__device__ __forceinline__ uint64_t div_est(uint64_t x, uint64_t d, double rd, uint64_t q_max) {
+    uint64_t q = (uint64_t)((double)x * rd);
+    q = q > q_max ? q_max : q;
+    const uint64_t p = q * d;
+    if (p > x) q -= 1;
+    else if (x - p >= d) q += 1;
+    return q;
+}
+__device__ __forceinline__ uint32_t div_est32(uint32_t x, uint32_t d, double rd, uint32_t q_max) {
+    uint32_t q = (uint32_t)((double)x * rd);
+    q = q > q_max ? q_max : q;
+    const uint32_t p = q * d;
+    if (p > x) q -= 1;
+    else if (x - p >= d) q += 1;
+    return q;
+}
+
+// Cell (cx, cy) of ray i of a stratified range and its factor (n / G^2) /
+// count.  cell = floor(i G^2 / n) < G^2 <= 2^32; the count is c0 plus the
+// difference of ceil(j r / G^2) at the cell's two ends (its first ray is
+// ceil(cell n / G^2) = cell c0 + ceil(cell r / G^2)).
+struct StratCell {
+    uint32_t cx, cy;
+    double factor;
+};
+__device__ __forceinline__ StratCell strat_cell(const StratDiv &s, uint64_t i) {
+    const uint64_t cell = div_est(i * s.G2, s.n, s.rn, s.G2 - 1);
+    const uint32_t cy = div_est32((uint32_t)cell, s.G, s.rG, s.G - 1);
+    const uint32_t cx = (uint32_t)cell - cy * s.G;
+    uint64_t count = s.c0;
+    if (s.r != 0)
+        count += div_est((cell + 1) * s.r + s.G2 - 1, s.G2, s.rG2, s.G2 - 1) -
+                 div_est(cell * s.r + s.G2 - 1, s.G2, s.rG2, s.G2 - 1);
+    return {cx, cy, count == s.c0 ? s.f0 : s.f1};
 }
 
 // Cone-beam point source, stratified: ray r lies in cell floor(r G^2 / N);
@@ -232,12 +289,10 @@ __device__ __forceinline__ double spectrum(const DevComp &c, double E) {
 // (dx, dy) = sin(theta) (px, py) / rho = 2 sin(alpha/2) cos(theta/2) (px, py).
 __device__ __forceinline__ void src_cone_beam(const DevComp &c, Stream &s, Ray &ray, uint64_t ray_id,
                                               const RunArgs &a) {
-    uint64_t cell = (ray_id * a.G2) / a.n_total;
-    uint64_t first = (cell * a.n_total + a.G2 - 1) / a.G2;
-    uint64_t next = ((cell + 1) * a.n_total + a.G2 - 1) / a.G2;
-    double factor = ((double)a.n_total / (double)a.G2) / (double)(next - first);
-    double u = ((double)(cell % a.G) + s.u(0)) / (double)a.G;
-    double v = ((double)(cell / a.G) + s.u(1)) / (double)a.G;
+    const StratCell sc = strat_cell(a.sd, ray_id);
+    const double factor = sc.factor;
+    double u = ((double)sc.cx + s.u(0)) * a.sd.rG;
+    double v = ((double)sc.cy + s.u(1)) * a.sd.rG;
     double ca = 2.0 * u - 1.0, cb = 2.0 * v - 1.0;
     double rad, ang;
     if (ca == 0.0 && cb == 0.0) {
@@ -291,26 +346,21 @@ __device__ __forceinline__ double trunc_normal(double Pa, double Pb, double Qa, 
 __device__ __forceinline__ bool src_cone_proposal(const DevComp &c, const PropTable *__restrict__ P, Stream &s,
                                                   Ray &ray, uint64_t ray_id, const RunArgs &a) {
     int branch = -1;
-    uint64_t start = 0, count = a.pb[0];
-    uint32_t G = a.pG[0];
+    uint64_t start = 0;
     if (ray_id >= a.pb[0]) {
         for (int k = 0; k < 8; ++k) {
             if (ray_id < a.pb[k + 1]) {
                 branch = k;
                 start = a.pb[k];
-                count = a.pb[k + 1] - a.pb[k];
-                G = a.pG[k + 1];
                 break;
             }
         }
     }
-    const uint64_t G2 = (uint64_t)G * G, i = ray_id - start;
-    const uint64_t cell = (i * G2) / count;
-    const uint64_t first = (cell * count + G2 - 1) / G2;
-    const uint64_t next = ((cell + 1) * count + G2 - 1) / G2;
-    const double factor = ((double)count / (double)G2) / (double)(next - first);
-    const double su = ((double)(cell % G) + s.u(0)) / (double)G;
-    const double sv = ((double)(cell / G) + s.u(1)) / (double)G;
+    const StratDiv &sd = a.psd[branch + 1];
+    const StratCell sc = strat_cell(sd, ray_id - start);
+    const double factor = sc.factor;
+    const double su = ((double)sc.cx + s.u(0)) * sd.rG;
+    const double sv = ((double)sc.cy + s.u(1)) * sd.rG;
     double y[3];
     if (branch < 0) {
         double ca = 2.0 * su - 1.0, cb = 2.0 * sv - 1.0;
@@ -346,7 +396,7 @@ __device__ __forceinline__ bool src_cone_proposal(const DevComp &c, const PropTa
     const bool in_box = y[0] >= P->lo[0] && y[0] <= P->hi[0] && y[1] >= P->lo[1] && y[1] <= P->hi[1] &&
                         y[2] >= P->lo[2] && y[2] <= P->hi[2];
     const double J = pow(1.0 + r2, -1.5);
-    double q = in_cone ? a.pc[0] * (J * P->inv_omega / c.aux[1]) : 0.0;
+    double q = in_cone ? a.pc[0] * (J * P->inv_omega * c.aux[7]) : 0.0;
     if (in_box) {
         for (int k = 0; k < 8; ++k) {
             if (a.pc[k + 1] == 0.0) continue;
