@@ -732,6 +732,7 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
     int kB = pick3(B, S.k[0], S.k[1], S.k[2]);
     const int oD = pick3(D, S.doff[0], S.doff[1], S.doff[2]), oA = pick3(A, S.doff[0], S.doff[1], S.doff[2]);
     const int oB = pick3(B, S.doff[0], S.doff[1], S.doff[2]);
+    const int dA = oA - oD, dB = oB - oD;  // offset change of an A or B step in place of the D step
     // plane k of a mirrored axis sits at -corner + k v
     const double cD = pick3(D, S.c[0], S.c[1], S.c[2]);
     const double cA = pick3(A, S.c[0], S.c[1], S.c[2]), cB = pick3(B, S.c[0], S.c[1], S.c[2]);
@@ -755,22 +756,22 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
             // its stride rather than the D stride, and its D plane is first
             // moved back by v (exact), so the step leaves it in place
             if (__builtin_amdgcn_ballot_w64(side) != 0) {
-                const bool tA = side && aA <= aB;
-                const bool tB = side && !tA;
-                off += (uint32_t)(tA ? oA - oD : (tB ? oB - oD : 0));
-                if constexpr (EXACT) {
-                    PD = fma(side ? -1.0 : 0.0, v, PD);
-                    PA = fma(tA ? 1.0 : 0.0, v, PA);
-                    PB = fma(tB ? 1.0 : 0.0, v, PB);
-                } else {
-                    kD -= side;
-                    kA += tA;
-                    kB += tB;
-                    PA = cA + (double)kA * v;
-                    PB = cB + (double)kB * v;
+                // lanes stepping A, then lanes stepping B (exec-masked)
+                const bool AfirstB = aA <= aB;
+                if (side && AfirstB) {
+                    off += (uint32_t)dA;
+                    PA = EXACT ? PA + v : cA + (double)(++kA) * v;
+                    aA = plane_alpha<ONE>(PA, qA, iA, nA);
+                    if constexpr (EXACT) PD = PD - v;
+                    else kD -= 1;
                 }
-                aA = plane_alpha<ONE>(PA, qA, iA, nA);
-                aB = plane_alpha<ONE>(PB, qB, iB, nB);
+                if (side && !AfirstB) {
+                    off += (uint32_t)dB;
+                    PB = EXACT ? PB + v : cB + (double)(++kB) * v;
+                    aB = plane_alpha<ONE>(PB, qB, iB, nB);
+                    if constexpr (EXACT) PD = PD - v;
+                    else kD -= 1;
+                }
                 mAB = min_f64(aA, aB);
             }
             off += (uint32_t)oD;
