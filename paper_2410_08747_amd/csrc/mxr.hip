@@ -139,6 +139,7 @@ __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream 
             g.n[1] = (int)c.dims[1];
             g.n[2] = (int)c.dims[2];
             g.v = c.par[0];
+            g.rv = c.aux[6];
             g.corner[0] = c.aux[0];
             g.corner[1] = c.aux[1];
             g.corner[2] = c.aux[2];
@@ -994,6 +995,7 @@ static mxr_status derive(const mxr_component_desc &s, DevComp &c, int k, uint32_
             n_ebin = (uint32_t)(s.data_len[1] / per_mat);
             for (int i = 0; i < 3; ++i) c.aux[i] = -0.5 * ((double)s.dims[i] * p[0]);
             c.aux[3] = (double)n_ebin / (p[2] - p[1]);
+            c.aux[6] = 1.0 / p[0];
             // can the walk step planes by adding v and stay exact?
             bool exact = true;
             for (int i = 0; i < 3 && exact; ++i) {

@@ -283,6 +283,55 @@ __device__ __forceinline__ StratCell strat_cell(const StratDiv &s, uint64_t i) {
     return {cx, cy, count == s.c0 ? s.f0 : s.f1};
 }
 
+// sin y and cos y for |y| <= pi/4 from their Maclaurin series through y^17
+// and y^18 (the first omitted terms, y^19/19! and y^20/20!, are below 1e-19
+// there), evaluated by Horner's rule in fused multiply-adds.
+__device__ __forceinline__ void sincos_quarter(double y, double &sn, double &cs) {
+    const double y2 = y * y;
+    double p = -1.0 / 355687428096000.0;
+    p = fma(y2, p, 1.0 / 1307674368000.0);
+    p = fma(y2, p, -1.0 / 6227020800.0);
+    p = fma(y2, p, 1.0 / 39916800.0);
+    p = fma(y2, p, -1.0 / 362880.0);
+    p = fma(y2, p, 1.0 / 5040.0);
+    p = fma(y2, p, -1.0 / 120.0);
+    p = fma(y2, p, 1.0 / 6.0);
+    sn = fma(-(y * y2), p, y);
+    double q = 1.0 / 6402373705728000.0;
+    q = fma(y2, q, -1.0 / 20922789888000.0);
+    q = fma(y2, q, 1.0 / 87178291200.0);
+    q = fma(y2, q, -1.0 / 479001600.0);
+    q = fma(y2, q, 1.0 / 3628800.0);
+    q = fma(y2, q, -1.0 / 40320.0);
+    q = fma(y2, q, 1.0 / 720.0);
+    q = fma(y2, q, -1.0 / 24.0);
+    q = fma(y2, q, 0.5);
+    cs = fma(-y2, q, 1.0);
+}
+
+// Concentric map of (ca, cb) in [-1, 1]^2 onto the unit disk: radius rad
+// and the angle's sine and cosine.  The angle is (pi/4) x with x = cb/ca,
+// or pi/2 - (pi/4) x with x = ca/cb, |x| <= 1; both come from sin and cos
+// of y = (pi/4) x (swapped for the second form).
+__device__ __forceinline__ void concentric(double ca, double cb, double &rad, double &sa, double &cs) {
+    double y = 0.0;
+    bool swap = false;
+    if (ca == 0.0 && cb == 0.0) {
+        rad = 0.0;
+    } else if (fabs(ca) > fabs(cb)) {
+        rad = ca;
+        y = (kPi / 4.0) * (cb / ca);
+    } else {
+        rad = cb;
+        y = (kPi / 4.0) * (ca / cb);
+        swap = true;
+    }
+    double sn, cn;
+    sincos_quarter(y, sn, cn);
+    sa = swap ? cn : sn;
+    cs = swap ? sn : cn;
+}
+
 // Cone-beam point source, stratified: ray r lies in cell floor(r G^2 / N);
 // the cell's square is mapped to the unit disk by the concentric map and the
 // disk radius rho to the cone by sin(theta/2) = rho sin(alpha/2).  Then
@@ -294,19 +343,8 @@ __device__ __forceinline__ void src_cone_beam(const DevComp &c, Stream &s, Ray &
     double u = ((double)sc.cx + s.u(0)) * a.sd.rG;
     double v = ((double)sc.cy + s.u(1)) * a.sd.rG;
     double ca = 2.0 * u - 1.0, cb = 2.0 * v - 1.0;
-    double rad, ang;
-    if (ca == 0.0 && cb == 0.0) {
-        rad = 0.0;
-        ang = 0.0;
-    } else if (fabs(ca) > fabs(cb)) {
-        rad = ca;
-        ang = (kPi / 4.0) * (cb / ca);
-    } else {
-        rad = cb;
-        ang = (kPi / 2.0) - (kPi / 4.0) * (ca / cb);
-    }
-    double sa, cs;
-    sincos(ang, &sa, &cs);
+    double rad, sa, cs;
+    concentric(ca, cb, rad, sa, cs);
     double px = rad * cs, py = rad * sa;
     double sh = fabs(rad) * c.aux[0];
     double ch = sqrt(1.0 - sh * sh);
@@ -364,19 +402,8 @@ __device__ __forceinline__ bool src_cone_proposal(const DevComp &c, const PropTa
     double y[3];
     if (branch < 0) {
         double ca = 2.0 * su - 1.0, cb = 2.0 * sv - 1.0;
-        double rad, ang;
-        if (ca == 0.0 && cb == 0.0) {
-            rad = 0.0;
-            ang = 0.0;
-        } else if (fabs(ca) > fabs(cb)) {
-            rad = ca;
-            ang = (kPi / 4.0) * (cb / ca);
-        } else {
-            rad = cb;
-            ang = (kPi / 2.0) - (kPi / 4.0) * (ca / cb);
-        }
-        double sa, cs;
-        sincos(ang, &sa, &cs);
+        double rad, sa, cs;
+        concentric(ca, cb, rad, sa, cs);
         double sh = fabs(rad) * c.aux[0];
         double ch = sqrt(1.0 - sh * sh);
         double k = 2.0 * c.aux[0] * ch;
@@ -584,7 +611,7 @@ struct PhantomGeo {
     const uint8_t *vol;
     uint32_t nvox;
     int n[3];
-    double v;
+    double v, rv;  // voxel edge and its reciprocal
     double corner[3];
 };
 
@@ -751,12 +778,14 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
         for (int j = 0; j < K; ++j) {
             const bool side = mAB < aD;
             t[j] = min_f64(aD, mAB);
-            // every lane takes the D step below; a lane whose next crossing
-            // is an A or B plane takes that one instead: the offset moves by
-            // its stride rather than the D stride, and its D plane is first
-            // moved back by v (exact), so the step leaves it in place
+            // every lane takes the D step; a lane whose next crossing is an
+            // A or B plane takes that one instead: in an exec-masked block it
+            // advances that plane, adds the stride difference and moves its
+            // D plane back by v (exact), so the step leaves it in place
+            off += (uint32_t)oD;
+            if constexpr (EXACT) PD = PD + v;
+            else ++kD;
             if (__builtin_amdgcn_ballot_w64(side) != 0) {
-                // lanes stepping A, then lanes stepping B (exec-masked)
                 const bool AfirstB = aA <= aB;
                 if (side && AfirstB) {
                     off += (uint32_t)dA;
@@ -774,8 +803,7 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
                 }
                 mAB = min_f64(aA, aB);
             }
-            off += (uint32_t)oD;
-            PD = EXACT ? PD + v : cD + (double)(++kD) * v;
+            if constexpr (!EXACT) PD = cD + (double)kD * v;
             aD = plane_alpha<ONE>(PD, qD, iD, nD);
             o[j] = off;
         }
@@ -860,7 +888,7 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
         }
         const double nq = -(q[i] * inv[i]);
         const double x_in = q[i] + a_in * dl[i];
-        const double f = (x_in - c) / v;
+        const double f = (x_in - c) * g.rv;  // an estimate: p is corrected below
         int p;
         if (dl[i] > 0.0) {
             // first plane p in [1, n] with alpha(p) > a_in
@@ -1065,6 +1093,7 @@ __device__ __forceinline__ bool comp_phantom_scatter(const DevComp &c, Stream &s
     g.n[1] = (int)c.dims[1];
     g.n[2] = (int)c.dims[2];
     g.v = c.par[0];
+    g.rv = c.aux[6];
     g.corner[0] = c.aux[0];
     g.corner[1] = c.aux[1];
     g.corner[2] = c.aux[2];
