@@ -785,21 +785,29 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
             off += (uint32_t)oD;
             if constexpr (EXACT) PD = PD + v;
             else ++kD;
-            if (__builtin_amdgcn_ballot_w64(side) != 0) {
+            const uint64_t wside = __builtin_amdgcn_ballot_w64(side);
+            if (wside != 0) {
+                // the A/B order as a lane mask straight from the compare, so
+                // the wave can skip a block that none of its lanes takes
+                const uint64_t wle = __builtin_amdgcn_fcmp(aA, aB, 5);  // FCMP_OLE: ordered <=
                 const bool AfirstB = aA <= aB;
-                if (side && AfirstB) {
-                    off += (uint32_t)dA;
-                    PA = EXACT ? PA + v : cA + (double)(++kA) * v;
-                    aA = plane_alpha<ONE>(PA, qA, iA, nA);
-                    if constexpr (EXACT) PD = PD - v;
-                    else kD -= 1;
+                if (__builtin_expect((wside & wle) != 0, 0)) {
+                    if (side && AfirstB) {
+                        off += (uint32_t)dA;
+                        PA = EXACT ? PA + v : cA + (double)(++kA) * v;
+                        aA = plane_alpha<ONE>(PA, qA, iA, nA);
+                        if constexpr (EXACT) PD = PD - v;
+                        else kD -= 1;
+                    }
                 }
-                if (side && !AfirstB) {
-                    off += (uint32_t)dB;
-                    PB = EXACT ? PB + v : cB + (double)(++kB) * v;
-                    aB = plane_alpha<ONE>(PB, qB, iB, nB);
-                    if constexpr (EXACT) PD = PD - v;
-                    else kD -= 1;
+                if (__builtin_expect((wside & ~wle) != 0, 0)) {
+                    if (side && !AfirstB) {
+                        off += (uint32_t)dB;
+                        PB = EXACT ? PB + v : cB + (double)(++kB) * v;
+                        aB = plane_alpha<ONE>(PB, qB, iB, nB);
+                        if constexpr (EXACT) PD = PD - v;
+                        else kD -= 1;
+                    }
                 }
                 mAB = min_f64(aA, aB);
             }
