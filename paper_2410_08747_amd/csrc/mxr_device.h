@@ -603,9 +603,13 @@ __device__ __forceinline__ bool comp_lens(const DevComp &c, Ray &ray) {
 // (hardware range check: an out-of-range offset reads 0 instead of
 // faulting).  The walk is bounded by nx + ny + nz + 3 steps.
 #ifndef MXR_WALK_ROUND
-#define MXR_WALK_ROUND 3
+#define MXR_WALK_ROUND 4
 #endif
-constexpr int kWalkRound = MXR_WALK_ROUND;  // crossings per round of loads
+#ifndef MXR_LOCATE_ROUND
+#define MXR_LOCATE_ROUND 3
+#endif
+constexpr int kWalkRound = MXR_WALK_ROUND;      // crossings per round of loads
+constexpr int kLocateRound = MXR_LOCATE_ROUND;  // the same for the locate walks
 
 struct PhantomGeo {
     const uint8_t *vol;
@@ -786,7 +790,28 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
             if constexpr (EXACT) PD = PD + v;
             else ++kD;
             const uint64_t wside = __builtin_amdgcn_ballot_w64(side);
-            if (wside != 0) {
+            if (LOCATE && wside != 0) {
+                // the locate walks (scattering chains, whose kernel runs
+                // short of registers): every lane advances each axis's plane
+                // by a 0/1 factor times v (branch-free, no exec changes)
+                const bool tA = side && aA <= aB;
+                const bool tB = side && !tA;
+                off += (uint32_t)(tA ? dA : (tB ? dB : 0));
+                if constexpr (EXACT) {
+                    PD = fma(side ? -1.0 : 0.0, v, PD);
+                    PA = fma(tA ? 1.0 : 0.0, v, PA);
+                    PB = fma(tB ? 1.0 : 0.0, v, PB);
+                } else {
+                    kD -= side;
+                    kA += tA;
+                    kB += tB;
+                    PA = cA + (double)kA * v;
+                    PB = cB + (double)kB * v;
+                }
+                aA = plane_alpha<ONE>(PA, qA, iA, nA);
+                aB = plane_alpha<ONE>(PB, qB, iB, nB);
+                mAB = min_f64(aA, aB);
+            } else if (wside != 0) {
                 // the A/B order as a lane mask straight from the compare, so
                 // the wave can skip a block that none of its lanes takes
                 const uint64_t wle = __builtin_amdgcn_fcmp(aA, aB, 5);  // FCMP_OLE: ordered <=
@@ -934,7 +959,8 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
     else if (ay >= az) { D = 1; A = 0; B = 2; }
     else { D = 2; A = 0; B = 1; }
     const uint32_t off = (uint32_t)(idx[0] + nx * idx[1] + nxy * idx[2]);
-    return siddon_walk<EXACT, kWalkRound, LOCATE>(g, S, D, A, B, off, a_in, a_out, mu_row, tau_star, hit);
+    return siddon_walk<EXACT, LOCATE ? kLocateRound : kWalkRound, LOCATE>(g, S, D, A, B, off, a_in, a_out, mu_row,
+                                                                         tau_star, hit);
 }
 
 // ------------------------------------------------- scattering phantom ----
