@@ -199,6 +199,16 @@ __device__ __forceinline__ void to_lab(const DevComp &c, const double q[3], cons
     }
 }
 
+// A ray leaving the component's origin: position pos, direction R dl (what
+// to_lab gives for q = 0, since R 0 + pos = pos for a finite rotation).
+__device__ __forceinline__ void from_origin(const DevComp &c, const double dl[3], Ray &ray) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        ray.r[i] = c.pos[i];
+        ray.d[i] = c.rot[i] * dl[0] + c.rot[3 + i] * dl[1] + c.rot[6 + i] * dl[2];
+    }
+}
+
 __device__ __forceinline__ bool plane_z0(double q[3], const double dl[3]) {
     if (!(dl[2] > 0.0)) return false;
     double t = -q[2] / dl[2];
@@ -349,14 +359,10 @@ __device__ __forceinline__ void src_cone_beam(const DevComp &c, Stream &s, Ray &
     double sh = fabs(rad) * c.aux[0];
     double ch = sqrt(1.0 - sh * sh);
     double k = 2.0 * c.aux[0] * ch;
-    ray.r[0] = c.pos[0];
-    ray.r[1] = c.pos[1];
-    ray.r[2] = c.pos[2];
     double dl[3] = {k * px, k * py, 1.0 - 2.0 * (sh * sh)};
-    double q[3] = {0.0, 0.0, 0.0};
     ray.E = c.par[1] + c.aux[1] * s.u(2);
     ray.w = (c.aux[1] * spectrum(c, ray.E)) * factor;
-    to_lab(c, q, dl, ray);
+    from_origin(c, dl, ray);
 }
 
 // Standard normal truncated to [za, zb] by inversion: the point leaving
@@ -436,10 +442,9 @@ __device__ __forceinline__ bool src_cone_proposal(const DevComp &c, const PropTa
     const double p_phys = in_cone ? spectrum(c, y[2]) * J * P->inv_omega : 0.0;
     const double n = sqrt(1.0 + r2);
     double dl[3] = {y[0] / n, y[1] / n, 1.0 / n};
-    double q0[3] = {0.0, 0.0, 0.0};
     ray.E = y[2];
     ray.w = p_phys > 0.0 ? (p_phys / q) * factor : 0.0;
-    to_lab(c, q0, dl, ray);
+    from_origin(c, dl, ray);
     return p_phys > 0.0;
 }
 
@@ -619,8 +624,13 @@ struct PhantomGeo {
     double corner[3];
 };
 
+// The loaded byte goes through an empty asm so that it stays a plain 32-bit
+// value: the compiler otherwise narrows the walk's materials to 16 bits and
+// masks the loads with extra instructions.
 __device__ __forceinline__ uint32_t load_voxel(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
-    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0);
+    uint32_t m = (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0);
+    asm("" : "+v"(m));
+    return m;
 }
 
 template <class T>
