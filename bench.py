@@ -33,6 +33,8 @@ N_RAYS = 10**9
 # 24 B of histogram update for the 30.2 % of rays that reach the detector.
 BYTES_PER_RAY = 270 * 1 + 0.302 * 24
 HBM_PEAK_GBS = 8000.0
+# wave64 VALU instructions per second: 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 # FP64 operations per emitted ray of the projection's walk: ~6 per voxel visit
 # (the plane alpha, two comparisons, the segment length, the optical-depth
 # fused multiply-add) over 270 visits, plus ~400 for source, clip and tally
@@ -110,6 +112,26 @@ def measured_traffic(profile=PROFILE):
     if kv.get("source") != h.hexdigest()[:16]:
         return None
     return (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) + float(kv["write_kib"]) * float(kv["write_scale"])) * 1024.0
+
+
+def measured_valu(profile=PROFILE):
+    """VALU wave-instructions per launch of the projection kernel from the
+    committed SQ_INSTS_VALU count; None when the kernel sources changed since
+    it was taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    try:
+        with open(os.path.join(ROOT, profile)) as fh:
+            line = [l for l in fh if l.startswith("issue:")][-1]
+    except (OSError, IndexError):
+        return None
+    kv = dict(x.split("=") for x in line.split()[1:])
+    if kv.get("source") != h.hexdigest()[:16]:
+        return None
+    return float(kv["valu_insts"])
 
 
 def cpu_model() -> str:
@@ -962,6 +984,7 @@ def main():
     achieved = BYTES_PER_RAY * n / (kern_ms * 1e-3) / 1e9
     detected = int(tallies[0]["count"].sum())
     traffic = measured_traffic()
+    valu = measured_valu()
 
     out = {
         "metric": METRIC,
@@ -994,6 +1017,13 @@ def main():
                               "frac": traffic / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}),
             "fp64": {"flop_per_ray": FP64_FLOP_PER_RAY, "achieved_TFLOPs": FP64_FLOP_PER_RAY * n / (kern_ms * 1e-3) / 1e12,
                      "peak_TFLOPs": 78.6, "frac": FP64_FLOP_PER_RAY * n / (kern_ms * 1e-3) / 78.6e12},
+            # the binding limit: VALU instruction issue (the launch's committed
+            # SQ_INSTS_VALU count over this run's kernel time, against one
+            # wave64 VALU instruction per SIMD per 4 cycles)
+            "valu_issue": (None if valu is None else
+                           {"insts_per_launch": valu, "achieved_per_s": valu / (kern_ms * 1e-3),
+                            "peak_per_s": VALU_ISSUE_PEAK, "frac": valu / (kern_ms * 1e-3) / VALU_ISSUE_PEAK}),
+            "binding": "valu_issue",
         },
     }
     if not args.no_learned:
