@@ -64,7 +64,8 @@ typedef enum {
  * MXR_SRC_CONE_BEAM (3 draws) -- point source at the local origin, direction
  *   uniform in solid angle inside a cone about +z, stratified over
  *   G x G equal-area cells (concentric square-to-disk map, Shirley & Chiu
- *   1997; G is reduced to the largest value with G^2 <= n_total), energy
+ *   1997; G is reduced to the largest value with 16 G^2 <= n_total, 1 if
+ *   none, so that a cell holds at least 16 rays), energy
  *   flat on [E min, E max] with the tube spectrum carried in the weight
  *   w0 = (E max - E min) S(E) (n_total / G^2) / n_cell (paper, section 3.3:
  *   a tube source illuminating the whole detector).  S is a Kramers
@@ -308,7 +309,7 @@ mxr_status mxr_autotune_instrument(mxr_instrument *ins, uint64_t n_total, double
  * (B0 = round(alpha n_total)) and one per component, sized by the rounded
  * running sums of the box masses pi_k Z_k.  Within its range a ray's first
  * two uniforms are stratified over G x G cells (G the source's strata,
- * reduced so G^2 <= the range size) exactly like the plain source; the plain
+ * reduced so 16 G^2 <= the range size) exactly like the plain source; the plain
  * branch maps them to the cone with the concentric map and draws E from the
  * third uniform, a component inverts a truncated normal per coordinate (u,
  * v from the stratified pair, E from the third uniform).  The ray's weight is

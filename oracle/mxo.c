@@ -228,11 +228,12 @@ static void src_rect_cone(const mxo_comp *c, mxo_stream *s, mxo_ray *ray)
 }
 
 /* Number of strata per side actually used for n_total rays: the largest
- * g <= G with g*g <= n_total, so that every stratum holds at least one ray. */
+ * g <= G with 16 g*g <= n_total (1 if none), so that every stratum holds at
+ * least 16 rays. */
 uint64_t mxo_strata_side(uint64_t G, uint64_t n_total)
 {
     uint64_t g = G < 1 ? 1 : G;
-    while (g > 1 && g * g > n_total)
+    while (g > 1 && 16 * g * g > n_total)
         g -= 1;
     return g;
 }

@@ -1269,6 +1269,16 @@ static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, b
 }
 
 
+// Strata per side used for n rays: the largest g <= G with 16 g^2 <= n (1 if
+// none).  Every cell then holds at least 16 rays, so the 64 consecutive rays
+// of a wave fall in a few neighbouring cells and leave the source in nearly
+// one direction (with one ray per cell a wave would span 64 cells).
+static uint64_t strata_side(uint64_t G, uint64_t n) {
+    uint64_t g = G < 1 ? 1 : G;
+    while (g > 1 && 16 * g * g > n) g -= 1;
+    return g;
+}
+
 // Divisors of n rays stratified over G x G cells (the device's strat_cell).
 static StratDiv strat_div(uint64_t n, uint64_t G) {
     StratDiv d{};
@@ -1299,8 +1309,7 @@ static mxr_status common_args(mxr_instrument *ins, uint64_t n_total, uint64_t se
     a.n_total = n_total;
     a.seed = seed;
     a.word3 = (purpose << 24) | job;
-    uint64_t G = ins->strata ? ins->strata : 1;
-    while (G > 1 && G * G > n_total) G -= 1;
+    const uint64_t G = strata_side(ins->strata, n_total);
     a.G = G;
     a.G2 = G * G;
     // the last cell's bound (cell + 1) n_total + G^2 - 1 must not wrap
@@ -1326,8 +1335,7 @@ static mxr_status common_args(mxr_instrument *ins, uint64_t n_total, uint64_t se
         const uint64_t gmax = ins->strata ? ins->strata : 1;
         for (int b = 0; b < 9; ++b) {
             const uint64_t cnt = a.pb[b] - (b ? a.pb[b - 1] : 0);
-            uint64_t g = gmax;
-            while (g > 1 && g * g > cnt) g -= 1;
+            const uint64_t g = strata_side(gmax, cnt);
             a.psd[b] = strat_div(cnt, g);
             a.pc[b] = (double)cnt / (double)n_total;
         }
@@ -1832,8 +1840,7 @@ mxr_status mxr_batch_create(const mxr_batch_job *jobs, uint32_t n_jobs, const mx
         b.n_total = j.n_rays;
         b.seed = j.seed;
         b.word3 = j.job;
-        uint64_t G = ins->strata ? ins->strata : 1;
-        while (G > 1 && G * G > j.n_rays) G -= 1;
+        const uint64_t G = strata_side(ins->strata, j.n_rays);
         if (G * G > 1 && j.n_rays > (~0ull - (G * G - 1)) / (G * G))
             return fail(MXR_E_INVALID, "job %u: n_rays * strata^2 + strata^2 - 1 must stay below 2^64", k);
         b.G = G;
@@ -2003,8 +2010,7 @@ mxr_status mxr_batch_autotune(mxr_batch *b, double rays_fraction, const char *ca
     for (BatchJob &j : b->host_jobs) {
         j.args.n = std::max<uint64_t>(1, (uint64_t)(j.args.n * rays_fraction));
         j.args.n_total = j.args.n;
-        uint64_t G = j.args.G;
-        while (G > 1 && G * G > j.args.n_total) G -= 1;
+        const uint64_t G = strata_side(j.args.G, j.args.n_total);
         j.args.G = G;
         j.args.G2 = G * G;
         j.args.sd = strat_div(j.args.n_total, G);
