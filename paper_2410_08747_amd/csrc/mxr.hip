@@ -549,6 +549,15 @@ __global__ __launch_bounds__(kBlock, WavesHint<C>::value) void k_trace_compact(c
 
 // ---------------------------------------------------------------- batch --
 
+// The device's constant address space, for tables that no kernel writes
+// while they are read (in the host pass, where kernel bodies are only
+// parsed, it is the ordinary one).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MXR_CONSTANT __attribute__((address_space(4)))
+#else
+#define MXR_CONSTANT
+#endif
+
 // One job of a batch: its instrument and the arguments of its run (read in
 // place from the job table, so their wave-uniform fields stay scalar loads).
 struct BatchJob {
@@ -591,8 +600,9 @@ __global__ __launch_bounds__(kBlock, BatchWavesHint<C>::value) void k_batch(cons
             if (jobs[mid].tile0 <= tile) lo = mid;
             else hi = mid;
         }
-        const BatchJob &J = jobs[lo];
-        const RunArgs &a = J.args;
+        // the job through the constant address space (see k_batch_grid)
+        const MXR_CONSTANT BatchJob &J = ((const MXR_CONSTANT BatchJob *)jobs)[lo];
+        const MXR_CONSTANT RunArgs &a = J.args;
         const DevInstr *ins = a.ins;
         const uint32_t n_mat = ins->n_mat, n_ebin = ins->n_ebin;
         if (ins->phantom >= 0) {
@@ -645,7 +655,11 @@ __global__ __launch_bounds__(kBlock, BatchWavesHint<C>::value) void k_batch_grid
         if (jobs[mid].tile0 <= tile) lo = mid;
         else hi = mid;
     }
-    const RunArgs &a = jobs[lo].args;
+    // the job's arguments through the constant address space: the job table
+    // does not change during the launch, and loads from that space may be
+    // repeated near each use (like the kernel-argument segment's) instead of
+    // held in registers for the whole chain (which spilled 172 B per lane)
+    const MXR_CONSTANT RunArgs &a = ((const MXR_CONSTANT BatchJob *)jobs)[lo].args;
     const DevInstr *ins = a.ins;
     const uint32_t n_mat = ins->n_mat, n_ebin = ins->n_ebin;
     double *mu_lds = smem;
