@@ -208,15 +208,18 @@ typedef struct {
 
 typedef struct mxr_instrument mxr_instrument;
 
-/* Returns MXR_ABI_VERSION. */
+/* Returns MXR_ABI_VERSION (library bookkeeping; no passage of the paper). */
 uint32_t mxr_abi_version(void);
 
 /* Message of the last error on this host thread; valid until the next call
- * on this thread.  Never NULL. */
+ * on this thread.  Never NULL.  (Library bookkeeping.) */
 const char *mxr_last_error(void);
 
 /* Validates desc, derives per-component constants and copies them to the
- * current device (one small allocation, owned by the handle).  The data
+ * current device (one small allocation, owned by the handle): the
+ * instrument as a sequence of components placed in the lab frame (paper,
+ * section 2.1), its component data held in structs and made available on
+ * the device once (section 2.2.2).  The data
  * arrays are referenced, not copied: they must stay alive and unchanged
  * while the handle is used.  Errors: MXR_E_INVALID (null pointers, wrong
  * version, bad component order, non-finite or out-of-range parameters),
@@ -224,13 +227,14 @@ const char *mxr_last_error(void);
 mxr_status mxr_instrument_create(const mxr_instrument_desc *desc, mxr_instrument **out);
 
 /* Frees the handle and its device copy (synchronises the device first).
- * NULL is accepted. */
+ * NULL is accepted.  (Library bookkeeping.) */
 void mxr_instrument_destroy(mxr_instrument *ins);
 
 /* Launch shape of an instrument's plain runs (mxr_run without a ledger or a
  * proposal).  It changes how rays are mapped onto the device, never which
  * rays are traced or their results (per bin up to the order of the atomic
- * additions).
+ * additions): the rays are independent (paper, section 2.2), so their
+ * mapping onto threads is free.
  *   occupancy  waves per SIMD the run kernel is compiled for: 0 the chain's
  *              own, or 4, 6, 8 (fixed chains only; others ignore it)
  *   compact    1: chains with a crop right after the source run the
@@ -247,7 +251,11 @@ typedef struct {
 
 /* Traces rays [first_ray, first_ray + n_rays) of an n_total-ray run and
  * adds their histograms into tallies[0 .. n_tallies) (one per monitor, in
- * instrument order, n_bins = nx*ny*ne each).  ledger (nullable, device,
+ * instrument order, n_bins = nx*ny*ne each).  The method of the paper:
+ * independent rays, each carried from the source through every component
+ * into the monitors (Introduction; section 2.2), the monitor arrays updated
+ * atomically (section 2.2.2), a run split into ray ranges as the MPI
+ * scatter-gather splits it (section 2.2.1).  ledger (nullable, device,
  * 4 * n_components + 1 doubles, added to): per component k, [4k] weight
  * entering (for the source: emitted), [4k+1] weight absorbed at k,
  * [4k+2] weight removed by attenuation at k, [4k+3] weight tallied at k;
@@ -259,13 +267,16 @@ mxr_status mxr_run(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays, uin
                    void *hip_stream);
 
 /* Traces the listed rays (ray_ids: device, n entries, each < n_total) of an
- * n_total-ray run and writes their final states into out (no tallies).
- * The same per-ray code as mxr_run.  Errors as mxr_run. */
+ * n_total-ray run and writes their final states into out (no tallies): the
+ * particle state of section 2.2.2 (position, wavevector as direction and
+ * energy, weight) at the end of each ray.  The same per-ray code as
+ * mxr_run.  Errors as mxr_run. */
 mxr_status mxr_trace_rays(mxr_instrument *ins, const uint64_t *ray_ids, uint64_t n, uint64_t n_total,
                           uint64_t seed, uint32_t purpose, uint32_t job, const mxr_ray_soa *out,
                           void *hip_stream);
 
-/* Current launch shape of the instrument's plain runs. */
+/* Current launch shape of the instrument's plain runs (see
+ * mxr_autotune_instrument). */
 mxr_status mxr_get_launch_shape(const mxr_instrument *ins, mxr_launch_shape *out);
 
 /* Sets the launch shape (validated: occupancy in {0, 4, 6, 8}, compact in
@@ -350,16 +361,20 @@ typedef struct {
     float context[6];  /* the run's context (e.g. focal spot, angle, size) */
 } mxr_hits;
 
-/* mxr_run that also appends every ray reaching the monitor to hits.  The
- * instrument must be a cone-beam source, then slits / boxes / phantoms
- * (which keep direction and energy), then one monitor.  Errors as mxr_run,
+/* mxr_run that also appends every ray reaching the monitor to hits: the
+ * particle state at the monitor (section 2.2.2) as training data for the
+ * learned proposal (this library's addition; the paper has no learned
+ * component).  The instrument must be a cone-beam source, then slits /
+ * boxes / phantoms (which keep direction and energy), then one monitor.  Errors as mxr_run,
  * plus MXR_E_UNSUPPORTED for other instruments. */
 mxr_status mxr_collect(mxr_instrument *ins, uint64_t first_ray, uint64_t n_rays, uint64_t n_total, uint64_t seed,
                        uint32_t purpose, uint32_t job, const mxr_tally *tallies, uint32_t n_tallies,
                        const mxr_hits *hits, void *hip_stream);
 
 /* ------------------------------------------------------------------------
- * The proposal network.
+ * The proposal network (this library's addition, not the paper's: its
+ * output enters the method only through the statistical weight of section
+ * 2.2.2, which the importance weights of the proposal keep unbiased).
  *
  * An MLP maps a 6-number context c (e.g. focal-spot position, projection
  * angle as cos / sin, phantom size) to the mixture above:
@@ -421,18 +436,21 @@ typedef struct {
     uint32_t first_step;         /* Adam steps already taken (0 for a fresh start) */
 } mxr_train_cfg;
 
-/* Bytes of workspace for batches of up to `batch` rows. */
+/* Bytes of workspace for batches of up to `batch` rows (network section
+ * above). */
 uint64_t mxr_mlp_workspace_bytes(uint64_t batch);
 
 /* Byte offsets of the MXR_MLP_WS_REGIONS workspace regions for a batch of
- * n rows (offsets[MXR_MLP_WS_REGIONS], host).  Errors: MXR_E_INVALID. */
+ * n rows (offsets[MXR_MLP_WS_REGIONS], host; network section above).
+ * Errors: MXR_E_INVALID. */
 mxr_status mxr_mlp_workspace_layout(uint64_t batch, uint64_t *offsets);
 
-/* y[i] = bfloat16(x[i]), round to nearest even. */
+/* y[i] = bfloat16(x[i]), round to nearest even (the network's working copy,
+ * network section above). */
 mxr_status mxr_mlp_to_bf16(const float *x, uint64_t n, uint16_t *y, void *hip_stream);
 
 /* Network outputs o (n x 56 f32) of contexts ctx (n x 6 f32) under the
- * bfloat16 parameters w; the layer values stay in ws (ws_bytes >=
+ * bfloat16 parameters w (the forward of the network section above); the layer values stay in ws (ws_bytes >=
  * mxr_mlp_workspace_bytes(n)).  Errors: MXR_E_INVALID, MXR_E_HIP. */
 mxr_status mxr_mlp_forward(const uint16_t *w, const float *ctx, uint64_t n, float *out, void *ws, uint64_t ws_bytes,
                            void *hip_stream);
@@ -450,14 +468,15 @@ mxr_status mxr_mlp_forward(const uint16_t *w, const float *ctx, uint64_t n, floa
 #define MXR_MLP_NOALLOC_ROWS 4096u
 mxr_status mxr_mlp_forward_noalloc(const uint16_t *w, const float *ctx, uint64_t n, float *out, void *hip_stream);
 
-/* Mixture tables for mxr_proposal_set from outputs: gmm (n x 56 f64, per
- * row 8 x (pi, mu[3], sigma[3])), with the source's box lo / hi (host, 3
- * doubles each: -tan a, -tan a, emin / tan a, tan a, emax). */
+/* Mixture tables for mxr_proposal_set from outputs (the head of the network
+ * section above): gmm (n x 56 f64, per row 8 x (pi, mu[3], sigma[3])),
+ * with the source's box lo / hi (host, 3 doubles each: -tan a, -tan a,
+ * emin / tan a, tan a, emax; mxr_proposal_box). */
 mxr_status mxr_mlp_mixture(const float *out, uint64_t n, const double lo[3], const double hi[3], double *gmm,
                            void *hip_stream);
 
-/* Loss L (loss: device double, nullable) and its gradient with respect to
- * the parameters (grad: MXR_MLP_PARAMS f32, overwritten) over n rows
+/* Loss L of the network section above (loss: device double, nullable) and
+ * its gradient with respect to the parameters (grad: MXR_MLP_PARAMS f32, overwritten) over n rows
  * (ctx n x 6 f32, y n x 3 f64, omega n f64 >= 0 with a positive sum).
  * The weight gradients are reduced over splits of 1024 rows in a fixed
  * order (deterministic).  Errors: MXR_E_INVALID, MXR_E_HIP. */
@@ -465,20 +484,24 @@ mxr_status mxr_mlp_loss_grad(const uint16_t *w, const float *ctx, const double *
                              const double lo[3], const double hi[3], float *grad, double *loss, void *ws,
                              uint64_t ws_bytes, void *hip_stream);
 
-/* One Adam step on master (f32) with moments m, v (f32), writing the
- * bfloat16 copy w; step counts from 1 (bias correction). */
+/* One Adam step (Kingma and Ba 2015) on master (f32) with moments m, v
+ * (f32), writing the bfloat16 copy w; step counts from 1 (bias
+ * correction). */
 mxr_status mxr_adam_step(float *master, uint16_t *w, const float *grad, float *m, float *v, uint64_t n_params,
                          uint32_t step, float lr, float beta1, float beta2, float eps, void *hip_stream);
 
-/* Training weights of collected rows: omega_i = w_i / max(I_b, floor_frac
- * * mean of I over bins with hits), I = sum_w of the collecting run's
- * monitor (n_bins), so every live bin carries equal total weight.
+/* Training weights of collected rows (mxr_collect): omega_i = w_i /
+ * max(I_b, floor_frac * mean of I over bins with hits), I = sum_w of the
+ * collecting run's monitor (n_bins), so every live bin carries equal total
+ * weight -- the proposal that equalises per-bin errors, the statistic the
+ * paper sizes its runs by (section 5.1: rays per pixel and energy bin).
  * scratch: 2 * 256 + 1 doubles. */
 mxr_status mxr_train_weights(const double *w, const int64_t *bin, uint64_t n, const double *sum_w, uint64_t n_bins,
                              double floor_frac, double *omega, double *scratch, void *hip_stream);
 
-/* Adam training over n_rows rows (< 2^32) for cfg->epochs epochs of
- * batches of cfg->batch rows, each epoch in its own shuffled order.  grad
+/* Adam training of the network section above over n_rows rows (< 2^32)
+ * for cfg->epochs epochs of batches of cfg->batch rows, each epoch in its
+ * own shuffled order.  grad
  * (MXR_MLP_PARAMS f32) is scratch; loss_log (nullable, epochs *
  * ceil(n_rows / batch) doubles) receives each step's loss.  Errors:
  * MXR_E_INVALID, MXR_E_UNSUPPORTED, MXR_E_HIP. */
@@ -529,7 +552,11 @@ mxr_status mxr_proposal_apply(mxr_instrument *ins, const uint16_t *w, const floa
                               uint64_t ws_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------------------
- * Per-bin error of a detector image by batch means.
+ * Per-bin error of a detector image by batch means.  The paper sizes runs by
+ * the statistics each pixel and energy bin receives (section 5.1) and judges
+ * images by contrast over noise; it gives no per-bin estimator, so this one
+ * is a reading: independent replicas, which stay valid for stratified and
+ * importance-weighted sources.
  *
  * sums: DEVICE array of R x n_bins doubles, row r the summed weights
  * (mxr_tally.sum_w) of replica r, an independent run of rays_per_replica
@@ -598,18 +625,21 @@ mxr_status mxr_batch_create(const mxr_batch_job *jobs, uint32_t n_jobs, const mx
  * MXR_E_STATE. */
 mxr_status mxr_batch_run(mxr_batch *batch, void *hip_stream);
 
-/* Current launch shape. */
+/* Current launch shape (batch section above). */
 mxr_status mxr_batch_get_schedule(const mxr_batch *batch, mxr_batch_schedule *out);
 
-/* Replaces the launch shape (the captured graph is rebuilt on the next run).
+/* Replaces the launch shape (batch section above; the captured graph is
+ * rebuilt on the next run).
  * Errors: MXR_E_INVALID for an out-of-range shape. */
 mxr_status mxr_batch_set_schedule(mxr_batch *batch, const mxr_batch_schedule *schedule);
 
 /* Synchronises the device, frees the handle and its device tables.  NULL is
- * accepted. */
+ * accepted.  (Library bookkeeping.) */
 void mxr_batch_destroy(mxr_batch *batch);
 
-/* Autotuner: times candidate launch shapes (the grid form; persistent forms
+/* Autotuner of a batch (the rays of all jobs are independent, paper section
+ * 2.2, so their order and grouping on the device are free): times candidate
+ * launch shapes (the grid form; persistent forms
  * of 2/4/8 groups per CU x 16K/64K-ray tiles; launches on 1/2/4 branches) on
  * the batch with every job's ray count scaled by rays_fraction (0 < f <= 1),
  * keeps the fastest and records it under a key describing the batch (its
@@ -623,7 +653,9 @@ mxr_status mxr_batch_autotune(mxr_batch *batch, double rays_fraction, const char
 
 /* ------------------------------------------------------------------------
  * Micro-benchmarks: the achievable rates that bound the tracing kernels, for
- * roofline denominators measured on the device beside the vendor figures.
+ * roofline denominators measured on the device beside the vendor figures
+ * (measurement infrastructure, not part of the method; the paper's own
+ * procedure, section 3.4, times whole runs).
  * Not part of tracing.  One launch of groups x 256 lanes on hip_stream
  * (asynchronous; the caller times it with events on that stream); *work
  * receives the operations (bytes for the read) the launch performs.
