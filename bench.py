@@ -62,6 +62,8 @@ def parse():
     p.add_argument("--train-hits", type=int, default=10**8, help="learned: detector hits collected for training")
     p.add_argument("--epochs", type=int, default=5, help="learned: training epochs")
     p.add_argument("--alpha", type=float, default=0.1, help="learned: share of the plain source in the proposal")
+    p.add_argument("--no-confirm", action="store_true",
+                   help="learned: skip the direct runs at the extrapolated 1 %% ray counts")
     p.add_argument("--eval-rays", type=int, default=16 * 10**8, help="learned: rays per error evaluation (16 replicas)")
     p.add_argument("--workload", choices=("projection", "batch", "learned", "train", "stepping", "crl", "scatter",
                                           "peaks", "basic", "beamline"),
@@ -355,6 +357,10 @@ def time_to_1pct(args):
         ins = workloads.edct_projection(vol, mu, angle=angle, strata=STRATA)
         return ins, mxr.Instrument(ins, dev, shared=shared)
 
+    def instrument_early_out(angle):
+        ins = workloads.edct_projection(vol, mu, angle=angle, strata=STRATA, early_out=True)
+        return ins, mxr.Instrument(ins, dev, shared=shared)
+
     def new_tally(sum_w=None):
         return {"count": torch.zeros(nb, dtype=torch.int64, device=dev),
                 "sum_w": torch.zeros(nb, dtype=torch.float64, device=dev) if sum_w is None else sum_w,
@@ -422,6 +428,19 @@ def time_to_1pct(args):
         f"trained {steps} steps in {t_train:.2f} s; loss {ll[:10].mean():.4f} -> {ll[-10:].mean():.4f}")
     del hits, images
 
+    def spread(rel, mask, n):
+        # relative variance per emitted ray of each signal bin, n rel_b^2
+        # (independent of n): the rays a bin needs for a 100 % error
+        v = n * rel[mask] ** 2
+        return {"median": float(np.median(v)), "q95": float(np.percentile(v, 95.0))}
+
+    def confirm(I, n_p, q, mask):
+        # one direct run at the extrapolated ray count, rounded up to whole
+        # replicas: its q95 should come out at 1 %
+        N = int(math.ceil(n_p * (q / 0.01) ** 2 / R)) * R
+        _, rc, tc, nc = replicas(I, N)
+        return {"rays": nc, "seconds": tc, "q95": metrics.q95(rc, mask)}
+
     results = {}
     for name, ang in (("angle_0", 0.0), ("angle_0.3_unseen", 0.3)):
         ins, I = instrument(ang)
@@ -436,6 +455,15 @@ def time_to_1pct(args):
         mp, rp, tp, n_p = replicas(I, args.eval_rays)
         q_p = metrics.q95(rp, mask)
         T_p = metrics.time_to_1pct(tp / n_p, n_p, q_p)
+        direct = name == "angle_0" and not args.no_confirm
+        conf_p = confirm(I, n_p, q_p, mask) if direct else None
+        # context: the plain source behind an aperture that ends the rays
+        # bound elsewhere before the phantom (the same image)
+        _, Ie = instrument_early_out(ang)
+        me, re_, te, n_e = replicas(Ie, args.eval_rays)
+        del Ie
+        q_e = metrics.q95(re_, mask)
+        T_e = metrics.time_to_1pct(te / n_e, n_e, q_e)
         torch.cuda.synchronize()
         ti = time.perf_counter()
         I.apply_proposal(net, workloads.projection_context(ang, 256), alpha=args.alpha, stream=stream)
@@ -444,18 +472,27 @@ def time_to_1pct(args):
         ml, rl, tl, n_l = replicas(I, args.eval_rays)
         q_l = metrics.q95(rl, mask)
         T_l = metrics.time_to_1pct(tl / n_l, n_l, q_l)
+        conf_l = confirm(I, n_l, q_l, mask) if direct else None
         z = (ml - I_ref)[mask] / np.sqrt((rl * ml)[mask] ** 2 + var_ref[mask])
-        log(f"{name}: plain q95 {q_p:.4f} T_1% {T_p:.2f} s; learned q95 {q_l:.4f} T_1% {T_l:.2f} s "
-            f"(+{t_learn + t_inf:.2f} s to learn); mean z^2 {np.mean(z * z):.3f}")
+        log(f"{name}: plain q95 {q_p:.4f} T_1% {T_p:.2f} s; early-out T_1% {T_e:.2f} s; learned q95 {q_l:.4f} "
+            f"T_1% {T_l:.2f} s (+{t_learn + t_inf:.2f} s to learn); mean z^2 {np.mean(z * z):.3f}"
+            + (f"; direct runs at 1 %: plain q95 {conf_p['q95']:.4f} in {conf_p['seconds']:.2f} s, "
+               f"learned q95 {conf_l['q95']:.4f} in {conf_l['seconds']:.2f} s" if direct else ""))
         results[name] = {
             "signal_bins": int(mask.sum()),
-            "plain": {"rays_per_s": n_p / tp, "q95": q_p, "time_to_1pct_s": T_p},
+            "plain": {"rays_per_s": n_p / tp, "q95": q_p, "time_to_1pct_s": T_p,
+                      "rel_var_per_ray": spread(rp, mask, n_p), "confirmed": conf_p},
+            "plain_early_out": {"rays_per_s": n_e / te, "q95": q_e, "time_to_1pct_s": T_e,
+                                "rel_var_per_ray": spread(re_, mask, n_e),
+                                "max_rel_diff_vs_plain_mean": float(np.max(np.abs(me - mp)[mask] / mp[mask]))},
             "learned": {"rays_per_s": n_l / tl, "q95": q_l, "time_to_1pct_s": T_l, "inference_s": t_inf,
+                        "rel_var_per_ray": spread(rl, mask, n_l), "confirmed": conf_l,
                         "time_to_1pct_with_learning_s": T_l + t_learn + t_inf,
                         "time_to_1pct_amortised_360_s": T_l + t_learn / 360 + t_inf,
                         "bias_mean_z2": float(np.mean(z * z)),
                         "bias_frac_abs_z_gt_4": float(np.mean(np.abs(z) > 4))},
             "gain_excl_learning": T_p / T_l,
+            "gain_excl_learning_vs_early_out": T_e / T_l,
             "gain_incl_learning": T_p / (T_l + t_learn + t_inf),
             "gain_amortised_360": T_p / (T_l + t_learn / 360 + t_inf),
         }
@@ -465,6 +502,9 @@ def time_to_1pct(args):
         "train_angles": len(train_angles), "epochs": args.epochs, "alpha": args.alpha,
         "learn_s": t_learn, "collect_s": t_collect, "train_s": t_train,
         "loss_first": float(ll[:10].mean()), "loss_last": float(ll[-10:].mean()),
+        "confirmed_q95": (None if results["angle_0"]["plain"]["confirmed"] is None else
+                          {"plain": results["angle_0"]["plain"]["confirmed"]["q95"],
+                           "learned": results["angle_0"]["learned"]["confirmed"]["q95"]}),
         **results,
     }
 

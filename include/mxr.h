@@ -216,7 +216,9 @@ uint32_t mxr_abi_version(void);
 const char *mxr_last_error(void);
 
 /* Validates desc, derives per-component constants and copies them to the
- * current device (one small allocation, owned by the handle): the
+ * current device (small allocations owned by the handle: the constants and,
+ * for a phantom, a copy of its attenuation table per mm and energy-major,
+ * the form the kernels stage in LDS): the
  * instrument as a sequence of components placed in the lab frame (paper,
  * section 2.1), its component data held in structs and made available on
  * the device once (section 2.2.2).  The data
@@ -240,8 +242,13 @@ void mxr_instrument_destroy(mxr_instrument *ins);
  *   compact    1: chains with a crop right after the source run the
  *              survivor-compacting kernel; 0: one ray per lane
  *   rounds     compacting kernel: 64-ray rounds per wave, 1..64 (0 = 64)
- *   xcd_order  0: the i-th of the eight XCDs traces the i-th eighth of the
- *              ray range; 1: work-groups take ray tiles in launch order */
+ *   xcd_order  which 256-ray tiles each of the eight XCDs traces: 0, the
+ *              i-th XCD the i-th eighth of the ray range; 1, launch order
+ *              (the default: the stratified source sends each block of ray
+ *              ids through one band of the cone, so order 0 leaves XCDs
+ *              idle where bands cost unequally); 2, runs of 64 consecutive
+ *              tiles dealt to the XCDs in turn.  Runs with a ledger, a
+ *              ray trace, a proposal or hit collection use order 1. */
 typedef struct {
     uint32_t occupancy;
     uint32_t compact;
@@ -280,7 +287,7 @@ mxr_status mxr_trace_rays(mxr_instrument *ins, const uint64_t *ray_ids, uint64_t
 mxr_status mxr_get_launch_shape(const mxr_instrument *ins, mxr_launch_shape *out);
 
 /* Sets the launch shape (validated: occupancy in {0, 4, 6, 8}, compact in
- * {0, 1}, rounds <= 64, xcd_order in {0, 1}).  Errors: MXR_E_INVALID. */
+ * {0, 1}, rounds <= 64, xcd_order in {0, 1, 2}).  Errors: MXR_E_INVALID. */
 mxr_status mxr_set_launch_shape(mxr_instrument *ins, const mxr_launch_shape *shape);
 
 /* Autotuner of an instrument's plain runs (paper, section 2.2: the

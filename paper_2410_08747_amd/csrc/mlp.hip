@@ -294,13 +294,13 @@ mxr_status gemm_splitk(const GemmArgs &g, int64_t splits, hipStream_t st) {
 // are copied.
 __global__ void k_gather(const float *ctx, const double *y, const double *omega, uint64_t n_data, uint64_t a,
                          uint64_t b, uint64_t first, uint64_t n, uint16_t *X, double *Yb, double *Wb) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t src = ((a * (first + i)) % n_data + b) % n_data;  // n_data < 2^32: no overflow
-    for (int j = 0; j < kIn; ++j) X[i * kIn + j] = f32_to_bf16(ctx[src * kIn + j]);
-    if (Yb) {
-        for (int j = 0; j < 3; ++j) Yb[i * 3 + j] = y[src * 3 + j];
-        Wb[i] = omega[src];
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t src = ((a * (first + i)) % n_data + b) % n_data;  // n_data < 2^32: no overflow
+        for (int j = 0; j < kIn; ++j) X[i * kIn + j] = f32_to_bf16(ctx[src * kIn + j]);
+        if (Yb) {
+            for (int j = 0; j < 3; ++j) Yb[i * 3 + j] = y[src * 3 + j];
+            Wb[i] = omega[src];
+        }
     }
 }
 
@@ -449,24 +449,24 @@ __global__ __launch_bounds__(kThreads) void k_head_loss_grad(HeadArgs h) {
 // like the training head and stored as float64.
 __global__ void k_head_params(const float *O, uint64_t n, float lo0, float lo1, float lo2, float hi0, float hi1,
                               float hi2, double *gmm) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float lo[3] = {lo0, lo1, lo2}, hi[3] = {hi0, hi1, hi2};
-    const float *o = O + i * kOut;
-    float mx = -INFINITY;
-    for (int k = 0; k < 8; ++k) mx = fmaxf(mx, o[7 * k]);
-    float se = 0.f;
-    for (int k = 0; k < 8; ++k) se += expf(o[7 * k] - mx);
-    const float lse = mx + logf(se);
-    for (int k = 0; k < 8; ++k) {
-        double *g = gmm + i * kOut + 7 * k;
-        g[0] = (double)expf(o[7 * k] - lse);
-        for (int d = 0; d < 3; ++d) {
-            const float cen = 0.5f * (lo[d] + hi[d]), half = 0.5f * (hi[d] - lo[d]);
-            const float raw = o[7 * k + 4 + d];
-            const float sp = raw > 20.f ? raw : log1pf(expf(raw));
-            g[1 + d] = (double)(cen + half * tanhf(o[7 * k + 1 + d]));
-            g[4 + d] = (double)(half * (1e-3f + sp));
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const float lo[3] = {lo0, lo1, lo2}, hi[3] = {hi0, hi1, hi2};
+        const float *o = O + i * kOut;
+        float mx = -INFINITY;
+        for (int k = 0; k < 8; ++k) mx = fmaxf(mx, o[7 * k]);
+        float se = 0.f;
+        for (int k = 0; k < 8; ++k) se += expf(o[7 * k] - mx);
+        const float lse = mx + logf(se);
+        for (int k = 0; k < 8; ++k) {
+            double *g = gmm + i * kOut + 7 * k;
+            g[0] = (double)expf(o[7 * k] - lse);
+            for (int d = 0; d < 3; ++d) {
+                const float cen = 0.5f * (lo[d] + hi[d]), half = 0.5f * (hi[d] - lo[d]);
+                const float raw = o[7 * k + 4 + d];
+                const float sp = raw > 20.f ? raw : log1pf(expf(raw));
+                g[1 + d] = (double)(cen + half * tanhf(o[7 * k + 1 + d]));
+                g[4 + d] = (double)(half * (1e-3f + sp));
+            }
         }
     }
 }
@@ -482,21 +482,21 @@ __global__ void k_reduce_partials(const float *partial, int64_t splits, float *g
 
 __global__ void k_adam(float *theta, uint16_t *wb, const float *g, float *m, float *v, uint64_t n, float lr, float b1,
                        float b2, float eps, float c1, float c2) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    const float t = theta[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
-    theta[i] = t;
-    wb[i] = f32_to_bf16(t);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float t = theta[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+        theta[i] = t;
+        wb[i] = f32_to_bf16(t);
+    }
 }
 
 __global__ void k_to_bf16(const float *x, uint64_t n, uint16_t *y) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = f32_to_bf16(x[i]);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        y[i] = f32_to_bf16(x[i]);
 }
 
 // ----------------------------------------------- fused training step --
@@ -873,15 +873,22 @@ __global__ void k_bin_stats_final(const double *partial, unsigned n_part, double
 
 __global__ void k_train_weights(const double *w, const int64_t *bin, uint64_t n, const double *sum_w, uint64_t n_bins,
                                 const double *mean_live, double floor_frac, double *omega) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t b = bin[i];
-    const double Ib = (b >= 0 && (uint64_t)b < n_bins) ? sum_w[b] : 0.0;
-    const double den = fmax(Ib, floor_frac * *mean_live);
-    omega[i] = den > 0.0 ? w[i] / den : 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const int64_t b = bin[i];
+        const double Ib = (b >= 0 && (uint64_t)b < n_bins) ? sum_w[b] : 0.0;
+        const double den = fmax(Ib, floor_frac * *mean_live);
+        omega[i] = den > 0.0 ? w[i] / den : 0.0;
+    }
 }
 
-unsigned blocks_for(uint64_t n) { return (unsigned)std::max<uint64_t>(1, (n + kThreads - 1) / kThreads); }
+// Work-groups for n items of a grid-stride kernel: at most 2^22 (the HSA
+// dispatch counts a grid's work-items with 32 bits), each item reached by the
+// kernel's stride loop.
+unsigned blocks_for(uint64_t n) {
+    return (unsigned)std::min<uint64_t>(1ull << 22, std::max<uint64_t>(1, (n + kThreads - 1) / kThreads));
+}
+// Work-groups for exactly n items, one per lane (n below 2^32 - kThreads).
+unsigned blocks_exact(uint64_t n) { return (unsigned)std::max<uint64_t>(1, (n + kThreads - 1) / kThreads); }
 
 // ------------------------------------------------------------ workspace --
 
@@ -1011,6 +1018,9 @@ mxr_status forward_ws(const uint16_t *w, uint64_t n, void *ws, const Layout &L, 
 // loss and gradient of the n rows gathered into the workspace
 mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const float hi[3], float *grad,
                         double *loss, void *ws, const Layout &L, hipStream_t st) {
+    // the head launches one lane per row and component
+    if (n > ((1ull << 32) - kThreads) / 8)
+        return fail(MXR_E_UNSUPPORTED, "%llu rows: at most 2^29 - 32 rows per gradient", (unsigned long long)n);
     mxr_status s = forward_ws(w, n, ws, L, st);
     if (s != MXR_OK) return s;
     double *red = at<double>(ws, L, MXR_MLP_WS_SCALARS);
@@ -1033,7 +1043,7 @@ mxr_status loss_grad_ws(const uint16_t *w, uint64_t n, const float lo[3], const 
     const int64_t tiles16 = ((int64_t)n + 15) / 16, groups8 = ((int64_t)n + 7) / 8;
     float *cp2 = at<float>(ws, L, MXR_MLP_WS_COLS), *cp1 = cp2 + tiles16 * kHid, *cp3 = cp1 + tiles16 * kHid;
     h.colpart = cp3;
-    hipLaunchKernelGGL(k_head_loss_grad, dim3(blocks_for(8 * n)), dim3(kThreads), 0, st, h);
+    hipLaunchKernelGGL(k_head_loss_grad, dim3(blocks_exact(8 * n)), dim3(kThreads), 0, st, h);
     if ((s = launch_check("head")) != MXR_OK) return s;
     if (loss) {
         s = sum_f64(h.row_loss, n, red, loss, st);

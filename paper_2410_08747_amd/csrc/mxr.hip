@@ -32,6 +32,10 @@ using namespace mxr;
 namespace {
 
 constexpr int kBlock = 256;
+// The HSA dispatch packet gives the grid size in work-items as a 32-bit count:
+// a launch of 256-item groups holds at most 2^24 - 1 of them.  2^24 - 8 keeps
+// the count a multiple of the 8 XCDs.
+constexpr uint64_t kMaxLaunchGroups = (1ull << 24) - 8;
 constexpr int kDynamic = -1;
 constexpr uint32_t kMaxBranches = 4;  // graph branches of a batch in the launches form
 // internal component kinds (not in the public enum): the cone-beam source
@@ -257,6 +261,10 @@ struct WavesHint<Chain<kSrcConeProposal, MXR_PHANTOM, MXR_DETECTOR>> {
     static constexpr int value = 8;
 };
 template <>
+struct WavesHint<Chain<MXR_SRC_CONE_BEAM, MXR_SLIT, MXR_PHANTOM, MXR_DETECTOR>> {
+    static constexpr int value = 8;
+};
+template <>
 struct WavesHint<Chain<MXR_SRC_CONE_BEAM, kPhantomStep, MXR_DETECTOR>> {
     static constexpr int value = 8;
 };
@@ -306,6 +314,27 @@ __device__ __forceinline__ bool run_chain(Chain<Ts...>, const DevInstr *ins, Ray
     }
 }
 
+// Ray tile of work-group b of a launch of 8 * per_xcd work-groups.  The
+// hardware deals work-groups to the eight XCDs round-robin (XCD b mod 8), so
+// the order decides which tiles an XCD traces: 0, the (b mod 8)-th eighth of
+// the range (each XCD a contiguous block of ray ids); 1, launch order (tile
+// b); 2, runs of kXcdRun consecutive tiles, the runs dealt to the XCDs in
+// turn.  The stratified source sends a block of ray ids through one band of
+// the cone, whose paths can be longer or shorter than the others', so order
+// 0 leaves XCDs idle at the end; orders 1 and 2 spread every band over all
+// eight.  Each order is a bijection of [0, 8 per_xcd).
+constexpr uint32_t kXcdRun = 64;
+__device__ __forceinline__ uint64_t tile_of(uint32_t b, uint32_t order, uint32_t per_xcd) {
+    const uint32_t x = b & 7u, slot = b >> 3;
+    if (order == 1) return b;
+    if (order == 2) {
+        const uint32_t full = per_xcd / kXcdRun * kXcdRun;
+        if (slot < full) return (uint64_t)(slot / kXcdRun) * (8 * kXcdRun) + x * kXcdRun + slot % kXcdRun;
+        return 8ull * full + (uint64_t)x * (per_xcd - full) + (slot - full);
+    }
+    return (uint64_t)x * per_xcd + slot;
+}
+
 // The instrument block is read-only for the whole launch; passing it as its
 // own restrict-qualified argument lets its wave-uniform fields be read with
 // scalar loads even though the kernel stores to the histograms.
@@ -313,10 +342,8 @@ __device__ __forceinline__ bool run_chain(Chain<Ts...>, const DevInstr *ins, Ray
 // One lane traces exactly one ray.  (A loop over several rays per lane lets
 // the compiler hoist every loop-invariant constant -- the polynomial
 // coefficients of exp, sin, cos -- into registers for the whole kernel, which
-// costs occupancy.)  Work-groups are dealt to the eight XCDs round-robin, so
-// work-group b is remapped to the b/8-th slot of the (b mod 8)-th eighth of
-// the ray range: each XCD traces a contiguous block of ray ids, which the
-// stratified source sends through neighbouring voxels and pixels.
+// costs occupancy.)  Which tiles of the ray range a work-group traces is
+// tile_of's choice (launch order unless the launch shape picks another).
 template <class C, bool LEDGER, bool TRACE, bool EXACT, int WAVES = WavesHint<C>::value>
 __global__ __launch_bounds__(kBlock, WAVES) void k_trace(const DevInstr *__restrict__ ins, RunArgs a) {
     extern __shared__ double smem[];
@@ -324,12 +351,9 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_trace(const DevInstr *__restr
     double *mu_lds = smem;
     const uint32_t n_mu = (ins->phantom >= 0) ? n_mat * n_ebin : 0u;
     if (n_mu) {
-        // stage mu / 10 (per mm), energy-major: row e holds every material
-        const double *T = (const double *)ins->c[ins->phantom].data1;
-        for (uint32_t i = threadIdx.x; i < n_mu; i += kBlock) {
-            uint32_t m = i / n_ebin, e = i - m * n_ebin;
-            mu_lds[e * n_mat + m] = T[i] * 0.1;
-        }
+        // stage the table as prepared at create (mu / 10, energy-major)
+        const double *T = ins->mu_em;
+        for (uint32_t i = threadIdx.x; i < n_mu; i += kBlock) mu_lds[i] = T[i];
     }
     LedgerLds L{nullptr};
     const uint32_t n_slots = 4 * ins->ncomp + 1;
@@ -339,8 +363,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void k_trace(const DevInstr *__restr
     }
     __syncthreads();
 
-    const uint64_t logical = a.xcd_order ? (uint64_t)blockIdx.x
-                                         : (uint64_t)(blockIdx.x & 7u) * a.blocks_per_xcd + (blockIdx.x >> 3);
+    const uint64_t logical = tile_of(blockIdx.x, a.xcd_order, a.blocks_per_xcd);
     const uint64_t i = logical * kBlock + threadIdx.x;
     if (i < a.n) {
         const uint64_t ray_id = TRACE ? a.ids[i] : a.first + i;
@@ -481,8 +504,7 @@ __global__ __launch_bounds__(kBlock, WavesHint<C>::value) void k_trace_compact(c
     L.tl_nb = tl_nb;
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     uint64_t *Q = queue[wave];
-    const uint64_t logical = a.xcd_order ? (uint64_t)blockIdx.x
-                                         : (uint64_t)(blockIdx.x & 7u) * a.blocks_per_xcd + (blockIdx.x >> 3);
+    const uint64_t logical = tile_of(blockIdx.x, a.xcd_order, a.blocks_per_xcd);
     const uint64_t per_wave = 64ull * a.compact_rounds;
     const uint64_t wbase = (logical * (kBlock / 64) + wave) * per_wave;
     const uint64_t wend = wbase + per_wave < a.n ? wbase + per_wave : a.n;
@@ -606,13 +628,10 @@ __global__ __launch_bounds__(kBlock, BatchWavesHint<C>::value) void k_batch(cons
         const DevInstr *ins = a.ins;
         const uint32_t n_mat = ins->n_mat, n_ebin = ins->n_ebin;
         if (ins->phantom >= 0) {
-            const double *T = (const double *)ins->c[ins->phantom].data1;
+            const double *T = ins->mu_em;
             if (T != staged) {
                 const uint32_t n_mu = n_mat * n_ebin;
-                for (uint32_t i = threadIdx.x; i < n_mu; i += kBlock) {
-                    uint32_t m = i / n_ebin, e = i - m * n_ebin;
-                    mu_lds[e * n_mat + m] = T[i] * 0.1;
-                }
+                for (uint32_t i = threadIdx.x; i < n_mu; i += kBlock) mu_lds[i] = T[i];
                 staged = T;
                 __syncthreads();
             }
@@ -664,12 +683,9 @@ __global__ __launch_bounds__(kBlock, BatchWavesHint<C>::value) void k_batch_grid
     const uint32_t n_mat = ins->n_mat, n_ebin = ins->n_ebin;
     double *mu_lds = smem;
     if (ins->phantom >= 0) {
-        const double *T = (const double *)ins->c[ins->phantom].data1;
+        const double *T = ins->mu_em;
         const uint32_t n_mu = n_mat * n_ebin;
-        for (uint32_t i = threadIdx.x; i < n_mu; i += kBlock) {
-            uint32_t m = i / n_ebin, e = i - m * n_ebin;
-            mu_lds[e * n_mat + m] = T[i] * 0.1;
-        }
+        for (uint32_t i = threadIdx.x; i < n_mu; i += kBlock) mu_lds[i] = T[i];
     }
     __syncthreads();
     const uint64_t ray_id = (tile - jobs[lo].tile0) * kBlock + threadIdx.x;
@@ -684,6 +700,16 @@ __global__ __launch_bounds__(kBlock, BatchWavesHint<C>::value) void k_batch_grid
     ray.w = 0.0;
     RayEnd end{kExited, -1, -1};
     run_chain<false, false, EXACT>(C{}, ins, ray, s, ray_id, a, mu_lds, n_mat, n_ebin, end, L);
+}
+
+// The phantom's attenuation table in the form the kernels stage (run once at
+// create): out[e n_mat + m] = T[m n_ebin + e] / 10, per mm and energy-major.
+__global__ __launch_bounds__(kBlock) void k_mu_energy_major(const double *T, uint32_t n_mat, uint32_t n_ebin,
+                                                            double *out) {
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n_mat * n_ebin) return;
+    const uint32_t m = i / n_ebin, e = i - m * n_ebin;
+    out[e * n_mat + m] = T[i] * 0.1;
 }
 
 // Largest material id in a volume (run once at create).
@@ -707,6 +733,9 @@ using ChainGeneric = Chain<kDynamic>;
 using ChainBasic = Chain<MXR_SRC_RECT_CONE, MXR_SLIT, MXR_BOX, MXR_DETECTOR>;
 using ChainEdct = Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR>;
 using ChainBeamline = Chain<MXR_SRC_GAUSSIAN, MXR_MIRROR_ELLIPTIC, MXR_DCM, MXR_POWDER, MXR_DETECTOR>;
+// the projection behind an aperture that passes exactly the rays bound for the
+// detector (a geometric early-out: the others end before the phantom)
+using ChainEdctAimed = Chain<MXR_SRC_CONE_BEAM, MXR_SLIT, MXR_PHANTOM, MXR_DETECTOR>;
 using ChainEdctProposal = Chain<kSrcConeProposal, MXR_PHANTOM, MXR_DETECTOR>;
 using ChainEdctCollect = Chain<MXR_SRC_CONE_BEAM, MXR_PHANTOM, kDetectorCollect>;
 using ChainEdctStep = Chain<MXR_SRC_CONE_BEAM, kPhantomStep, MXR_DETECTOR>;
@@ -734,6 +763,7 @@ enum Recipe {
     kRecipeEdctStep,
     kRecipeCrl,
     kRecipeEdctScatter,
+    kRecipeEdctAimed,
     kNumRecipes
 };
 
@@ -767,6 +797,7 @@ KernelFn pick_plain(int recipe, bool exact, uint32_t waves) {
         case kRecipeCrl: return KernelSet<ChainCrl, true>::plain(waves);
         case kRecipeEdctScatter:
             return exact ? KernelSet<ChainEdctScatter, true>::plain(waves) : KernelSet<ChainEdctScatter, false>::plain(waves);
+        case kRecipeEdctAimed: return exact ? KernelSet<ChainEdctAimed, true>::plain(waves) : nullptr;
         default: return nullptr;
     }
 }
@@ -797,6 +828,11 @@ KernelFn pick_kernel(int recipe, bool ledger, bool trace, bool exact, int mode) 
         case kRecipeEdctScatter:
             return exact ? KernelSet<ChainEdctScatter, true>::get(ledger, trace)
                          : KernelSet<ChainEdctScatter, false>::get(ledger, trace);
+        case kRecipeEdctAimed:
+            // plain runs only; ledgers and ray traces take the generic chain
+            if (exact && !ledger && !trace) return k_trace<ChainEdctAimed, false, false, true>;
+            return exact ? KernelSet<ChainGeneric, true>::get(ledger, trace)
+                         : KernelSet<ChainGeneric, false>::get(ledger, trace);
         default:
             return exact ? KernelSet<ChainGeneric, true>::get(ledger, trace)
                          : KernelSet<ChainGeneric, false>::get(ledger, trace);
@@ -845,6 +881,7 @@ int match_recipe(const DevInstr &d) {
     if (is({MXR_SRC_RECT_CONE, MXR_SLIT, MXR_BOX, MXR_DETECTOR})) return kRecipeBasic;
     if (is({MXR_SRC_CONE_BEAM, MXR_PHANTOM, MXR_DETECTOR}))
         return (d.c[1].flags & 2u) ? kRecipeEdctScatter : ((d.c[1].flags & 1u) ? kRecipeEdctStep : kRecipeEdct);
+    if (is({MXR_SRC_CONE_BEAM, MXR_SLIT, MXR_PHANTOM, MXR_DETECTOR}) && d.c[2].flags == 0) return kRecipeEdctAimed;
     if (is({MXR_SRC_GAUSSIAN, MXR_MIRROR_ELLIPTIC, MXR_DCM, MXR_POWDER, MXR_DETECTOR})) return kRecipeBeamline;
     if (is({MXR_SRC_GAUSSIAN, MXR_SLIT, MXR_LENS_CRL, MXR_SLIT, MXR_DETECTOR, MXR_DETECTOR})) return kRecipeCrl;
     return kRecipeGeneric;
@@ -898,7 +935,7 @@ mxr_status set_error(mxr_status st, const char *msg) {
 }  // namespace mxr_host
 
 struct mxr_instrument {
-    mxr_launch_shape shape{0, 1, 0, 0};  // plain runs' launch shape (see mxr_set_launch_shape)
+    mxr_launch_shape shape{0, 1, 0, 1};  // plain runs' launch shape (see mxr_set_launch_shape)
     int device;
     DevInstr host;
     DevInstr *dev;
@@ -908,6 +945,7 @@ struct mxr_instrument {
     uint64_t strata;      // G of the cone-beam source, 0 if none
     int n_cu;             // compute units of the device
     PropTable *prop_dev;  // proposal mixture (device), allocated on first use
+    double *mu_dev;       // the phantom's staged attenuation table (device), or null
     PropTable prop_host;  // its host copy (branch sizes are set per run)
     bool prop_on;
 };
@@ -1171,14 +1209,34 @@ mxr_status mxr_instrument_create(const mxr_instrument_desc *desc, mxr_instrument
     if (hipDeviceGetAttribute(&ins->n_cu, hipDeviceAttributeMultiprocessorCount, ins->device) != hipSuccess ||
         ins->n_cu < 1)
         ins->n_cu = 256;
+    ins->mu_dev = nullptr;
+    if (d.phantom >= 0) {
+        const uint32_t n_mu = d.n_mat * d.n_ebin;
+        e = hipMalloc((void **)&ins->mu_dev, (size_t)n_mu * sizeof(double));
+        if (e != hipSuccess) {
+            delete ins;
+            return fail(MXR_E_NOMEM, "hipMalloc of the attenuation table: %s", hipGetErrorString(e));
+        }
+        hipLaunchKernelGGL(k_mu_energy_major, dim3((n_mu + kBlock - 1) / kBlock), dim3(kBlock), 0, 0,
+                           (const double *)d.c[d.phantom].data1, d.n_mat, d.n_ebin, ins->mu_dev);
+        e = hipGetLastError();
+        if (e != hipSuccess) {
+            (void)hipFree(ins->mu_dev);
+            delete ins;
+            return hip_fail(e, "attenuation table launch");
+        }
+        d.mu_em = ins->mu_dev;
+    }
     e = hipMalloc((void **)&ins->dev, sizeof(DevInstr));
     if (e != hipSuccess) {
+        if (ins->mu_dev) (void)hipFree(ins->mu_dev);
         delete ins;
         return fail(MXR_E_NOMEM, "hipMalloc of the instrument block: %s", hipGetErrorString(e));
     }
     e = hipMemcpy(ins->dev, &d, sizeof(DevInstr), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(ins->dev);
+        if (ins->mu_dev) (void)hipFree(ins->mu_dev);
         delete ins;
         return hip_fail(e, "hipMemcpy of the instrument block");
     }
@@ -1197,11 +1255,13 @@ mxr_status mxr_instrument_create(const mxr_instrument_desc *desc, mxr_instrument
         if (dmax) (void)hipFree(dmax);
         if (e != hipSuccess) {
             (void)hipFree(ins->dev);
+            (void)hipFree(ins->mu_dev);
             delete ins;
             return hip_fail(e, "phantom id check");
         }
         if (hmax >= d.n_mat) {
             (void)hipFree(ins->dev);
+            (void)hipFree(ins->mu_dev);
             delete ins;
             return fail(MXR_E_INVALID, "phantom holds material id %u but the table has %u materials", hmax, d.n_mat);
         }
@@ -1217,6 +1277,7 @@ void mxr_instrument_destroy(mxr_instrument *ins) {
     (void)hipDeviceSynchronize();
     (void)hipFree(ins->dev);
     if (ins->prop_dev) (void)hipFree(ins->prop_dev);
+    if (ins->mu_dev) (void)hipFree(ins->mu_dev);
     if (cur >= 0 && cur != ins->device) (void)hipSetDevice(cur);
     delete ins;
 }
@@ -1240,9 +1301,10 @@ static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, b
         int32_t off[MXR_MAX_DETECTORS];
         shmem = lds_tally_layout(ins->host, off);
     }
-    // one lane per ray; launches of at most 2^30 work-groups (a multiple of
-    // the 8 XCDs), so ray ranges beyond that are split into several launches
-    const uint64_t max_rays = (1ull << 30) * kBlock;
+    // one lane per ray; a launch's grid is counted in work-items with 32 bits,
+    // so a launch takes at most kMaxLaunchGroups work-groups and longer ray
+    // ranges are split into several launches
+    const uint64_t max_rays = kMaxLaunchGroups * kBlock;
     for (uint64_t done = 0; done < n;) {
         const uint64_t m = std::min(n - done, max_rays);
         RunArgs a = base;
@@ -1268,7 +1330,7 @@ static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, b
         a.compact_rounds = (uint32_t)std::max<uint64_t>(
             1, std::min<uint64_t>(ins->shape.rounds ? ins->shape.rounds : kCompactRounds,
                                   m / ((uint64_t)kBlock * 4 * ins->n_cu)));
-        a.xcd_order = plain ? ins->shape.xcd_order : 0u;
+        a.xcd_order = plain ? ins->shape.xcd_order : 1u;
         const uint64_t rays_per_group = kc ? (uint64_t)kBlock * a.compact_rounds : (uint64_t)kBlock;
         const uint64_t groups = (m + rays_per_group - 1) / rays_per_group;
         a.blocks_per_xcd = (uint32_t)((groups + 7) / 8);
@@ -1517,7 +1579,7 @@ mxr_status mxr_set_launch_shape(mxr_instrument *ins, const mxr_launch_shape *sha
     if (!ins || !shape) return fail(MXR_E_INVALID, "null instrument or shape");
     const mxr_launch_shape &s = *shape;
     if (!(s.occupancy == 0 || s.occupancy == 4 || s.occupancy == 6 || s.occupancy == 8) || s.compact > 1 ||
-        s.rounds > kCompactRounds || s.xcd_order > 1)
+        s.rounds > kCompactRounds || s.xcd_order > 2)
         return fail(MXR_E_INVALID, "launch shape out of range (occupancy %u, compact %u, rounds %u, xcd order %u)",
                     s.occupancy, s.compact, s.rounds, s.xcd_order);
     ins->shape = s;
@@ -1574,7 +1636,7 @@ mxr_status mxr_autotune_instrument(mxr_instrument *ins, uint64_t n_total, double
     std::vector<mxr_launch_shape> cand;
     for (uint32_t occ : {0u, 4u, 6u, 8u}) {
         if (occ && !fixed) continue;
-        for (uint32_t xo : {0u, 1u}) {
+        for (uint32_t xo : {0u, 1u, 2u}) {
             if (compactable) {
                 cand.push_back({occ, 1, 0, xo});
                 cand.push_back({occ, 1, 16, xo});
@@ -1746,15 +1808,16 @@ static const char *kScheduleRule =
     "schedule: form 0 (grid), 1 (persistent: groups_per_cu 1..8, tile_rays a multiple of 256 in [256, 2^24]) "
     "or 2 (launches: branches 1..4)";
 
-// One job's rays as k_trace launches of at most 2^30 work-groups (the same
-// kernels and launch shape as mxr_run).
+// One job's rays as k_trace launches of at most kMaxLaunchGroups work-groups
+// (the same kernels and launch shape as mxr_run).
 static hipError_t launch_job(KernelFn k, const RunArgs &job, size_t shmem, hipStream_t st) {
-    const uint64_t max_rays = (1ull << 30) * kBlock;
+    const uint64_t max_rays = kMaxLaunchGroups * kBlock;
     for (uint64_t done = 0; done < job.n;) {
         const uint64_t m = std::min(job.n - done, max_rays);
         RunArgs a = job;
         a.first = done;
         a.n = m;
+        a.xcd_order = 1;
         const uint64_t groups = (m + kBlock - 1) / kBlock;
         a.blocks_per_xcd = (uint32_t)((groups + 7) / 8);
         hipLaunchKernelGGL(k, dim3((unsigned)((uint64_t)a.blocks_per_xcd * 8)), dim3(kBlock), shmem, st, job.ins, a);

@@ -47,6 +47,9 @@ struct DevInstr {
     uint32_t ncomp;
     int32_t phantom;  // index of the phantom component or -1
     uint32_t n_mat, n_ebin;
+    // the phantom's attenuation table as the kernels stage it in LDS: mu / 10
+    // (per mm), energy-major (row e holds every material), n_ebin x n_mat
+    const double *mu_em;
     DevComp c[MXR_MAX_COMPONENTS];
 };
 
@@ -106,7 +109,7 @@ struct RunArgs {
     uint32_t word3;  // purpose << 24 | job
     uint32_t blocks_per_xcd;
     uint32_t compact_rounds;  // compacting kernel: 64-ray rounds per wave
-    uint32_t xcd_order;       // 0: XCD x traces the x-th eighth of the range; 1: work-groups in launch order
+    uint32_t xcd_order;       // tiles per XCD: 0 the x-th eighth of the range, 1 launch order, 2 runs of 64 tiles
     TallyPtrs tally;
     double *ledger;
     const uint64_t *ids;  // trace mode: ray ids

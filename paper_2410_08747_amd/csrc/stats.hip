@@ -9,6 +9,7 @@
 // importance-weighted rays.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 
@@ -22,18 +23,19 @@ namespace {
 
 __global__ void k_batch_means(const double *sums, uint32_t R, uint64_t n_bins, double inv_n, double *mean,
                               double *rel) {
-    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n_bins) return;
-    double m = 0.0;
-    for (uint32_t r = 0; r < R; ++r) m += sums[(uint64_t)r * n_bins + b] * inv_n;
-    m /= (double)R;
-    double ss = 0.0;
-    for (uint32_t r = 0; r < R; ++r) {
-        const double d = sums[(uint64_t)r * n_bins + b] * inv_n - m;
-        ss += d * d;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_bins;
+         b += (uint64_t)gridDim.x * blockDim.x) {
+        double m = 0.0;
+        for (uint32_t r = 0; r < R; ++r) m += sums[(uint64_t)r * n_bins + b] * inv_n;
+        m /= (double)R;
+        double ss = 0.0;
+        for (uint32_t r = 0; r < R; ++r) {
+            const double d = sums[(uint64_t)r * n_bins + b] * inv_n - m;
+            ss += d * d;
+        }
+        mean[b] = m;
+        rel[b] = m > 0.0 ? sqrt(ss / (double)(R - 1)) / (sqrt((double)R) * m) : INFINITY;
     }
-    mean[b] = m;
-    rel[b] = m > 0.0 ? sqrt(ss / (double)(R - 1)) / (sqrt((double)R) * m) : INFINITY;
 }
 
 }  // namespace
@@ -44,7 +46,9 @@ extern "C" mxr_status mxr_batch_means(const double *sums, uint32_t R, uint64_t n
     if (R < 2) return mxr_host::set_error(MXR_E_INVALID, "batch means need at least 2 replicas");
     if (rays_per_replica == 0) return mxr_host::set_error(MXR_E_INVALID, "replicas must trace rays");
     if (n_bins == 0) return MXR_OK;
-    const unsigned blocks = (unsigned)((n_bins + 255) / 256);
+    // grid-stride: at most 2^22 work-groups (the dispatch counts work-items
+    // with 32 bits)
+    const unsigned blocks = (unsigned)std::min<uint64_t>((n_bins + 255) / 256, 1ull << 22);
     hipLaunchKernelGGL(k_batch_means, dim3(blocks), dim3(256), 0, (hipStream_t)hip_stream, sums, R, n_bins,
                        1.0 / (double)rays_per_replica, mean, rel);
     hipError_t e = hipGetLastError();

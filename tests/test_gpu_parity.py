@@ -217,17 +217,24 @@ def odd_edct(angle, voxel):
     return ins
 
 
+def early_out_edct(size=64, angle=0.4, strata=64):
+    return workloads.edct_projection(workloads.make_phantom(size, seed=1), workloads.make_mu_tables(1),
+                                     angle=angle, strata=strata, early_out=True)
+
+
 def instruments(small_edct):
     return {
         "basic_absorber": workloads.basic_absorber(),
         "edct_64": small_edct,
+        "edct_64_early_out": early_out_edct(),
         "beamline": workloads.beamline(),
         "edct_odd_45deg": odd_edct(math.pi / 4, 1.0),
         "edct_odd_voxel0.8": odd_edct(1.1, 0.8),
     }
 
 
-@pytest.mark.parametrize("name", ["basic_absorber", "edct_64", "beamline", "edct_odd_45deg", "edct_odd_voxel0.8"])
+@pytest.mark.parametrize("name", ["basic_absorber", "edct_64", "edct_64_early_out", "beamline", "edct_odd_45deg",
+                                  "edct_odd_voxel0.8"])
 def test_per_ray_parity(torch_cuda, small_edct, name):
     ins = instruments(small_edct)[name]
     n = 100003  # ragged: not a multiple of the work-group or XCD count
@@ -308,6 +315,30 @@ def test_largest_phantom_sampled(torch_cuda):
     t = I.run(n, seed=6, first_ray=first, n_total=n_total)
     torch_cuda.cuda.synchronize()
     compare_bins(t[0], oracle.run(ins, n, seed=6, first=first, n_total=n_total)[0], "512^3 ray range")
+
+
+@pytest.mark.parametrize("size,first,n,n_total", [(64, 0, 300001, 300001), (256, 499_999_937, 150001, 10**9)])
+def test_early_out_aperture(torch_cuda, size, first, n, n_total):
+    """The projection behind the early-out aperture, through its own plain
+    run kernel: per bin against the oracle, and the same image as the
+    projection without the aperture (the same rays reach the detector; their
+    positions differ only by rounding, the aperture moving each ray to its
+    plane first)."""
+    strata = 64 if size == 64 else 4096
+    aimed = early_out_edct(size, 0.4 if size == 64 else 0.0, strata)
+    plain = workloads.edct_projection(workloads.make_phantom(size, seed=1), workloads.make_mu_tables(1),
+                                      angle=0.4 if size == 64 else 0.0, strata=strata)
+    announce("early-out aperture", size, first, n, "n_total", n_total)
+    t = mxr().Instrument(aimed).run(n, seed=1, first_ray=first, n_total=n_total)
+    p = mxr().Instrument(plain).run(n, seed=1, first_ray=first, n_total=n_total)
+    torch_cuda.cuda.synchronize()
+    compare_bins(t[0], oracle.run(aimed, n, seed=1, first=first, n_total=n_total)[0], f"early-out {size}^3")
+    assert np.array_equal(cpu(t[0]["count"]), cpu(p[0]["count"]))
+    for key in ("sum_w", "sum_w2"):
+        g, o = cpu(t[0][key]), cpu(p[0][key])
+        nz = o != 0
+        assert np.array_equal(g == 0, o == 0)
+        assert np.max(np.abs(g[nz] - o[nz]) / o[nz]) <= REL_BIN
 
 
 def test_chunked_runs_equal_one_run(torch_cuda, small_edct):
@@ -451,3 +482,27 @@ def test_errors(torch_cuda, small_edct):
     with pytest.raises(m.MxrError):
         m.Instrument(b)
     assert "non-finite" in m.mxr_last_error()
+
+
+def test_run_beyond_2pow32_rays(torch_cuda):
+    """One call of more than 2^32 rays: the launch is split so that no grid
+    exceeds the dispatch's 32-bit work-item count.  Every ray is emitted
+    (the ledger's source weight, 1 per ray, sums to n exactly) and the image
+    equals the same run made in two calls."""
+    ins = workloads.basic_absorber()
+    n = (1 << 32) + 12345
+    announce("run beyond 2^32 rays", n)
+    I = mxr().Instrument(ins)
+    led = I.new_ledger()
+    I.run(n, seed=4, ledger=led)
+    one = I.run(n, seed=4)
+    parts = I.new_tallies()
+    I.run(1 << 32, seed=4, first_ray=0, n_total=n, tallies=parts)
+    I.run(12345, seed=4, first_ray=1 << 32, n_total=n, tallies=parts)
+    torch_cuda.cuda.synchronize()
+    assert cpu(led)[0] == float(n)
+    assert np.array_equal(cpu(one[0]["count"]), cpu(parts[0]["count"]))
+    g, o = cpu(parts[0]["sum_w"]), cpu(one[0]["sum_w"])
+    nz = o != 0
+    assert np.array_equal(g == 0, o == 0)
+    assert np.max(np.abs(g[nz] - o[nz]) / o[nz]) <= REL_BIN

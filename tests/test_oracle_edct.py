@@ -137,3 +137,27 @@ def test_metrics_flat_field_matches_closed_form():
     assert np.allclose(got, want, rtol=1e-12, atol=0)
     # a full detector sums to the fraction of the cone it covers times the band's mass
     assert abs(got.sum() - om.sum() / cone * spectrum_bin_integral(src, 20.0, 150.0)) < 1e-12
+
+
+def test_early_out_aperture_keeps_the_image():
+    """An aperture in front of the phantom that passes the detector
+    rectangle (scaled to its distance) removes only rays that miss the
+    detector, since the phantom only absorbs: the image keeps its counts,
+    and its sums change only by the rounding of the extra propagation."""
+    vol = workloads.make_phantom(64, seed=1)
+    mu = workloads.make_mu_tables(1)
+    n = 200000
+    plain = oracle.run(workloads.edct_projection(vol, mu, angle=0.4, strata=64), n, seed=3)[0]
+    aimed_ins = workloads.edct_projection(vol, mu, angle=0.4, strata=64, early_out=True)
+    assert [c["type"] for c in aimed_ins["components"]][1] == "slit"
+    aimed = oracle.run(aimed_ins, n, seed=3)[0]
+    assert plain["count"].sum() > 0.2 * n
+    assert np.array_equal(plain["count"], aimed["count"])
+    for key in ("sum_w", "sum_w2"):
+        nz = plain[key] != 0
+        assert np.array_equal(nz, aimed[key] != 0)
+        assert np.max(np.abs(aimed[key][nz] - plain[key][nz]) / plain[key][nz]) <= 1e-9
+    # a narrower aperture does cut detected rays
+    narrow = workloads.edct_projection(vol, mu, angle=0.4, strata=64, early_out=True)
+    narrow["components"][1]["w"] *= 0.5
+    assert oracle.run(narrow, n, seed=3)[0]["count"].sum() < 0.75 * plain["count"].sum()

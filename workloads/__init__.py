@@ -218,7 +218,8 @@ def edct_half_angle() -> float:
 
 def edct_projection(volume: np.ndarray, mu_table: np.ndarray, angle: float = 0.0,
                     strata: int = 1024, nx: int = EDCT_NX, ny: int = EDCT_NY, ne: int = EDCT_NE,
-                    step: float = None, scatter_order: int = None, aim: bool = True) -> Dict:
+                    step: float = None, scatter_order: int = None, aim: bool = True,
+                    early_out: bool = False) -> Dict:
     """Energy-dispersive CT projection: cone-beam point source (Kramers
     continuum (150 - E)/E on 20-150 keV plus lines at 59.3 and 67.2 keV,
     sigma 0.3 keV, 10 % of the photons each), voxel phantom of 1 mm voxels
@@ -230,16 +231,26 @@ def edct_projection(volume: np.ndarray, mu_table: np.ndarray, angle: float = 0.0
     ``scatter_order`` K >= 1: trace the photons scattered exactly K times in
     the phantom instead of the uncollided ones; ``mu_table`` must then be
     the three-channel table of ``make_scatter_tables``; with ``aim`` the last
-    scatter is aimed at the detector rectangle."""
+    scatter is aimed at the detector rectangle.  ``early_out``: an aperture
+    100 mm from the source, the detector rectangle scaled to that distance
+    (widened by a relative 1e-9), ends the rays bound elsewhere before the
+    phantom; the phantom only absorbs, so every ray that would reach the
+    detector passes it and the image is that of the plain instrument."""
     hx = 0.5 * nx * EDCT_PITCH
     hy = 0.5 * ny * EDCT_PITCH
     target = None
     if scatter_order is not None and aim:
         target = ((0.0, 0.0, EDCT_SDD), (hx, 0.0, 0.0), (0.0, hy, 0.0))
+    aperture = []
+    if early_out:
+        zs, grow = 100.0, 1.0 + 1e-9
+        aperture = [_c("slit", pos=(0, 0, zs), w=2.0 * hx * zs / EDCT_SDD * grow,
+                       h=2.0 * hy * zs / EDCT_SDD * grow)]
     return {"name": "edct_projection", "components": [
         _c("source_cone_beam", half_angle=math.atan(math.sqrt(hx * hx + hy * hy) / EDCT_SDD),
            emin=20.0, emax=150.0, e0=150.0, f_cont=0.8, e_line1=59.3, f_line1=0.1,
            e_line2=67.2, f_line2=0.1, line_sigma=0.3, strata=strata),
+        *aperture,
         _c("phantom", pos=(0, 0, EDCT_SOD), rot=rot_y(angle), voxel=1.0, volume=volume,
            mu_table=mu_table, table_emin=20.0, table_emax=150.0, step=step, scatter_order=scatter_order,
            scatter_target=target),
