@@ -148,13 +148,19 @@ __device__ __forceinline__ bool apply(const DevComp &c, int k, Ray &ray, Stream 
             g.corner[1] = c.aux[1];
             g.corner[2] = c.aux[2];
             g.nvox = (uint32_t)c.n0;
+            for (int i = 0; i < 3; ++i) {
+                g.blo[i] = c.aux[8 + i];
+                g.bhi[i] = c.aux[11 + i];
+            }
+            g.bg = (uint32_t)c.aux[14];
+            g.box = c.aux[15] != 0.0;
             double f = floor((ray.E - c.par[1]) * c.aux[3]);
             int e = (int)fmin(fmax(f, 0.0), (double)(n_ebin - 1));
             double tau;
             if constexpr (T == kPhantomStep)
                 tau = step_tau(g, q, dl, c.par[3], (int)c.aux[5], mu_lds + e * n_mat);
             else
-                tau = siddon_tau<EXACT>(g, q, dl, mu_lds + e * n_mat);
+                tau = siddon_tau<EXACT, false, true>(g, q, dl, mu_lds + e * n_mat);
             ray.w = ray.w * exp(-tau);
         }
         if constexpr (T == MXR_MIRROR_ELLIPTIC) ok = comp_mirror(c, ray);
@@ -712,19 +718,54 @@ __global__ __launch_bounds__(kBlock) void k_mu_energy_major(const double *T, uin
     out[e * n_mat + m] = T[i] * 0.1;
 }
 
-// Largest material id in a volume (run once at create).
-__global__ __launch_bounds__(kBlock) void k_max_id(const uint8_t *vol, uint64_t n, unsigned int *out) {
-    unsigned int m = 0;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kBlock)
-        m = m > vol[i] ? m : vol[i];
-    __shared__ unsigned int red[kBlock];
-    red[threadIdx.x] = m;
+// One pass over a phantom (run once at create), one row of x per lane: the
+// largest material id, and the box of the voxels whose material differs from
+// the corner voxel's.  out[0] = largest id, out[1..3] = least x, y, z of such
+// a voxel, out[4..6] = largest x, y, z + 1, out[7] = the corner's material
+// (out[1..3] start at ~0 and out[0], out[4..6] at 0).
+__global__ __launch_bounds__(kBlock) void k_phantom_scan(const uint8_t *vol, uint32_t nx, uint32_t ny, uint32_t nz,
+                                                        unsigned int *out) {
+    __shared__ unsigned int red[7];
+    if (threadIdx.x < 7) red[threadIdx.x] = (threadIdx.x >= 1 && threadIdx.x <= 3) ? ~0u : 0u;
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + w] ? red[threadIdx.x] : red[threadIdx.x + w];
-        __syncthreads();
+    const uint32_t bg = vol[0];
+    const uint32_t rows = ny * nz;
+    unsigned int mx = 0, lo[3] = {~0u, ~0u, ~0u}, hi[3] = {0u, 0u, 0u};
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < rows; r += gridDim.x * kBlock) {
+        const uint8_t *row = vol + (uint64_t)r * nx;
+        uint32_t first = nx, last = 0;
+        for (uint32_t x = 0; x < nx; ++x) {
+            const uint32_t m = row[x];
+            mx = m > mx ? m : mx;
+            if (m != bg) {
+                first = x < first ? x : first;
+                last = x + 1;
+            }
+        }
+        if (last > 0) {
+            const uint32_t z = r / ny, y = r - z * ny;
+            lo[0] = first < lo[0] ? first : lo[0];
+            hi[0] = last > hi[0] ? last : hi[0];
+            lo[1] = y < lo[1] ? y : lo[1];
+            hi[1] = y + 1 > hi[1] ? y + 1 : hi[1];
+            lo[2] = z < lo[2] ? z : lo[2];
+            hi[2] = z + 1 > hi[2] ? z + 1 : hi[2];
+        }
     }
-    if (threadIdx.x == 0) atomicMax(out, red[0]);
+    atomicMax(&red[0], mx);
+    for (int d = 0; d < 3; ++d) {
+        atomicMin(&red[1 + d], lo[d]);
+        atomicMax(&red[4 + d], hi[d]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicMax(out, red[0]);
+        for (int d = 0; d < 3; ++d) {
+            atomicMin(out + 1 + d, red[1 + d]);
+            atomicMax(out + 4 + d, red[4 + d]);
+        }
+        if (blockIdx.x == 0) out[7] = bg;
+    }
 }
 
 // ------------------------------------------------------------- recipes --
@@ -1227,6 +1268,41 @@ mxr_status mxr_instrument_create(const mxr_instrument_desc *desc, mxr_instrument
         }
         d.mu_em = ins->mu_dev;
     }
+    if (d.phantom >= 0) {
+        // one pass over the volume: every material id must index the mu
+        // table, and the box of voxels unlike the corner bounds the walk
+        DevComp &c = d.c[d.phantom];
+        unsigned int *dscan = nullptr, hs[8] = {0u, ~0u, ~0u, ~0u, 0u, 0u, 0u, 0u};
+        e = hipMalloc((void **)&dscan, sizeof hs);
+        if (e == hipSuccess) e = hipMemcpy(dscan, hs, sizeof hs, hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            const uint64_t rows = (uint64_t)c.dims[1] * c.dims[2];
+            const uint64_t nb = std::min<uint64_t>((rows + kBlock - 1) / kBlock, 4096);
+            hipLaunchKernelGGL(k_phantom_scan, dim3((unsigned)nb), dim3(kBlock), 0, 0, (const uint8_t *)c.data0,
+                               c.dims[0], c.dims[1], c.dims[2], dscan);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpy(hs, dscan, sizeof hs, hipMemcpyDeviceToHost);
+        if (dscan) (void)hipFree(dscan);
+        if (e != hipSuccess) {
+            (void)hipFree(ins->mu_dev);
+            delete ins;
+            return hip_fail(e, "phantom scan");
+        }
+        if (hs[0] >= d.n_mat) {
+            (void)hipFree(ins->mu_dev);
+            delete ins;
+            return fail(MXR_E_INVALID, "phantom holds material id %u but the table has %u materials", hs[0], d.n_mat);
+        }
+        // box planes as the walk places them: corner + k v
+        const bool any = hs[4] > 0;
+        for (int i = 0; i < 3; ++i) {
+            c.aux[8 + i] = c.aux[i] + (double)(any ? hs[1 + i] : 0u) * c.par[0];
+            c.aux[11 + i] = c.aux[i] + (double)(any ? hs[4 + i] : 0u) * c.par[0];
+        }
+        c.aux[14] = (double)hs[7];
+        c.aux[15] = any ? 1.0 : 0.0;
+    }
     e = hipMalloc((void **)&ins->dev, sizeof(DevInstr));
     if (e != hipSuccess) {
         if (ins->mu_dev) (void)hipFree(ins->mu_dev);
@@ -1239,32 +1315,6 @@ mxr_status mxr_instrument_create(const mxr_instrument_desc *desc, mxr_instrument
         if (ins->mu_dev) (void)hipFree(ins->mu_dev);
         delete ins;
         return hip_fail(e, "hipMemcpy of the instrument block");
-    }
-    if (d.phantom >= 0) {
-        // every material id must index the mu table
-        const DevComp &c = d.c[d.phantom];
-        unsigned int *dmax = nullptr, hmax = 0;
-        e = hipMalloc((void **)&dmax, sizeof(unsigned int));
-        if (e == hipSuccess) e = hipMemset(dmax, 0, sizeof(unsigned int));
-        if (e == hipSuccess) {
-            uint64_t nb = std::min<uint64_t>((c.n0 + kBlock - 1) / kBlock, 4096);
-            hipLaunchKernelGGL(k_max_id, dim3((unsigned)nb), dim3(kBlock), 0, 0, (const uint8_t *)c.data0, c.n0, dmax);
-            e = hipGetLastError();
-        }
-        if (e == hipSuccess) e = hipMemcpy(&hmax, dmax, sizeof(unsigned int), hipMemcpyDeviceToHost);
-        if (dmax) (void)hipFree(dmax);
-        if (e != hipSuccess) {
-            (void)hipFree(ins->dev);
-            (void)hipFree(ins->mu_dev);
-            delete ins;
-            return hip_fail(e, "phantom id check");
-        }
-        if (hmax >= d.n_mat) {
-            (void)hipFree(ins->dev);
-            (void)hipFree(ins->mu_dev);
-            delete ins;
-            return fail(MXR_E_INVALID, "phantom holds material id %u but the table has %u materials", hmax, d.n_mat);
-        }
     }
     *out = ins;
     return MXR_OK;

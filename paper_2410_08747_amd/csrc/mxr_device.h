@@ -625,6 +625,11 @@ struct PhantomGeo {
     int n[3];
     double v, rv;  // voxel edge and its reciprocal
     double corner[3];
+    // the occupied box: every voxel outside the planes blo[i] .. bhi[i] holds
+    // material bg; box = false when every voxel does
+    double blo[3], bhi[3];
+    uint32_t bg;
+    bool box;
 };
 
 // The loaded byte goes through an empty asm so that it stays a plain 32-bit
@@ -756,10 +761,14 @@ __device__ __forceinline__ void close_run(double tc, double mu, uint32_t m, doub
     tau = closed;
 }
 
+// a_vol <= a_in: the path enters the volume at a_vol and the walk at a_in,
+// the first voxel (off) lying just past a_in; before it the path runs in
+// material bg (bg < 0: a_vol = a_in).  The walk stops once every lane's events
+// reach a_stop <= a_out; runs still close at a_out.
 template <bool EXACT, int K, bool LOCATE = false>
 __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet &S, int D, int A, int B,
-                                              uint32_t off, double a_in, double a_out,
-                                              const double *__restrict__ mu_row, double tau_star = 0.0,
+                                              uint32_t off, double a_vol, double a_in, double a_stop, double a_out,
+                                              int bg, const double *__restrict__ mu_row, double tau_star = 0.0,
                                               WalkHit *hit = nullptr) {
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)g.vol, (short)0, (int)g.nvox, 0x00020000);
     const double v = g.v;
@@ -786,7 +795,12 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
     double mAB = min_f64(aA, aB);
 
     uint32_t run_m = load_voxel(rs, off);
-    double a_start = a_in, tau = 0.0;
+    double a_start = a_vol, tau = 0.0;
+    if (bg >= 0 && run_m != (uint32_t)bg) {
+        // the background run ends where the walk enters its first voxel
+        close_run<LOCATE>(a_in, mu_row[bg], (uint32_t)bg, tau, a_vol, tau_star, hit);
+        a_start = a_in;
+    }
     const int max_rounds = __builtin_amdgcn_readfirstlane((g.n[0] + g.n[1] + g.n[2] + 3) / K + 2);
     for (int round = 0; round < max_rounds; ++round) {
         uint32_t o[K];
@@ -871,7 +885,7 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
         if constexpr (LOCATE) {
             if (__builtin_amdgcn_ballot_w64(t[K - 1] < a_out && !hit->found) == 0) break;
         } else {
-            if (__builtin_amdgcn_ballot_w64(t[K - 1] < a_out) == 0) break;
+            if (__builtin_amdgcn_ballot_w64(t[K - 1] < a_stop) == 0) break;
         }
     }
     close_run<LOCATE>(a_out, mu_row[run_m], run_m, tau, a_start, tau_star, hit);
@@ -880,7 +894,14 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
 
 // EXACT: every plane coordinate corner + i v is reached exactly by adding v
 // (true for dyadic voxel sizes such as 1 mm); decided once per instrument.
-template <bool EXACT, bool LOCATE = false>
+// BOX (optical depths only): the walk covers the path's stretch inside the
+// occupied box.  Outside it every voxel holds the background material, so
+// the run that enters the volume there stays open up to the box, and the
+// box's faces are crossed at the alphas the full walk computes for those
+// planes (fma(plane, inv, -q inv)): the same runs and sums, except that a
+// path touching the box only along an edge or a face takes its background run
+// in one piece (a zero-length run less, a rounding of the sum).
+template <bool EXACT, bool LOCATE = false, bool BOX = false>
 __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q[3], const double dl[3],
                                              const double *__restrict__ mu_row, double tau_star = 0.0,
                                              WalkHit *hit = nullptr) {
@@ -902,8 +923,32 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
         }
     }
     if (!(a_out > a_in)) return 0.0;
+    const double a_vol = a_in;
+    double a_stop = a_out;
+    int bg = -1;
+    if constexpr (BOX && !LOCATE) {
+        bool miss = !g.box;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (dl[i] == 0.0) {
+                // the voxel slab the walk would keep (as in the set-up below)
+                const double f = floor((q[i] - g.corner[i]) / g.v);
+                const int idx = (int)fmin(fmax(f, 0.0), (double)(g.n[i] - 1));
+                const int lo = (int)rint((g.blo[i] - g.corner[i]) * g.rv);
+                const int hi = (int)rint((g.bhi[i] - g.corner[i]) * g.rv);
+                if (idx < lo || idx >= hi) miss = true;
+            } else {
+                const double nq = -(q[i] * inv[i]);
+                const double b0 = fma(g.blo[i], inv[i], nq), b1 = fma(g.bhi[i], inv[i], nq);
+                a_in = fmax(a_in, fmin(b0, b1));
+                a_stop = fmin(a_stop, fmax(b0, b1));
+            }
+        }
+        if (miss || !(a_stop > a_in)) return fma(mu_row[g.bg], a_out - a_vol, 0.0);
+        bg = (int)g.bg;
+    }
 
-    // Per axis: the voxel holding the start of the path and the first plane
+    // Per axis: the voxel holding the start of the walk and the first plane
     // crossed after a_in.  Planes are mirrored for negative directions
     // (coordinate -x, plane index counted downwards), so that the next plane
     // is always reached by adding v; alpha keeps its value (with -P, -q and
@@ -972,8 +1017,8 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
     else if (ay >= az) { D = 1; A = 0; B = 2; }
     else { D = 2; A = 0; B = 1; }
     const uint32_t off = (uint32_t)(idx[0] + nx * idx[1] + nxy * idx[2]);
-    return siddon_walk<EXACT, LOCATE ? kLocateRound : kWalkRound, LOCATE>(g, S, D, A, B, off, a_in, a_out, mu_row,
-                                                                         tau_star, hit);
+    return siddon_walk<EXACT, LOCATE ? kLocateRound : kWalkRound, LOCATE>(g, S, D, A, B, off, a_vol, a_in, a_stop,
+                                                                         a_out, bg, mu_row, tau_star, hit);
 }
 
 // ------------------------------------------------- scattering phantom ----
