@@ -243,12 +243,15 @@ void mxr_instrument_destroy(mxr_instrument *ins);
  *              survivor-compacting kernel; 0: one ray per lane
  *   rounds     compacting kernel: 64-ray rounds per wave, 1..64 (0 = 64)
  *   xcd_order  which 256-ray tiles each of the eight XCDs traces: 0, the
- *              i-th XCD the i-th eighth of the ray range; 1, launch order
- *              (the default: the stratified source sends each block of ray
- *              ids through one band of the cone, so order 0 leaves XCDs
- *              idle where bands cost unequally); 2, runs of 64 consecutive
- *              tiles dealt to the XCDs in turn.  Runs with a ledger, a
- *              ray trace, a proposal or hit collection use order 1. */
+ *              i-th XCD the i-th eighth of the ray range; 1, launch order;
+ *              2, runs of 64 consecutive tiles dealt to the XCDs in turn.
+ *              The default is 1 for instruments with a phantom (the
+ *              stratified source sends each block of ray ids through one
+ *              band of the cone, so order 0 leaves XCDs idle where the
+ *              bands' paths cost unequally) and 0 otherwise (neighbouring
+ *              rays keep their tally updates in one XCD's L2).  Runs with a
+ *              ledger, a ray trace, a proposal or hit collection use the
+ *              default. */
 typedef struct {
     uint32_t occupancy;
     uint32_t compact;

@@ -976,7 +976,8 @@ mxr_status set_error(mxr_status st, const char *msg) {
 }  // namespace mxr_host
 
 struct mxr_instrument {
-    mxr_launch_shape shape{0, 1, 0, 1};  // plain runs' launch shape (see mxr_set_launch_shape)
+    mxr_launch_shape shape{0, 1, 0, 0};  // plain runs' launch shape (see mxr_set_launch_shape)
+    uint32_t order = 0;                  // XCD order of the other runs (see tile_of)
     int device;
     DevInstr host;
     DevInstr *dev;
@@ -1242,6 +1243,11 @@ mxr_status mxr_instrument_create(const mxr_instrument_desc *desc, mxr_instrument
     }
     ins->n_det = n_det;
     ins->recipe = match_recipe(d);
+    // launch order spreads a phantom's bands of unequal path length over the
+    // XCDs; without a phantom the per-XCD blocks of neighbouring rays keep
+    // their tally updates in one L2 and measured faster
+    ins->order = d.phantom >= 0 ? 1u : 0u;
+    ins->shape.xcd_order = ins->order;
     hipError_t e = hipGetDevice(&ins->device);
     if (e != hipSuccess) {
         delete ins;
@@ -1380,7 +1386,7 @@ static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, b
         a.compact_rounds = (uint32_t)std::max<uint64_t>(
             1, std::min<uint64_t>(ins->shape.rounds ? ins->shape.rounds : kCompactRounds,
                                   m / ((uint64_t)kBlock * 4 * ins->n_cu)));
-        a.xcd_order = plain ? ins->shape.xcd_order : 1u;
+        a.xcd_order = plain ? ins->shape.xcd_order : ins->order;
         const uint64_t rays_per_group = kc ? (uint64_t)kBlock * a.compact_rounds : (uint64_t)kBlock;
         const uint64_t groups = (m + rays_per_group - 1) / rays_per_group;
         a.blocks_per_xcd = (uint32_t)((groups + 7) / 8);
@@ -1435,6 +1441,7 @@ static mxr_status common_args(mxr_instrument *ins, uint64_t n_total, uint64_t se
     a.n_total = n_total;
     a.seed = seed;
     a.word3 = (purpose << 24) | job;
+    a.xcd_order = ins->order;
     const uint64_t G = strata_side(ins->strata, n_total);
     a.G = G;
     a.G2 = G * G;
@@ -1867,7 +1874,6 @@ static hipError_t launch_job(KernelFn k, const RunArgs &job, size_t shmem, hipSt
         RunArgs a = job;
         a.first = done;
         a.n = m;
-        a.xcd_order = 1;
         const uint64_t groups = (m + kBlock - 1) / kBlock;
         a.blocks_per_xcd = (uint32_t)((groups + 7) / 8);
         hipLaunchKernelGGL(k, dim3((unsigned)((uint64_t)a.blocks_per_xcd * 8)), dim3(kBlock), shmem, st, job.ins, a);

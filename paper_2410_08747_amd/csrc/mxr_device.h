@@ -47,10 +47,11 @@ struct DevInstr {
     uint32_t ncomp;
     int32_t phantom;  // index of the phantom component or -1
     uint32_t n_mat, n_ebin;
-    // the phantom's attenuation table as the kernels stage it in LDS: mu / 10
-    // (per mm), energy-major (row e holds every material), n_ebin x n_mat
-    const double *mu_em;
     DevComp c[MXR_MAX_COMPONENTS];
+    // the phantom's attenuation table as the kernels stage it in LDS: mu / 10
+    // (per mm), energy-major (row e holds every material), n_ebin x n_mat.
+    // (After the components, which keep their 16-byte alignment.)
+    const double *mu_em;
 };
 
 struct TallyPtrs {
