@@ -80,6 +80,7 @@ def parse():
     p.add_argument("--step", type=float, default=1.0 / 3.0, help="stepping: step length (mm)")
     p.add_argument("--batch-rays", type=int, default=10**8, help="rays per job of the batch")
     p.add_argument("--batch-angles", type=int, default=360)
+    p.add_argument("--batch-forms", action="store_true", help="batch: also time every launch form once")
     p.add_argument("--batch-sizes", default="64,128,256,512", help="phantom edges (voxels) of the batch")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="copy 1 GiB device to device before the timed region: a kernel of known traffic "
@@ -325,6 +326,24 @@ def batch_bench(args):
         "separate_launches": {"value": n_rays / wall_s, "unit": "rays/s", "ms_per_step": wall_s * 1e3},
         "batch_over_separate": wall_s / wall_b,
     }
+    if args.batch_forms:
+        # every launch form once (after a capturing warm-up pass), beside
+        # the separate launches timed above
+        forms = {}
+        for sch in ((0, 0, 0, 0), (1, 4, 65536, 0), (1, 8, 16384, 0), (2, 0, 0, 4)):
+            B.schedule = sch
+            zero()
+            B.run(stream)
+            zero()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            B.run(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            name = ["grid", "persistent", "launches"][sch[0]] + str(list(sch[1:]))
+            forms[name] = {"s_per_pass": wall, "rays_per_s": n_rays / wall}
+            print(f"[bench] form {name}: {wall:.2f} s", file=sys.stderr, flush=True)
+        out["forms"] = forms
     print(json.dumps(out), flush=True)
 
 

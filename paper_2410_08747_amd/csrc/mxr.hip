@@ -31,6 +31,19 @@ using namespace mxr;
 
 namespace {
 
+// The device's constant address space, for tables that no kernel writes
+// while they are read (in the host pass, where kernel bodies are only
+// parsed, it is the ordinary one).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MXR_CONSTANT __attribute__((address_space(4)))
+#else
+#define MXR_CONSTANT
+#endif
+// The same space for a kernel's pointer parameter, in both passes: a
+// parameter's type is part of the kernel's mangled name, by which the host
+// stub finds the device code, so host and device must spell it alike.
+#define MXR_CONSTANT_PARAM __attribute__((address_space(4)))
+
 constexpr int kBlock = 256;
 // The HSA dispatch packet gives the grid size in work-items as a 32-bit count:
 // a launch of 256-item groups holds at most 2^24 - 1 of them.  2^24 - 8 keeps
@@ -351,7 +364,12 @@ __device__ __forceinline__ uint64_t tile_of(uint32_t b, uint32_t order, uint32_t
 // costs occupancy.)  Which tiles of the ray range a work-group traces is
 // tile_of's choice (launch order unless the launch shape picks another).
 template <class C, bool LEDGER, bool TRACE, bool EXACT, int WAVES = WavesHint<C>::value>
-__global__ __launch_bounds__(kBlock, WAVES) void k_trace(const DevInstr *__restrict__ ins, RunArgs a) {
+__global__ __launch_bounds__(kBlock, WAVES) void k_trace(const MXR_CONSTANT_PARAM DevInstr *__restrict__ insc,
+                                                         RunArgs a) {
+    // the instrument block through the constant address space: nothing writes
+    // it during a launch, so its wave-uniform fields may be loaded again near
+    // each use instead of being held in scalar registers across the walk
+    const DevInstr *ins = (const DevInstr *)insc;
     extern __shared__ double smem[];
     const uint32_t n_mat = ins->n_mat, n_ebin = ins->n_ebin;
     double *mu_lds = smem;
@@ -483,8 +501,9 @@ __device__ __forceinline__ void fresh_ray(Ray &ray) {
 // The chains compacted here hold no phantom, so no attenuation table is
 // staged; the dynamic LDS holds the private monitors.
 template <class C, bool EXACT>
-__global__ __launch_bounds__(kBlock, WavesHint<C>::value) void k_trace_compact(const DevInstr *__restrict__ ins,
+__global__ __launch_bounds__(kBlock, WavesHint<C>::value) void k_trace_compact(const MXR_CONSTANT_PARAM DevInstr *__restrict__ insc,
                                                                                RunArgs a) {
+    const DevInstr *ins = (const DevInstr *)insc;  // as in k_trace
     constexpr int CUT = CompactCut<C>::value;
     static_assert(CUT >= 0, "chain without a compaction prefix");
     extern __shared__ double smem[];
@@ -576,15 +595,6 @@ __global__ __launch_bounds__(kBlock, WavesHint<C>::value) void k_trace_compact(c
 }
 
 // ---------------------------------------------------------------- batch --
-
-// The device's constant address space, for tables that no kernel writes
-// while they are read (in the host pass, where kernel bodies are only
-// parsed, it is the ordinary one).
-#if defined(__HIP_DEVICE_COMPILE__)
-#define MXR_CONSTANT __attribute__((address_space(4)))
-#else
-#define MXR_CONSTANT
-#endif
 
 // One job of a batch: its instrument and the arguments of its run (read in
 // place from the job table, so their wave-uniform fields stay scalar loads).
@@ -808,7 +818,7 @@ enum Recipe {
     kNumRecipes
 };
 
-typedef void (*KernelFn)(const DevInstr *, RunArgs);
+typedef void (*KernelFn)(const MXR_CONSTANT_PARAM DevInstr *, RunArgs);
 
 template <class C, bool EXACT>
 struct KernelSet {
@@ -1392,7 +1402,7 @@ static mxr_status launch(mxr_instrument *ins, const RunArgs &base, uint64_t n, b
         a.blocks_per_xcd = (uint32_t)((groups + 7) / 8);
         const uint64_t blocks = (uint64_t)a.blocks_per_xcd * 8;
         hipLaunchKernelGGL(kc ? kc : k, dim3((unsigned)blocks), dim3(kBlock), shmem, stream,
-                           (const DevInstr *)ins->dev, a);
+                           (const MXR_CONSTANT_PARAM DevInstr *)ins->dev, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         done += m;
@@ -1876,7 +1886,8 @@ static hipError_t launch_job(KernelFn k, const RunArgs &job, size_t shmem, hipSt
         a.n = m;
         const uint64_t groups = (m + kBlock - 1) / kBlock;
         a.blocks_per_xcd = (uint32_t)((groups + 7) / 8);
-        hipLaunchKernelGGL(k, dim3((unsigned)((uint64_t)a.blocks_per_xcd * 8)), dim3(kBlock), shmem, st, job.ins, a);
+        hipLaunchKernelGGL(k, dim3((unsigned)((uint64_t)a.blocks_per_xcd * 8)), dim3(kBlock), shmem, st,
+                           (const MXR_CONSTANT_PARAM DevInstr *)job.ins, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         done += m;

@@ -93,3 +93,27 @@ int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mx
     assert sizes[8] == ctypes.sizeof(m.mxr_train_rows) == 80
     assert sizes[9] == m.mxr_train_rows.floor_frac.offset
     assert sizes[10] == ctypes.sizeof(m.mxr_launch_shape) == 16
+
+
+def test_every_kernel_stub_finds_its_device_code():
+    """The host side launches a kernel through a stub whose mangled name must
+    equal the device kernel's: a parameter type spelled differently in the
+    two compilation passes (an address space seen only by the device pass)
+    builds without error and aborts at the first launch.  Every stub's
+    kernel must have its descriptor (<name>.kd) in the library's gfx950
+    code objects."""
+    if not os.path.exists(LIB):
+        pytest.skip("libmxr.so not built")
+    out = subprocess.run(["nm", LIB], capture_output=True, text=True, check=True).stdout
+    data = open(LIB, "rb").read()
+    names = set()
+    for line in out.splitlines():
+        parts = line.split()
+        if len(parts) != 3 or "__device_stub__" not in parts[2]:
+            continue
+        m = re.match(r"(_ZN12_GLOBAL__N_1|_Z)(\d+)__device_stub__(.*)", parts[2])
+        assert m, f"unexpected stub name {parts[2]}"
+        names.add(m.group(1) + str(int(m.group(2)) - len("__device_stub__")) + m.group(3))
+    assert len(names) > 50
+    missing = sorted(n for n in names if (n + ".kd").encode() not in data)
+    assert not missing, f"{len(missing)} kernels without device code, e.g. {missing[0]}"
