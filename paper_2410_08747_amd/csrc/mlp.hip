@@ -513,6 +513,7 @@ __global__ void k_to_bf16(const float *x, uint64_t n, uint16_t *y) {
 // accumulation, f32 pre-activations, bf16 copies of activations and
 // gradients), only the order of the float32 sums differs.
 constexpr int kStripRows = 32;
+static_assert(kStripRows % 32 == 0, "weight-gradient products take K = 32 rows per instruction");
 constexpr int kFusedGroups = 256;
 
 struct FusedArgs {
@@ -537,6 +538,24 @@ __device__ __forceinline__ v4s frag_s(const uint16_t *p, int stride) {
 }
 __device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// gfx950's 16 x 16 x 32 bfloat16 product (twice the K of one instruction):
+// lane l holds row (A) or column (B) l % 16 and eight values of k, the same
+// eight for A and B (here k = 8 (l / 16) + j); the accumulator layout is the
+// 16 x 16 x 16 product's.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ v8bf frag8_c(const uint16_t *p) { return __builtin_bit_cast(v8bf, *(const uint4 *)p); }
+__device__ __forceinline__ v8bf frag8_s(const uint16_t *p, int stride) {
+    uint4 u;
+    u.x = (uint32_t)p[0] | ((uint32_t)p[stride] << 16);
+    u.y = (uint32_t)p[2 * stride] | ((uint32_t)p[3 * stride] << 16);
+    u.z = (uint32_t)p[4 * stride] | ((uint32_t)p[5 * stride] << 16);
+    u.w = (uint32_t)p[6 * stride] | ((uint32_t)p[7 * stride] << 16);
+    return __builtin_bit_cast(v8bf, u);
+}
+__device__ __forceinline__ v4f mfma32(v8bf a, v8bf b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 constexpr int kFusedThreads = 512;  // eight waves: two per SIMD
@@ -629,10 +648,10 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_train_fused(FusedArgs f) {
         {
             v4f c[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-            for (int k0 = 0; k0 < H; k0 += 16) {
-                const v4s b = frag_s(sW2 + (k0 + 4 * q) * H + nt * 16 + r, H);
-                c[0] = mfma16(frag_c(sH1 + r * H + k0 + 4 * q), b, c[0]);
-                c[1] = mfma16(frag_c(sH1 + (16 + r) * H + k0 + 4 * q), b, c[1]);
+            for (int k0 = 0; k0 < H; k0 += 32) {
+                const v8bf b = frag8_s(sW2 + (k0 + 8 * q) * H + nt * 16 + r, H);
+                c[0] = mfma32(frag8_c(sH1 + r * H + k0 + 8 * q), b, c[0]);
+                c[1] = mfma32(frag8_c(sH1 + (16 + r) * H + k0 + 8 * q), b, c[1]);
             }
             for (int mt = 0; mt < 2; ++mt)
                 for (int j = 0; j < 4; ++j) {
@@ -648,9 +667,9 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_train_fused(FusedArgs f) {
             const int mt = wave >> 2, ot = wave & 3;
             v4f c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int k0 = 0; k0 < H; k0 += 16)
-                c = mfma16(frag_c(sH2 + (mt * 16 + r) * H + k0 + 4 * q),
-                           frag_s(sW3 + (k0 + 4 * q) * O64 + ot * 16 + r, O64), c);
+            for (int k0 = 0; k0 < H; k0 += 32)
+                c = mfma32(frag8_c(sH2 + (mt * 16 + r) * H + k0 + 8 * q),
+                           frag8_s(sW3 + (k0 + 8 * q) * O64 + ot * 16 + r, O64), c);
             for (int j = 0; j < 4; ++j) {
                 const int m = mt * 16 + 4 * q + j, n = ot * 16 + r;
                 sO[m * O64 + n] = c[j] + sB3[n];
@@ -678,10 +697,10 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_train_fused(FusedArgs f) {
         {
             v4f c[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-            for (int k0 = 0; k0 < O64; k0 += 16) {
-                const v4s b = frag_c(sW3 + (nt * 16 + r) * O64 + k0 + 4 * q);
-                c[0] = mfma16(frag_c(sdO + r * O64 + k0 + 4 * q), b, c[0]);
-                c[1] = mfma16(frag_c(sdO + (16 + r) * O64 + k0 + 4 * q), b, c[1]);
+            for (int k0 = 0; k0 < O64; k0 += 32) {
+                const v8bf b = frag8_c(sW3 + (nt * 16 + r) * O64 + k0 + 8 * q);
+                c[0] = mfma32(frag8_c(sdO + r * O64 + k0 + 8 * q), b, c[0]);
+                c[1] = mfma32(frag8_c(sdO + (16 + r) * O64 + k0 + 8 * q), b, c[1]);
             }
             float cs = 0.f;
             for (int mt = 0; mt < 2; ++mt)
@@ -700,11 +719,11 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_train_fused(FusedArgs f) {
         {
             const int mt = wave;
 #pragma unroll
-            for (int k0 = 0; k0 < R; k0 += 16) {
-                const v4s a = frag_s(sH2 + (k0 + 4 * q) * H + mt * 16 + r, H);
+            for (int k0 = 0; k0 < R; k0 += 32) {
+                const v8bf a = frag8_s(sH2 + (k0 + 8 * q) * H + mt * 16 + r, H);
 #pragma unroll
                 for (int ot = 0; ot < 4; ++ot)
-                    acc3[ot] = mfma16(a, frag_s(sdO + (k0 + 4 * q) * O64 + ot * 16 + r, O64), acc3[ot]);
+                    acc3[ot] = mfma32(a, frag8_s(sdO + (k0 + 8 * q) * O64 + ot * 16 + r, O64), acc3[ot]);
             }
         }
         // dZ1 = (dZ2 W2^T) * silu'(Z1), its column sums (bias 1); Z2 is no
@@ -712,10 +731,10 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_train_fused(FusedArgs f) {
         {
             v4f c[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-            for (int k0 = 0; k0 < H; k0 += 16) {
-                const v4s b = frag_c(sW2 + (nt * 16 + r) * H + k0 + 4 * q);
-                c[0] = mfma16(frag_c(sdZ2 + r * H + k0 + 4 * q), b, c[0]);
-                c[1] = mfma16(frag_c(sdZ2 + (16 + r) * H + k0 + 4 * q), b, c[1]);
+            for (int k0 = 0; k0 < H; k0 += 32) {
+                const v8bf b = frag8_c(sW2 + (nt * 16 + r) * H + k0 + 8 * q);
+                c[0] = mfma32(frag8_c(sdZ2 + r * H + k0 + 8 * q), b, c[0]);
+                c[1] = mfma32(frag8_c(sdZ2 + (16 + r) * H + k0 + 8 * q), b, c[1]);
             }
             float cs = 0.f;
             for (int mt = 0; mt < 2; ++mt)
@@ -734,13 +753,13 @@ __global__ __launch_bounds__(kFusedThreads, 1) void k_train_fused(FusedArgs f) {
         {
             const int mt = wave;
 #pragma unroll
-            for (int k0 = 0; k0 < R; k0 += 16) {
-                const v4s a = frag_s(sH1 + (k0 + 4 * q) * H + mt * 16 + r, H);
+            for (int k0 = 0; k0 < R; k0 += 32) {
+                const v8bf a = frag8_s(sH1 + (k0 + 8 * q) * H + mt * 16 + r, H);
 #pragma unroll
                 for (int t = 0; t < 8; ++t)
-                    acc2[t] = mfma16(a, frag_s(sdZ2 + (k0 + 4 * q) * H + t * 16 + r, H), acc2[t]);
-                acc1 = mfma16(frag_s(sX + (k0 + 4 * q) * X16 + r, X16),
-                              frag_s(sdZ1 + (k0 + 4 * q) * H + nt * 16 + r, H), acc1);
+                    acc2[t] = mfma32(a, frag8_s(sdZ2 + (k0 + 8 * q) * H + t * 16 + r, H), acc2[t]);
+                acc1 = mfma32(frag8_s(sX + (k0 + 8 * q) * X16 + r, X16),
+                              frag8_s(sdZ1 + (k0 + 8 * q) * H + nt * 16 + r, H), acc1);
             }
         }
         __syncthreads();
