@@ -385,6 +385,8 @@ def time_to_1pct(args):
                 "sum_w": torch.zeros(nb, dtype=torch.float64, device=dev) if sum_w is None else sum_w,
                 "sum_w2": torch.zeros(nb, dtype=torch.float64, device=dev)}
 
+    last = {}
+
     def replicas(I, n_rays):
         per = n_rays // R
         sums = torch.zeros(R, nb, dtype=torch.float64, device=dev)
@@ -398,6 +400,8 @@ def time_to_1pct(args):
         torch.cuda.synchronize()
         secs = e0.elapsed_time(e1) * 1e-3
         mean, rel = mxr.batch_means(sums, per)
+        # share of the emitted rays that reached the detector
+        last["detected"] = float(sum(int(t[0]["count"].sum().item()) for t in tallies)) / (per * R)
         return mean.cpu().numpy(), rel.cpu().numpy(), secs, per * R
 
     # training rows (purpose 1) from 8 angles, each run covering its whole cone
@@ -472,6 +476,7 @@ def time_to_1pct(args):
         del ref
         mask = metrics.signal_bins(I_ref, metrics.flat_field(ins))
         mp, rp, tp, n_p = replicas(I, args.eval_rays)
+        det_p = last["detected"]
         q_p = metrics.q95(rp, mask)
         T_p = metrics.time_to_1pct(tp / n_p, n_p, q_p)
         direct = name == "angle_0" and not args.no_confirm
@@ -480,6 +485,7 @@ def time_to_1pct(args):
         # bound elsewhere before the phantom (the same image)
         _, Ie = instrument_early_out(ang)
         me, re_, te, n_e = replicas(Ie, args.eval_rays)
+        det_e = last["detected"]
         del Ie
         q_e = metrics.q95(re_, mask)
         T_e = metrics.time_to_1pct(te / n_e, n_e, q_e)
@@ -489,6 +495,7 @@ def time_to_1pct(args):
         torch.cuda.synchronize()
         t_inf = time.perf_counter() - ti
         ml, rl, tl, n_l = replicas(I, args.eval_rays)
+        det_l = last["detected"]
         q_l = metrics.q95(rl, mask)
         T_l = metrics.time_to_1pct(tl / n_l, n_l, q_l)
         conf_l = confirm(I, n_l, q_l, mask) if direct else None
@@ -499,12 +506,13 @@ def time_to_1pct(args):
                f"learned q95 {conf_l['q95']:.4f} in {conf_l['seconds']:.2f} s" if direct else ""))
         results[name] = {
             "signal_bins": int(mask.sum()),
-            "plain": {"rays_per_s": n_p / tp, "q95": q_p, "time_to_1pct_s": T_p,
+            "plain": {"rays_per_s": n_p / tp, "q95": q_p, "time_to_1pct_s": T_p, "detected_fraction": det_p,
                       "rel_var_per_ray": spread(rp, mask, n_p), "confirmed": conf_p},
-            "plain_early_out": {"rays_per_s": n_e / te, "q95": q_e, "time_to_1pct_s": T_e,
+            "plain_early_out": {"rays_per_s": n_e / te, "q95": q_e, "time_to_1pct_s": T_e, "detected_fraction": det_e,
                                 "rel_var_per_ray": spread(re_, mask, n_e),
                                 "max_rel_diff_vs_plain_mean": float(np.max(np.abs(me - mp)[mask] / mp[mask]))},
             "learned": {"rays_per_s": n_l / tl, "q95": q_l, "time_to_1pct_s": T_l, "inference_s": t_inf,
+                        "detected_fraction": det_l,
                         "rel_var_per_ray": spread(rl, mask, n_l), "confirmed": conf_l,
                         "time_to_1pct_with_learning_s": T_l + t_learn + t_inf,
                         "time_to_1pct_amortised_360_s": T_l + t_learn / 360 + t_inf,
