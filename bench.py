@@ -123,10 +123,9 @@ def measured_traffic(profile=PROFILE):
     return (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) + float(kv["write_kib"]) * float(kv["write_scale"])) * 1024.0
 
 
-def measured_valu(profile=PROFILE):
-    """VALU wave-instructions per launch of the projection kernel from the
-    committed SQ_INSTS_VALU count; None when the kernel sources changed since
-    it was taken."""
+def profile_line(prefix, profile=PROFILE):
+    """key=value fields of the committed profile's last line starting with
+    prefix; None when the kernel sources changed since it was taken."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -134,13 +133,32 @@ def measured_valu(profile=PROFILE):
             h.update(fh.read())
     try:
         with open(os.path.join(ROOT, profile)) as fh:
-            line = [l for l in fh if l.startswith("issue:")][-1]
+            line = [l for l in fh if l.startswith(prefix)][-1]
     except (OSError, IndexError):
         return None
     kv = dict(x.split("=") for x in line.split()[1:])
     if kv.get("source") != h.hexdigest()[:16]:
         return None
-    return float(kv["valu_insts"])
+    return kv
+
+
+def measured_valu(profile=PROFILE):
+    """VALU wave-instructions per launch of the projection kernel from the
+    committed SQ_INSTS_VALU count; None when the kernel sources changed since
+    it was taken."""
+    kv = profile_line("issue:", profile)
+    return None if kv is None else float(kv["valu_insts"])
+
+
+def measured_fp64_flop(profile=PROFILE):
+    """FP64 operations per launch of the projection kernel from the committed
+    SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counts: 64 lanes per wave
+    instruction, an FMA as two operations (every lane of an instruction is
+    counted, masked or not, so this bounds the executed work from above)."""
+    kv = profile_line("fp64:", profile)
+    if kv is None:
+        return None
+    return 64.0 * (float(kv["add"]) + float(kv["mul"]) + 2.0 * float(kv["fma"]) + float(kv["trans"]))
 
 
 def cpu_model() -> str:
@@ -1060,12 +1078,31 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    kern_ms_median = float(np.median([a.elapsed_time(b) for a, b in events]))
     wall = t1 - t0
     value = n * args.steps / wall
     achieved = BYTES_PER_RAY * n / (kern_ms * 1e-3) / 1e9
     detected = int(tallies[0]["count"].sum())
     traffic = measured_traffic()
     valu = measured_valu()
+    fp64 = measured_fp64_flop()
+
+    # end to end, outside the timed region: an instrument created from the
+    # host arrays (the volume's and tables' uploads, the phantom scan), the
+    # run, and the image copied back to the host; warm, median of 5
+    def end_to_end():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        J = mxr.Instrument(instr, dev)
+        tl = J.new_tallies()
+        J.run(n, seed=1, n_total=n, tallies=tl, stream=stream)
+        host = {k: v.cpu().numpy() for k, v in tl[0].items()}
+        torch.cuda.synchronize()
+        del J, tl, host
+        return time.perf_counter() - t
+
+    end_to_end()
+    e2e = float(np.median([end_to_end() for _ in range(5)]))
 
     out = {
         "metric": METRIC,
@@ -1085,6 +1122,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "kernel_ms": kern_ms,
+        "kernel_ms_median": kern_ms_median,
+        "end_to_end": {"median_ms": e2e * 1e3, "repeats": 5, "rays_per_s": n / e2e,
+                       "includes": "instrument create from host arrays (16 MiB volume and tables uploaded, "
+                                   "phantom scan) + the run + the 3 x 16 MiB image copied to the host"},
         "detected_fraction": detected / n,
         # the same time against the other limits: the HBM bytes the counters
         # measured (the volume stays in the caches) and the FP64 arithmetic
@@ -1097,7 +1138,10 @@ def main():
                              {"bytes_per_launch": traffic, "achieved_GBs": traffic / (kern_ms * 1e-3) / 1e9,
                               "frac": traffic / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}),
             "fp64": {"flop_per_ray": FP64_FLOP_PER_RAY, "achieved_TFLOPs": FP64_FLOP_PER_RAY * n / (kern_ms * 1e-3) / 1e12,
-                     "peak_TFLOPs": 78.6, "frac": FP64_FLOP_PER_RAY * n / (kern_ms * 1e-3) / 78.6e12},
+                     "peak_TFLOPs": 78.6, "frac": FP64_FLOP_PER_RAY * n / (kern_ms * 1e-3) / 78.6e12,
+                     # the same from the committed FP64 op-class counters
+                     "measured_flop_per_ray": (None if fp64 is None else fp64 / n),
+                     "measured_frac": (None if fp64 is None else fp64 / (kern_ms * 1e-3) / 78.6e12)},
             # the binding limit: VALU instruction issue (the launch's committed
             # SQ_INSTS_VALU count over this run's kernel time, against one
             # wave64 VALU instruction per SIMD per 4 cycles)
