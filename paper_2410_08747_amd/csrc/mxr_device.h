@@ -902,7 +902,7 @@ __device__ __forceinline__ double siddon_walk(const PhantomGeo &g, const AxisSet
 // planes (fma(plane, inv, -q inv)): the same runs and sums, except that a
 // path touching the box only along an edge or a face takes its background run
 // in one piece (a zero-length run less, a rounding of the sum).
-template <bool EXACT, bool LOCATE = false, bool BOX = false>
+template <bool EXACT, bool LOCATE = false, bool BOX = false, int KW = kWalkRound>
 __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q[3], const double dl[3],
                                              const double *__restrict__ mu_row, double tau_star = 0.0,
                                              WalkHit *hit = nullptr) {
@@ -1018,7 +1018,7 @@ __device__ __forceinline__ double siddon_tau(const PhantomGeo &g, const double q
     else if (ay >= az) { D = 1; A = 0; B = 2; }
     else { D = 2; A = 0; B = 1; }
     const uint32_t off = (uint32_t)(idx[0] + nx * idx[1] + nxy * idx[2]);
-    return siddon_walk<EXACT, LOCATE ? kLocateRound : kWalkRound, LOCATE>(g, S, D, A, B, off, a_vol, a_in, a_stop,
+    return siddon_walk<EXACT, LOCATE ? kLocateRound : KW, LOCATE>(g, S, D, A, B, off, a_vol, a_in, a_stop,
                                                                          a_out, bg, mu_row, tau_star, hit);
 }
 
