@@ -59,7 +59,7 @@ def parse():
     p.add_argument("--cpu-sample", type=int, default=None,
                    help="rays of the oracle's timed sample (default: 1.6e7 for the projection, 2e8 for the "
                         "basic, beamline and focusing instruments, whose rays cost the oracle ~30x less)")
-    p.add_argument("--train-hits", type=int, default=10**8, help="learned: detector hits collected for training")
+    p.add_argument("--train-hits", type=int, default=25 * 10**6, help="learned: detector hits collected for training")
     p.add_argument("--epochs", type=int, default=5, help="learned: training epochs")
     p.add_argument("--alpha", type=float, default=0.1, help="learned: share of the plain source in the proposal")
     p.add_argument("--no-confirm", action="store_true",
