@@ -1130,7 +1130,7 @@ def main():
         # the same time against the other limits: the HBM bytes the counters
         # measured (the volume stays in the caches) and the FP64 arithmetic
         # of the walk (about 6 operations per voxel visit + 400 per ray of
-        # source, clip and tally, SURVEY-style count: 2.0 kflop per ray)
+        # source, clip and tally: a model count of 2.0 kflop per ray)
         "roofline_detail": {
             "gather_model": "1 B per voxel visit (270 per ray) + 24 B per detected ray; L2/MALL-resident, "
                             "the HBM proxy this workload is quoted on",
