@@ -38,3 +38,16 @@ def test_measured_traffic_lookup(tmp_path):
     fake = tmp_path / "p.md"
     fake.write_text("counters: source=0000000000000000 fetch_kib=1 write_kib=1 fetch_scale=2.00 write_scale=1.00\n")
     assert bench.measured_traffic(str(fake)) is None  # an absolute path is used as is
+
+
+def test_committed_profiles_match_the_kernel_sources():
+    """The headline line's measured figures (HBM traffic, VALU issue, FP64
+    op classes) come from the committed counters only while their source
+    hash is the current kernel sources'; a kernel change without new
+    counters would silently turn them into nulls."""
+    sys.path.insert(0, ROOT)
+    import bench
+    for prof in (bench.PROFILE, bench.PROFILE_STEP, bench.PROFILE_CRL, bench.PROFILE_SCATTER):
+        assert bench.measured_traffic(prof) is not None, f"{prof}: counters taken on other kernel sources"
+    assert bench.measured_valu() is not None
+    assert bench.measured_fp64_flop() is not None
